@@ -1,0 +1,208 @@
+/*
+ * sfq.h -- C ABI of the MI355X strong-field QED Monte Carlo step.
+ *
+ * Method: Montefiori & Tamburini, "SFQEDtoolkit: a high-performance library for the accurate
+ * modeling of strong-field QED processes in PIC and Monte Carlo codes", arXiv:2301.07684.
+ * The calls follow the paper's App. A (user guide) in batched, device-pointer form.
+ *
+ * Conventions for every call below
+ *   - Units are the paper's normalised units (Sec. 4.1 and App. A): energies gamma = eps/(m c^2),
+ *     momenta in m c, fields E and B in m c omega_r/|e|, rates in omega_r, times in 1/omega_r.
+ *   - Every array argument is a DEVICE pointer (hipMalloc'd or from a framework allocator) of
+ *     the documented length; arrays are structure-of-arrays (one pointer per component).  The
+ *     library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Calls are asynchronous:
+ *     they validate their arguments, enqueue kernels on `stream` and return.  Results are valid
+ *     after the stream has been synchronised.
+ *   - n == 0 is a no-op returning SFQ_OK.
+ *   - Errors: argument errors are reported synchronously as a non-zero sfq_status with a message
+ *     available from sfq_last_error(); nothing is enqueued in that case.  Conditions found on
+ *     the device (product-buffer overflow, chi beyond the tables) are reported in the
+ *     sfq_counters structure of sfq_step.  No C++ exception crosses this interface.
+ *   - A handle may be used from several host threads and streams at once for sfq_rates,
+ *     sfq_chi, sfq_sample_* and sfq_philox; sfq_step calls that share a handle must be
+ *     serialised by the caller (they share the handle's emitter queue).
+ */
+#ifndef SFQ_H
+#define SFQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sfq_ctx* sfq_handle;
+
+typedef enum {
+    SFQ_OK = 0,
+    SFQ_E_ARG = 1,      /* invalid argument (NULL pointer, bad enum, inconsistent config)      */
+    SFQ_E_STATE = 2,    /* invalid handle                                                        */
+    SFQ_E_NOMEM = 3,    /* device allocation failed                                              */
+    SFQ_E_CAPACITY = 4, /* request exceeds a fixed limit of the library                          */
+    SFQ_E_DEVICE = 5,   /* HIP runtime error                                                     */
+    SFQ_E_TABLES = 6    /* approximation table file missing, corrupt or of another geometry      */
+} sfq_status;
+
+typedef enum { SFQ_ELECTRON = 0, SFQ_POSITRON = 1, SFQ_PHOTON = 2 } sfq_species;
+
+/* FP64: everything in double precision.  MIXED: chi, optical depths and the inverse-CDF tails
+ * with energy fraction above 0.999 in FP64; approximation evaluation and sampling in FP32. */
+typedef enum { SFQ_FP64 = 0, SFQ_MIXED = 1 } sfq_precision;
+
+/* Paper Sec. 2: optical-depth method (Eq. (any_event)) or local method (R dt > r). */
+typedef enum { SFQ_OPTICAL_DEPTH = 0, SFQ_LOCAL = 1 } sfq_decision;
+
+/* Philox draw purposes (counter word 3).  See sfq_philox. */
+enum { SFQ_P_INIT = 0, SFQ_P_EMIT = 1, SFQ_P_CHILD = 2, SFQ_P_CHILD2 = 3, SFQ_P_LOCAL = 4 };
+
+typedef struct {
+    double ref_omega;        /* reference angular frequency omega_r in rad/s (App. A function 2) */
+    double ref_length;       /* reference length lambda_r = c/omega_r in m (App. A function 1);
+                                exactly one of ref_omega and ref_length must be > 0             */
+    double dt;               /* time step in units of 1/omega_r (App. A functions 1-2, "ts")    */
+    int32_t precision;       /* sfq_precision                                                     */
+    int32_t decision;        /* sfq_decision used by sfq_step                                     */
+    int32_t blcfa;           /* 1: leptons use the beyond-LCFA emission of Sec. 5 in sfq_step;
+                                requires decision == SFQ_LOCAL (Sec. 2, App. A)                   */
+    int32_t bw_fast;         /* 1: pair rate is zero for chi < 0.3 (App. A function 7)           */
+    int32_t device;          /* HIP device ordinal the handle's tables live on                   */
+    int32_t reserved;        /* must be 0                                                          */
+    const char* tables_path; /* approximation table file; NULL = data/sfq_tables.bin next to
+                                the shared library                                                */
+} sfq_config;
+
+/* Initialisation (paper App. A functions 1 and 2, SFQED_INIT_ALL_ref_len / _ref_freq): loads
+ * the approximation tables into device memory of cfg->device.  On success *out receives a new
+ * handle and SFQ_OK is returned (the paper's `true`). */
+sfq_status sfq_create(const sfq_config* cfg, sfq_handle* out);
+
+/* Teardown (paper App. A function 14, SFQED_FINALIZE_ALL): frees the handle's device memory.
+ * The caller must have synchronised every stream that used the handle.  NULL is ignored. */
+void sfq_destroy(sfq_handle h);
+
+/* Message of the last error on this host thread (h may be NULL); never NULL. */
+const char* sfq_last_error(sfq_handle h);
+
+/* Derived constants of a handle: lambda_C/lambda_r and lambda_r/lambda_C (dimensionless). */
+sfq_status sfq_units(sfq_handle h, double* lc_over_lr, double* lr_over_lc);
+
+/* Quantum parameter chi (paper Eq. (chi_exact); App. A functions 15-16) and energy gamma
+ * (sqrt(1+p^2) for leptons, |p| for photons) of n particles of one species.  Inputs: momentum
+ * and local fields (n doubles each).  Outputs: gamma_out (nullable), chi_out (n doubles). */
+sfq_status sfq_chi(sfq_handle h, int species, size_t n, const double* px, const double* py,
+                   const double* pz, const double* ex, const double* ey, const double* ez,
+                   const double* bx, const double* by, const double* bz, double* gamma_out,
+                   double* chi_out, void* stream);
+
+/* LCFA rates W = R/omega_r (paper Eqs. (pe_rate_3) and (pp_tot_real); App. A functions 5-7):
+ * species SFQ_ELECTRON or SFQ_POSITRON -> nonlinear Compton rate; SFQ_PHOTON -> nonlinear
+ * Breit-Wheeler rate, zero for chi < 0.01 (Sec. 4.2) or chi < 0.3 with bw_fast.  Inputs gamma,
+ * chi (n doubles each, gamma > 0, chi >= 0); output rate_out (n doubles). */
+sfq_status sfq_rates(sfq_handle h, int species, size_t n, const double* gamma, const double* chi,
+                     double* rate_out, void* stream);
+
+/* LCFA photon energy (paper Sec. 4.3, Eq. (again); App. A function 9): for emitter energy gamma,
+ * quantum parameter chi and uniform r in (0,1), gamma_photon_out receives the emitted photon
+ * energy.  gamma_emitter_out (nullable) receives the emitter's energy after collinear recoil,
+ * gamma - gamma_photon, computed without cancellation.  n doubles each. */
+sfq_status sfq_sample_photon(sfq_handle h, size_t n, const double* gamma, const double* chi,
+                             const double* r, double* gamma_photon_out, double* gamma_emitter_out,
+                             void* stream);
+
+/* Pair energies (paper Sec. 4.4, Eqs. (again_pp), (return_to_nrg); App. A function 11): for a
+ * photon of energy gamma and quantum parameter chi (tabulated for chi >= 2^-7) and uniform r in
+ * (0,1), gamma_electron_out receives the electron energy; gamma_positron_out (nullable) the
+ * positron energy gamma - gamma_electron, computed without cancellation.  n doubles each. */
+sfq_status sfq_sample_pair(sfq_handle h, size_t n, const double* gamma, const double* chi,
+                           const double* r, double* gamma_electron_out,
+                           double* gamma_positron_out, void* stream);
+
+/* Philox4x32-10 draws (Salmon et al., SC'11) with key (seed mod 2^32, seed >> 32) and counter
+ * (uid mod 2^32, uid >> 32, step mod 2^32, purpose).  a_out and b_out (n uint64 each) receive
+ * the words x0:x1 and x2:x3.  The uniform used by the step is ((a >> 12) + 1/2) 2^-52. */
+sfq_status sfq_philox(sfq_handle h, size_t n, const uint64_t* uid, uint64_t seed, uint64_t step,
+                      uint32_t purpose, uint64_t* a_out, uint64_t* b_out, void* stream);
+
+/* Initial optical depths tau_0 = -ln(1 - r) (paper Sec. 2, text after Eq. (any_event)) with r
+ * from purpose SFQ_P_INIT at step 0.  tau_out: n doubles. */
+sfq_status sfq_init_optical_depth(sfq_handle h, size_t n, const uint64_t* uid, uint64_t seed,
+                                  double* tau_out, void* stream);
+
+/* One tile of particles of one species for sfq_step.  All pointers are device pointers of n
+ * elements unless stated. */
+typedef struct {
+    int32_t species;           /* sfq_species                                                     */
+    int32_t reserved;          /* must be 0                                                       */
+    uint64_t n;                /* number of particles                                             */
+    double *px, *py, *pz;      /* momentum, updated in place by recoil.  With blcfa leptons this
+                                  is the pushed momentum p_L^{(n+1/2)} of Sec. 5                  */
+    const double *ex, *ey, *ez;/* electric field at the particle (unused by blcfa leptons)        */
+    const double *bx, *by, *bz;/* magnetic field at the particle (unused by blcfa leptons)        */
+    double* tau;               /* remaining optical depth tau_d (OPTICAL_DEPTH; else nullable)    */
+    const uint64_t* uid;       /* particle identifiers: the Philox counter of every draw          */
+    uint8_t* alive;            /* nullable (all alive).  Converted photons are set to 0           */
+    /* beyond-LCFA state (blcfa handles, lepton tiles; else NULL): the momentum before the push
+     * p^{(n-1/2)}, the stored transverse Lorentz force F_perp^{(n-1)} and its last difference
+     * (3n doubles each, component-major: x[0..n), y[0..n), z[0..n)), and the just-created flag */
+    const double *px_prev, *py_prev, *pz_prev;
+    double* fperp;
+    double* dfperp;
+    uint8_t* just_created;
+    double* chi_out;           /* nullable: chi of every alive particle                          */
+    double* rate_out;          /* nullable: rate W of every alive particle                       */
+} sfq_tile;
+
+/* Product buffers of one species (device SoA arrays of `capacity` elements). */
+typedef struct {
+    double *px, *py, *pz, *tau;
+    uint64_t *uid, *parent;
+    uint64_t capacity;
+} sfq_products;
+
+/* Device counters, accumulated by sfq_step (the caller zeroes them when it wants). */
+typedef struct {
+    unsigned long long processed;       /* alive particles taken through the step                */
+    unsigned long long emitted;         /* Compton emissions kept                                */
+    unsigned long long converted;       /* photons converted to pairs                            */
+    unsigned long long blcfa_rejected;  /* beyond-LCFA candidates rejected by Eq. (rej_cond)     */
+    unsigned long long out_of_domain;   /* chi above the tables (2^16): asymptotic forms used    */
+    unsigned long long clamped;         /* leptons left with gamma <= 1 and put at rest          */
+    unsigned long long overflow;        /* products that did not fit their buffer                */
+    unsigned long long reserved;
+} sfq_counters;
+
+typedef struct {
+    uint64_t seed;             /* Philox key                                                      */
+    uint64_t step;             /* step index: Philox counter word 2 (mod 2^32)                    */
+    int32_t ntiles;            /* 1 .. SFQ_MAX_TILES                                              */
+    int32_t reserved;
+    const sfq_tile* tiles;     /* HOST array of ntiles tile descriptors                           */
+    sfq_products photons;      /* Compton photons                                                 */
+    sfq_products electrons;    /* Breit-Wheeler electrons                                         */
+    sfq_products positrons;    /* Breit-Wheeler positrons                                         */
+    unsigned long long* product_counts; /* device [3]: photons, electrons, positrons already in
+                                  the buffers; products are appended there and the counts grow
+                                  (beyond capacity too: the final count is the size needed)      */
+    sfq_counters* counters;    /* device, accumulated                                             */
+} sfq_step_desc;
+
+#define SFQ_MAX_TILES 4096
+
+/* The Monte Carlo step (paper Fig. 7 workflow; App. A functions 4-6, 8-11, 15-17): for every
+ * alive particle of every tile, gamma and chi (or, for blcfa leptons, the Sec. 5 force update),
+ * the LCFA rate, the decision of cfg.decision, and for the particles that emit: Philox draws,
+ * the energy sample, collinear recoil and the products.  All tiles run in one launch sequence
+ * on `stream`.  Draws depend only on (seed, uid, step, purpose), so results do not depend on how
+ * particles are split into tiles or batched with other work; only the order of products in
+ * their buffers does (identify them by parent uid and species).  On product overflow the
+ * particle state has still been advanced: restore it and re-run with larger buffers to get the
+ * same result. */
+sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFQ_H */

@@ -1,0 +1,55 @@
+"""Build step of the package: the approximation tables and the HIP library for gfx950.
+
+    python -m paper_2301_07684_amd.build
+
+compiles csrc/sfq.hip into libsfq.so next to this file (hipcc, --offload-arch=gfx950) and
+(re)generates data/sfq_tables.bin when the table generator's source changed.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libsfq.so")
+SOURCES = [os.path.join(HERE, "csrc", "sfq.hip")]
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def hipcc() -> str:
+    for c in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found: the HIP library cannot be built")
+
+
+def build_library(verbose: bool = True) -> str:
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), *HIP_FLAGS, "-o", tmp, *SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed")
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def build_tables(verbose: bool = True) -> str:
+    from . import tablegen
+
+    tablegen.main([tablegen.default_path()])
+    return tablegen.default_path()
+
+
+def build(verbose: bool = True):
+    build_tables(verbose)
+    build_library(verbose)
+
+
+if __name__ == "__main__":
+    build()

@@ -1,0 +1,999 @@
+// sfq.hip -- HIP kernels and the C ABI (include/sfq.h) of the MI355X QED Monte Carlo step.
+//
+// Method: Montefiori & Tamburini, arXiv:2301.07684 (SFQEDtoolkit); see sfq_device.h for the
+// equation behind every device function.
+//
+// Kernel design (gfx950, wave64):
+//   step_kernel  one persistent launch per step over all tiles.  Phase 1 streams the SoA
+//                particle arrays (coalesced FP64 loads), computes gamma, chi, the rate from
+//                LDS-staged coefficient tables and the decision; emitters are compacted with a
+//                wave ballot + popcount prefix into the block's own slice of a global queue (one
+//                LDS atomic per wave, no global atomics).  Phase 2 (same launch, after a block
+//                barrier) samples the block's emitters with all lanes busy: Philox draws, the
+//                inverse-CDF tables (L2-resident), recoil and products (one global atomic per
+//                wave and product buffer).
+//   rates/chi/sample/philox kernels: grid-stride elementwise kernels behind the batched calls.
+#include <hip/hip_runtime.h>
+
+#include <dlfcn.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sfq.h"
+#include "sfq_device.h"
+
+using namespace sfq;
+
+// =============================================================================================
+// Kernel arguments
+// =============================================================================================
+struct Tables {
+    const double *rad, *pair, *ka, *kb, *phinv, *ppinv;
+    const float *rad32, *pair32, *phinv32, *ppinv32;
+};
+
+struct Physics {
+    double dt;
+    double lc_over_lr;   // lambda_C/lambda_r: chi = gamma lc |...|, tau_C in units of 1/omega_r
+    double k_rate;       // alpha/(sqrt3 pi) lambda_r/lambda_C
+    double chi_min_pair; // 0.01, or 0.3 with bw_fast
+};
+
+struct StepArgs {
+    Tables tb;
+    Physics ph;
+    const sfq_tile* tiles;
+    const uint32_t* chunk_off;  // [ntiles + 1], prefix sums of chunks per tile
+    int ntiles;
+    int nchunks;
+    int chunk;
+    int decision;
+    int blcfa;
+    uint32_t step;
+    uint64_t seed;
+    uint32_t* q_idx;
+    uint32_t* q_tile;
+    double* q_chi;
+    double* q_gamma;
+    double* q_aux;
+    uint64_t q_cap_per_block;
+    sfq_products prod[3];       // photons, electrons, positrons
+    unsigned long long* prod_counts;
+    sfq_counters* counters;
+};
+
+enum { CNT_PROCESSED, CNT_EMITTED, CNT_CONVERTED, CNT_REJECTED, CNT_OOD, CNT_CLAMPED, CNT_OVERFLOW,
+       CNT_N };
+
+// =============================================================================================
+// Device helpers shared by the step and the batched calls
+// =============================================================================================
+template <bool MIXED>
+__device__ __forceinline__ double rate_lepton(const void* rad, const Physics& ph, double gamma,
+                                              double chi, bool* ood)
+{
+    if (!(chi > 0.0) || !(gamma > 0.0)) return 0.0;
+    if (MIXED) {
+        const float wt = wtilde_rad((const float*)rad, (float)chi, ood);
+        return (double)((float)ph.k_rate * (float)chi / (float)gamma * wt);
+    }
+    const double wt = wtilde_rad((const double*)rad, chi, ood);
+    return ph.k_rate * chi / gamma * wt;
+}
+
+template <bool MIXED>
+__device__ __forceinline__ double rate_photon(const void* pair, const Physics& ph, double gamma,
+                                              double chi, bool* ood)
+{
+    if (!(chi >= ph.chi_min_pair) || !(gamma > 0.0)) return 0.0;
+    if (MIXED) {
+        const float wt = wtilde_pair((const float*)pair, (float)chi, ood);
+        return (double)((float)ph.k_rate / (float)gamma * wt);
+    }
+    const double wt = wtilde_pair((const double*)pair, chi, ood);
+    return ph.k_rate / gamma * wt;
+}
+
+// photon emission: s = 3 chi wbar^3/2; FP32 evaluation in MIXED with FP64 where the photon
+// takes more than 0.999 of the energy (s > 999)
+template <bool MIXED>
+__device__ __forceinline__ double photon_s(const Tables& tb, double chi, double r, bool* ood)
+{
+    if (MIXED) {
+        const float s = photon_s32(tb.phinv32, chi, r, ood);
+        if (s <= 999.0f) return (double)s;
+    }
+    return photon_s64(tb.phinv, chi, r, ood);
+}
+
+// pair energies for uniform r: electron and positron energies (Eq. (return_to_nrg))
+template <bool MIXED>
+__device__ __forceinline__ void pair_split(const Tables& tb, double chi, double r, double gamma,
+                                           double& ge, double& gp, bool* ood)
+{
+    const double rp = 2.0 * r - 1.0;  // exact
+    const double q = fabs(rp);
+    double v, omv;
+    bool done = false;
+    if (MIXED) {
+        const float y = pair_y32(tb.ppinv32, chi, q, ood);
+        const float eta0 = (float)(8.0 / (3.0 * chi));
+        const float den = y + eta0;
+        const float vf = sqrtf(y / den);
+        if (vf <= 0.998f) {
+            v = (double)vf;
+            omv = (double)((eta0 / den) / (1.0f + vf));
+            done = true;
+        }
+    }
+    if (!done) {
+        const double y = pair_y64(tb.ppinv, chi, q, ood);
+        const double eta0 = 8.0 / (3.0 * chi);
+        const double den = y + eta0;
+        v = sqrt(y / den);
+        omv = (eta0 / den) / (1.0 + v);
+    }
+    const double hi = 0.5 * gamma * (1.0 + v), lo = 0.5 * gamma * omv;
+    if (rp < 0.0) { ge = lo; gp = hi; } else { ge = hi; gp = lo; }
+}
+
+__device__ __forceinline__ double lepton_momentum_factor(double g, double pn, bool& clamped)
+{
+    if (g > 1.0 && pn > 0.0) {
+        clamped = false;
+        return sqrt((g - 1.0) * (g + 1.0)) / pn;
+    }
+    clamped = true;
+    return 0.0;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// wave-aggregated reservation of `want` slots on a global counter; returns this lane's slot
+__device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* counter, bool want)
+{
+    const unsigned long long mask = __ballot(want);
+    if (mask == 0) return 0;
+    const int leader = __ffsll((long long)mask) - 1;
+    const int lane = lane_id();
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+    const unsigned long long below = mask & ((1ull << lane) - 1ull);
+    return base + (unsigned long long)__popcll(below);
+}
+
+// =============================================================================================
+// The step kernel
+// =============================================================================================
+constexpr int STEP_BLOCK = 256;
+
+__device__ __forceinline__ int find_tile(const uint32_t* off, int ntiles, int c)
+{
+    int lo = 0, hi = ntiles - 1;
+    while (lo < hi) {  // last t with off[t] <= c
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int)off[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
+{
+    using RT = typename std::conditional<MIXED, float, double>::type;
+    __shared__ RT s_rad[RAD_SIZE];
+    __shared__ RT s_pair[PAIR_SIZE];
+    __shared__ unsigned s_qn;
+    __shared__ unsigned long long s_cnt[CNT_N];
+
+    const int tid = threadIdx.x;
+    const RT* g_rad = MIXED ? (const RT*)A.tb.rad32 : (const RT*)A.tb.rad;
+    const RT* g_pair = MIXED ? (const RT*)A.tb.pair32 : (const RT*)A.tb.pair;
+    for (int k = tid; k < RAD_SIZE; k += STEP_BLOCK) s_rad[k] = g_rad[k];
+    for (int k = tid; k < PAIR_SIZE; k += STEP_BLOCK) s_pair[k] = g_pair[k];
+    if (tid == 0) s_qn = 0;
+    if (tid < CNT_N) s_cnt[tid] = 0;
+    __syncthreads();
+
+    unsigned long long c_proc = 0, c_ood = 0;
+    const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
+    const double dt = A.ph.dt;
+
+    // ---------------- phase 1: stream particles, rates, decisions, compaction ----------------
+    for (int c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
+        const int t = find_tile(A.chunk_off, A.ntiles, c);
+        const sfq_tile T = A.tiles[t];
+        const uint64_t start = (uint64_t)(c - (int)A.chunk_off[t]) * (uint64_t)A.chunk;
+        const uint64_t end = min(start + (uint64_t)A.chunk, T.n);
+        const bool photon = (T.species == SFQ_PHOTON);
+        const bool blcfa = A.blcfa && !photon;
+        for (uint64_t base = start; base < end; base += STEP_BLOCK) {
+            const uint64_t i = base + tid;
+            bool emit = false;
+            double chi = 0.0, gamma = 0.0, aux = 0.0;
+            if (i < end && (T.alive == nullptr || T.alive[i] != 0)) {
+                ++c_proc;
+                bool ood = false;
+                double W;
+                if (!blcfa) {
+                    gamma_chi(photon, T.px[i], T.py[i], T.pz[i], T.ex[i], T.ey[i], T.ez[i],
+                              T.bx[i], T.by[i], T.bz[i], A.ph.lc_over_lr, gamma, chi);
+                    W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
+                               : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+                    if (A.decision == SFQ_OPTICAL_DEPTH) {
+                        const double tau = T.tau[i] - W * dt;
+                        emit = tau < 0.0;
+                        if (!emit) T.tau[i] = tau;  // emitters get a fresh depth in phase 2
+                    } else {
+                        const Draw d = philox_draw(A.seed, T.uid[i], A.step, SFQ_P_LOCAL);
+                        emit = W * dt > uniform53(d.a);
+                    }
+                } else {
+                    // beyond-LCFA force update, Sec. 5 Eqs. (fl)-(condit)
+                    const uint64_t n = T.n;
+                    const double ux = T.px[i], uy = T.py[i], uz = T.pz[i];
+                    const double vx = T.px_prev[i], vy = T.py_prev[i], vz = T.pz_prev[i];
+                    const double flx = (ux - vx) / dt, fly = (uy - vy) / dt, flz = (uz - vz) / dt;
+                    const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
+                    const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
+                    gamma = sqrt(g2);
+                    const double fp = (flx * plx + fly * ply + flz * plz) / g2;
+                    const double Fx = flx - fp * plx, Fy = fly - fp * ply, Fz = flz - fp * plz;
+                    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+                    const double tc = A.ph.lc_over_lr;
+                    chi = tc * gamma * sqrt(F2);
+                    W = rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+                    if (T.just_created[i]) {
+                        T.fperp[i] = Fx; T.fperp[n + i] = Fy; T.fperp[2 * n + i] = Fz;
+                        T.dfperp[i] = 0.0; T.dfperp[n + i] = 0.0; T.dfperp[2 * n + i] = 0.0;
+                        T.just_created[i] = 0;
+                    } else {
+                        const double ox = T.fperp[i], oy = T.fperp[n + i], oz = T.fperp[2 * n + i];
+                        const double qx = T.dfperp[i], qy = T.dfperp[n + i], qz = T.dfperp[2 * n + i];
+                        const double ax = Fx - ox, ay = Fy - oy, az = Fz - oz;
+                        const double d1x = ax / dt, d1y = ay / dt, d1z = az / dt;
+                        const double dt2 = dt * dt;
+                        const double d2x = (ax - qx) / dt2, d2y = (ay - qy) / dt2, d2z = (az - qz) / dt2;
+                        const double delta = tc * tc * ((d1x * d1x + d1y * d1y + d1z * d1z) +
+                                                        fabs(Fx * d2x + Fy * d2y + Fz * d2z));
+                        T.fperp[i] = Fx; T.fperp[n + i] = Fy; T.fperp[2 * n + i] = Fz;
+                        T.dfperp[i] = ax; T.dfperp[n + i] = ay; T.dfperp[2 * n + i] = az;
+                        const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
+                        const Draw d = philox_draw(A.seed, T.uid[i], A.step, SFQ_P_LOCAL);
+                        emit = W * dt > uniform53(d.a);
+                        if (emit) {
+                            if (flag) {
+                                const double tau_ratio = 2.0 * PI * sqrt(F2 / delta);
+                                const double arg = chi / (8.0 * gamma) * tau_ratio;
+                                aux = 0.7 * gamma /
+                                      (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
+                                if (!(aux < 0.75 * gamma)) emit = false;  // Eq. (gammaLCFA) check
+                            } else if (chi > ZETA) {
+                                aux = 0.0;  // fields effectively constant: LCFA throughout
+                            } else {
+                                emit = false;
+                            }
+                        }
+                    }
+                }
+                if (T.chi_out) T.chi_out[i] = chi;
+                if (T.rate_out) T.rate_out[i] = W;
+                c_ood += ood ? 1 : 0;
+            }
+            // wave ballot + popcount prefix into the block's queue slice
+            const unsigned long long mask = __ballot(emit);
+            if (mask) {
+                const int lane = lane_id();
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned off = 0;
+                if (lane == leader) off = atomicAdd(&s_qn, (unsigned)__popcll(mask));
+                off = __shfl(off, leader);
+                if (emit) {
+                    const uint64_t slot =
+                        qbase + off + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+                    A.q_idx[slot] = (uint32_t)i;
+                    A.q_tile[slot] = (uint32_t)t;
+                    A.q_chi[slot] = chi;
+                    A.q_gamma[slot] = gamma;
+                    if (blcfa) A.q_aux[slot] = aux;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------- phase 2: the block's emitters ----------------
+    const unsigned nq = s_qn;
+    unsigned long long c_emit = 0, c_conv = 0, c_rej = 0, c_clamp = 0, c_over = 0;
+    for (unsigned b0 = 0; b0 < nq; b0 += STEP_BLOCK) {
+        const unsigned e = b0 + tid;
+        const bool valid = e < nq;
+        bool want_ph = false, want_pair = false;
+        double pgx = 0, pgy = 0, pgz = 0, tau_a = 0, pbx = 0, pby = 0, pbz = 0, tau_b = 0;
+        uint64_t uid_a = 0, uid_b = 0, parent = 0;
+        if (valid) {
+            const uint64_t slot = qbase + e;
+            const uint64_t i = A.q_idx[slot];
+            const int t = (int)A.q_tile[slot];
+            const double chi = A.q_chi[slot], gamma = A.q_gamma[slot];
+            const sfq_tile& T = A.tiles[t];
+            const uint64_t uid = T.uid[i];
+            parent = uid;
+            const Draw d1 = philox_draw(A.seed, uid, A.step, SFQ_P_EMIT);
+            const Draw d2 = philox_draw(A.seed, uid, A.step, SFQ_P_CHILD);
+            const double r = uniform53(d1.a);
+            const double px = T.px[i], py = T.py[i], pz = T.pz[i];
+            const double pn = sqrt(fma(px, px, fma(py, py, pz * pz)));
+            bool ood = false;
+            if (T.species != SFQ_PHOTON) {
+                const double s = photon_s<MIXED>(A.tb, chi, r, &ood);
+                const double gph = gamma * (s / (1.0 + s));
+                bool accept = true;
+                double gem;
+                if (A.blcfa) {
+                    const double limit = A.q_aux[slot];
+                    if (!(gph > limit)) {  // Eq. (rej_cond)
+                        const Draw dl = philox_draw(A.seed, uid, A.step, SFQ_P_LOCAL);
+                        const double r2 = uniform53(dl.b);
+                        const double lp_s = log_photon_pdf(A.tb.ka, A.tb.kb, gph, gamma, chi);
+                        const double lp_l = log_photon_pdf(A.tb.ka, A.tb.kb, limit, gamma, chi);
+                        accept = log(r2) + lp_s <= lp_l;
+                    }
+                    // recoil of the pushed momentum by the photon energy
+                    const double gpush = sqrt(1.0 + pn * pn);
+                    const double plx = 0.5 * (px + T.px_prev[i]), ply = 0.5 * (py + T.py_prev[i]),
+                                 plz = 0.5 * (pz + T.pz_prev[i]);
+                    const double dg = (pn * pn - (plx * plx + ply * ply + plz * plz)) / (gpush + gamma);
+                    gem = dg + gamma / (1.0 + s);
+                } else {
+                    gem = gamma / (1.0 + s);
+                }
+                if (accept) {
+                    bool cl;
+                    const double f = lepton_momentum_factor(gem, pn, cl);
+                    c_clamp += cl ? 1 : 0;
+                    T.px[i] = px * f; T.py[i] = py * f; T.pz[i] = pz * f;
+                    if (A.decision == SFQ_OPTICAL_DEPTH) T.tau[i] = optical_depth(d1.b);
+                    const double fg = pn > 0.0 ? gph / pn : 0.0;
+                    pgx = px * fg; pgy = py * fg; pgz = pz * fg;
+                    tau_a = optical_depth(d2.a);
+                    uid_a = d2.b;
+                    want_ph = true;
+                    ++c_emit;
+                } else {
+                    ++c_rej;
+                }
+            } else {
+                const Draw d3 = philox_draw(A.seed, uid, A.step, SFQ_P_CHILD2);
+                double ge, gp;
+                pair_split<MIXED>(A.tb, chi, r, gamma, ge, gp, &ood);
+                bool c1, c2;
+                const double fe = lepton_momentum_factor(ge, pn, c1);
+                const double fp = lepton_momentum_factor(gp, pn, c2);
+                c_clamp += (c1 ? 1 : 0) + (c2 ? 1 : 0);
+                pgx = px * fe; pgy = py * fe; pgz = pz * fe;   // electron
+                pbx = px * fp; pby = py * fp; pbz = pz * fp;   // positron
+                tau_a = optical_depth(d1.b);
+                uid_a = d2.b;
+                tau_b = optical_depth(d2.a);
+                uid_b = d3.a;
+                if (T.alive) T.alive[i] = 0;
+                want_pair = true;
+                ++c_conv;
+            }
+            c_ood += ood ? 1 : 0;
+        }
+        // products: one global atomic per wave and buffer
+        {
+            const unsigned long long k = wave_reserve(&A.prod_counts[0], want_ph);
+            if (want_ph) {
+                const sfq_products& P = A.prod[0];
+                if (k < P.capacity) {
+                    P.px[k] = pgx; P.py[k] = pgy; P.pz[k] = pgz; P.tau[k] = tau_a;
+                    P.uid[k] = uid_a; P.parent[k] = parent;
+                } else {
+                    ++c_over;
+                }
+            }
+        }
+        {
+            const unsigned long long ke = wave_reserve(&A.prod_counts[1], want_pair);
+            const unsigned long long kp = wave_reserve(&A.prod_counts[2], want_pair);
+            if (want_pair) {
+                const sfq_products& E = A.prod[1];
+                if (ke < E.capacity) {
+                    E.px[ke] = pgx; E.py[ke] = pgy; E.pz[ke] = pgz; E.tau[ke] = tau_a;
+                    E.uid[ke] = uid_a; E.parent[ke] = parent;
+                } else {
+                    ++c_over;
+                }
+                const sfq_products& P = A.prod[2];
+                if (kp < P.capacity) {
+                    P.px[kp] = pbx; P.py[kp] = pby; P.pz[kp] = pbz; P.tau[kp] = tau_b;
+                    P.uid[kp] = uid_b; P.parent[kp] = parent;
+                } else {
+                    ++c_over;
+                }
+            }
+        }
+    }
+
+    // ---------------- counters: block reduction, one global atomic per counter ----------------
+    const unsigned long long vals[CNT_N] = {c_proc, c_emit, c_conv, c_rej, c_ood, c_clamp, c_over};
+#pragma unroll
+    for (int k = 0; k < CNT_N; ++k) {
+        unsigned long long v = vals[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+        if (lane_id() == 0 && v) atomicAdd(&s_cnt[k], v);
+    }
+    __syncthreads();
+    if (tid < CNT_N && s_cnt[tid]) {
+        unsigned long long* dst = &A.counters->processed + tid;
+        atomicAdd(dst, s_cnt[tid]);
+    }
+}
+
+// =============================================================================================
+// Batched elementwise kernels
+// =============================================================================================
+template <bool MIXED>
+__global__ __launch_bounds__(256) void rates_kernel(Tables tb, Physics ph, int photon, size_t n,
+                                                    const double* gamma, const double* chi,
+                                                    double* out)
+{
+    using RT = typename std::conditional<MIXED, float, double>::type;
+    __shared__ RT s_tab[RAD_SIZE > PAIR_SIZE ? RAD_SIZE : PAIR_SIZE];
+    const RT* src = photon ? (MIXED ? (const RT*)tb.pair32 : (const RT*)tb.pair)
+                           : (MIXED ? (const RT*)tb.rad32 : (const RT*)tb.rad);
+    const int sz = photon ? PAIR_SIZE : RAD_SIZE;
+    for (int k = threadIdx.x; k < sz; k += blockDim.x) s_tab[k] = src[k];
+    __syncthreads();
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        bool ood = false;
+        out[i] = photon ? rate_photon<MIXED>(s_tab, ph, gamma[i], chi[i], &ood)
+                        : rate_lepton<MIXED>(s_tab, ph, gamma[i], chi[i], &ood);
+    }
+}
+
+__global__ __launch_bounds__(256) void chi_kernel(int photon, size_t n, const double* px,
+                                                  const double* py, const double* pz,
+                                                  const double* ex, const double* ey,
+                                                  const double* ez, const double* bx,
+                                                  const double* by, const double* bz,
+                                                  double lc, double* gamma_out, double* chi_out)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double g, c;
+        gamma_chi(photon != 0, px[i], py[i], pz[i], ex[i], ey[i], ez[i], bx[i], by[i], bz[i], lc,
+                  g, c);
+        if (gamma_out) gamma_out[i] = g;
+        chi_out[i] = c;
+    }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void sample_photon_kernel(Tables tb, size_t n,
+                                                            const double* gamma,
+                                                            const double* chi, const double* r,
+                                                            double* gph, double* gem)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        bool ood = false;
+        const double s = photon_s<MIXED>(tb, chi[i], r[i], &ood);
+        const double g = gamma[i];
+        gph[i] = g * (s / (1.0 + s));
+        if (gem) gem[i] = g / (1.0 + s);
+    }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void sample_pair_kernel(Tables tb, size_t n, const double* gamma,
+                                                          const double* chi, const double* r,
+                                                          double* ge, double* gp)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        bool ood = false;
+        double a, b;
+        pair_split<MIXED>(tb, chi[i], r[i], gamma[i], a, b, &ood);
+        ge[i] = a;
+        if (gp) gp[i] = b;
+    }
+}
+
+__global__ __launch_bounds__(256) void philox_kernel(size_t n, const uint64_t* uid, uint64_t seed,
+                                                     uint32_t step, uint32_t purpose,
+                                                     uint64_t* a, uint64_t* b)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const Draw d = philox_draw(seed, uid[i], step, purpose);
+        a[i] = d.a;
+        if (b) b[i] = d.b;
+    }
+}
+
+__global__ __launch_bounds__(256) void init_tau_kernel(size_t n, const uint64_t* uid,
+                                                       uint64_t seed, double* tau)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        tau[i] = optical_depth(philox_draw(seed, uid[i], 0, SFQ_P_INIT).a);
+}
+
+// =============================================================================================
+// Host side
+// =============================================================================================
+namespace {
+
+thread_local std::string tl_error = "";
+
+struct Staging {
+    void* host = nullptr;   // pinned
+    void* dev = nullptr;
+    hipEvent_t done = nullptr;
+    size_t bytes = 0;
+};
+
+constexpr int N_STAGING = 8;
+constexpr size_t STAGING_BYTES = 1 << 20;
+
+}  // namespace
+
+struct sfq_ctx {
+    int device = 0;
+    int precision = SFQ_FP64, decision = SFQ_OPTICAL_DEPTH, blcfa = 0, bw_fast = 0;
+    double lc_over_lr = 0, lr_over_lc = 0, dt = 0;
+    Physics ph{};
+    Tables tb{};
+    void* d_tab64 = nullptr;
+    void* d_tab32 = nullptr;
+    int num_cus = 256;
+    // step scratch
+    std::mutex mu;
+    void* d_queue = nullptr;
+    size_t queue_entries = 0;
+    Staging staging[N_STAGING];
+    int next_staging = 0;
+    // launch shape of the step kernel (tunable)
+    int blocks_per_cu = 4;
+    int chunk = 2048;
+};
+
+static sfq_status fail(sfq_ctx* h, sfq_status st, const std::string& msg)
+{
+    tl_error = msg;
+    (void)h;
+    return st;
+}
+
+#define HIP_TRY(h, expr)                                                                       \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(h, SFQ_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+static std::string default_tables_path()
+{
+    Dl_info info;
+    if (dladdr((void*)&sfq_create, &info) && info.dli_fname) {
+        std::string p(info.dli_fname);
+        const size_t s = p.find_last_of('/');
+        std::string dir = (s == std::string::npos) ? std::string(".") : p.substr(0, s);
+        return dir + "/data/sfq_tables.bin";
+    }
+    return "data/sfq_tables.bin";
+}
+
+static sfq_status load_tables(sfq_ctx* h, const char* path_in)
+{
+    const std::string path = path_in ? std::string(path_in) : default_tables_path();
+    FILE* f = fopen(path.c_str(), "rb");
+    if (!f) return fail(h, SFQ_E_TABLES, "cannot open table file " + path);
+    std::vector<char> buf;
+    {
+        fseek(f, 0, SEEK_END);
+        const long sz = ftell(f);
+        fseek(f, 0, SEEK_SET);
+        buf.resize(sz > 0 ? (size_t)sz : 0);
+        const size_t got = buf.empty() ? 0 : fread(buf.data(), 1, buf.size(), f);
+        fclose(f);
+        if (got != buf.size()) return fail(h, SFQ_E_TABLES, "short read on " + path);
+    }
+    size_t pos = 0;
+    auto need = [&](size_t k) { return pos + k <= buf.size(); };
+    if (!need(8 + 16) || memcmp(buf.data(), "SFQTAB02", 8) != 0)
+        return fail(h, SFQ_E_TABLES, "bad table file magic in " + path);
+    pos = 8;
+    uint32_t version, narr;
+    uint64_t hash;
+    memcpy(&version, &buf[pos], 4);
+    memcpy(&narr, &buf[pos + 4], 4);
+    memcpy(&hash, &buf[pos + 8], 8);
+    pos += 16;
+    (void)hash;
+    const int expect_geom[18] = {RATE_DEG, CHI_OCT_LO, CHI_OCT_HI, N_CHI_SEG, PAIR_OCT_LO,
+                                 N_PAIR_SEG, KA_DEG, N_KA, KB_DEG, KB_OCT_LO, KB_OCT_HI, INV_NC,
+                                 INV_NR, N_LO_SEG, T_OCT_LO, T_OCT_HI, N_HI_SEG, N_R_SEG};
+    if (version != 2 || narr != 6 || !need(sizeof(expect_geom)))
+        return fail(h, SFQ_E_TABLES, "unsupported table file version in " + path);
+    int geom[18];
+    memcpy(geom, &buf[pos], sizeof(geom));
+    pos += sizeof(geom);
+    for (int k = 0; k < 18; ++k)
+        if (geom[k] != expect_geom[k])
+            return fail(h, SFQ_E_TABLES, "table geometry mismatch (field " + std::to_string(k) +
+                                             ") in " + path + ": rebuild the tables");
+    const size_t sizes[6] = {RAD_SIZE, PAIR_SIZE, KA_SIZE, KB_SIZE, PHINV_SIZE, PPINV_SIZE};
+    size_t total = 0;
+    for (size_t s : sizes) total += s;
+    std::vector<double> host64(total);
+    size_t o = 0;
+    for (int a = 0; a < 6; ++a) {
+        uint64_t cnt;
+        if (!need(8)) return fail(h, SFQ_E_TABLES, "truncated table file " + path);
+        memcpy(&cnt, &buf[pos], 8);
+        pos += 8;
+        if (cnt != sizes[a] || !need(cnt * 8))
+            return fail(h, SFQ_E_TABLES, "table array size mismatch in " + path);
+        memcpy(&host64[o], &buf[pos], cnt * 8);
+        pos += cnt * 8;
+        o += cnt;
+    }
+    std::vector<float> host32(total);
+    for (size_t k = 0; k < total; ++k) host32[k] = (float)host64[k];
+    HIP_TRY(h, hipMalloc(&h->d_tab64, total * sizeof(double)));
+    HIP_TRY(h, hipMalloc(&h->d_tab32, total * sizeof(float)));
+    HIP_TRY(h, hipMemcpy(h->d_tab64, host64.data(), total * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->d_tab32, host32.data(), total * sizeof(float), hipMemcpyHostToDevice));
+    const double* d = (const double*)h->d_tab64;
+    const float* s = (const float*)h->d_tab32;
+    size_t off[6];
+    off[0] = 0;
+    for (int a = 1; a < 6; ++a) off[a] = off[a - 1] + sizes[a - 1];
+    h->tb.rad = d + off[0];
+    h->tb.pair = d + off[1];
+    h->tb.ka = d + off[2];
+    h->tb.kb = d + off[3];
+    h->tb.phinv = d + off[4];
+    h->tb.ppinv = d + off[5];
+    h->tb.rad32 = s + off[0];
+    h->tb.pair32 = s + off[1];
+    h->tb.phinv32 = s + off[4];
+    h->tb.ppinv32 = s + off[5];
+    return SFQ_OK;
+}
+
+static void release(sfq_ctx* h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    for (auto& s : h->staging) {
+        if (s.done) {
+            (void)hipEventSynchronize(s.done);
+            (void)hipEventDestroy(s.done);
+        }
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+    }
+    if (h->d_queue) (void)hipFree(h->d_queue);
+    if (h->d_tab64) (void)hipFree(h->d_tab64);
+    if (h->d_tab32) (void)hipFree(h->d_tab32);
+    delete h;
+}
+
+static int grid_for(const sfq_ctx* h, size_t n, int per_cu = 8)
+{
+    const size_t blocks = (n + 255) / 256;
+    const size_t cap = (size_t)h->num_cus * per_cu;
+    return (int)std::max<size_t>(1, std::min(blocks, cap));
+}
+
+extern "C" {
+
+sfq_status sfq_create(const sfq_config* cfg, sfq_handle* out)
+{
+    if (!cfg || !out) return fail(nullptr, SFQ_E_ARG, "sfq_create: NULL argument");
+    *out = nullptr;
+    const bool have_w = cfg->ref_omega > 0.0, have_l = cfg->ref_length > 0.0;
+    if (have_w == have_l)
+        return fail(nullptr, SFQ_E_ARG, "sfq_create: exactly one of ref_omega, ref_length must be > 0");
+    if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt))
+        return fail(nullptr, SFQ_E_ARG, "sfq_create: dt must be positive and finite");
+    if (cfg->precision != SFQ_FP64 && cfg->precision != SFQ_MIXED)
+        return fail(nullptr, SFQ_E_ARG, "sfq_create: bad precision");
+    if (cfg->decision != SFQ_OPTICAL_DEPTH && cfg->decision != SFQ_LOCAL)
+        return fail(nullptr, SFQ_E_ARG, "sfq_create: bad decision");
+    if (cfg->blcfa && cfg->decision != SFQ_LOCAL)
+        return fail(nullptr, SFQ_E_ARG, "sfq_create: beyond-LCFA emission requires the local decision");
+    if (cfg->reserved != 0) return fail(nullptr, SFQ_E_ARG, "sfq_create: reserved field must be 0");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(nullptr, SFQ_E_DEVICE, "sfq_create: no HIP device");
+    if (cfg->device < 0 || cfg->device >= ndev)
+        return fail(nullptr, SFQ_E_ARG, "sfq_create: device ordinal out of range");
+    sfq_ctx* h = new sfq_ctx();
+    h->device = cfg->device;
+    if (hipSetDevice(h->device) != hipSuccess) {
+        delete h;
+        return fail(nullptr, SFQ_E_DEVICE, "sfq_create: hipSetDevice failed");
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess && prop.multiProcessorCount > 0)
+        h->num_cus = prop.multiProcessorCount;
+    const double lambda_r = have_l ? cfg->ref_length : C_LIGHT / cfg->ref_omega;
+    h->lc_over_lr = LAMBDA_C / lambda_r;
+    h->lr_over_lc = lambda_r / LAMBDA_C;
+    h->dt = cfg->dt;
+    h->precision = cfg->precision;
+    h->decision = cfg->decision;
+    h->blcfa = cfg->blcfa;
+    h->bw_fast = cfg->bw_fast;
+    h->ph.dt = cfg->dt;
+    h->ph.lc_over_lr = h->lc_over_lr;
+    h->ph.k_rate = ALPHA / (sqrt(3.0) * PI) * h->lr_over_lc;
+    h->ph.chi_min_pair = cfg->bw_fast ? 0.3 : 0.01;
+    const sfq_status st = load_tables(h, cfg->tables_path);
+    if (st != SFQ_OK) {
+        const std::string msg = tl_error;
+        release(h);
+        tl_error = msg;
+        return st;
+    }
+    *out = h;
+    return SFQ_OK;
+}
+
+void sfq_destroy(sfq_handle h) { release(h); }
+
+const char* sfq_last_error(sfq_handle h)
+{
+    (void)h;
+    return tl_error.c_str();
+}
+
+sfq_status sfq_units(sfq_handle h, double* lc_over_lr, double* lr_over_lc)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_units: NULL handle");
+    if (lc_over_lr) *lc_over_lr = h->lc_over_lr;
+    if (lr_over_lc) *lr_over_lc = h->lr_over_lc;
+    return SFQ_OK;
+}
+
+sfq_status sfq_chi(sfq_handle h, int species, size_t n, const double* px, const double* py,
+                   const double* pz, const double* ex, const double* ey, const double* ez,
+                   const double* bx, const double* by, const double* bz, double* gamma_out,
+                   double* chi_out, void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_chi: NULL handle");
+    if (species < 0 || species > 2) return fail(h, SFQ_E_ARG, "sfq_chi: bad species");
+    if (n == 0) return SFQ_OK;
+    if (!px || !py || !pz || !ex || !ey || !ez || !bx || !by || !bz || !chi_out)
+        return fail(h, SFQ_E_ARG, "sfq_chi: NULL array");
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipLaunchKernelGGL(chi_kernel, dim3(grid_for(h, n)), dim3(256), 0, (hipStream_t)stream,
+                       species == SFQ_PHOTON, n, px, py, pz, ex, ey, ez, bx, by, bz,
+                       h->lc_over_lr, gamma_out, chi_out);
+    HIP_TRY(h, hipGetLastError());
+    return SFQ_OK;
+}
+
+sfq_status sfq_rates(sfq_handle h, int species, size_t n, const double* gamma, const double* chi,
+                     double* rate_out, void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_rates: NULL handle");
+    if (species < 0 || species > 2) return fail(h, SFQ_E_ARG, "sfq_rates: bad species");
+    if (n == 0) return SFQ_OK;
+    if (!gamma || !chi || !rate_out) return fail(h, SFQ_E_ARG, "sfq_rates: NULL array");
+    HIP_TRY(h, hipSetDevice(h->device));
+    const int photon = species == SFQ_PHOTON;
+    if (h->precision == SFQ_MIXED)
+        hipLaunchKernelGGL(rates_kernel<true>, dim3(grid_for(h, n)), dim3(256), 0,
+                           (hipStream_t)stream, h->tb, h->ph, photon, n, gamma, chi, rate_out);
+    else
+        hipLaunchKernelGGL(rates_kernel<false>, dim3(grid_for(h, n)), dim3(256), 0,
+                           (hipStream_t)stream, h->tb, h->ph, photon, n, gamma, chi, rate_out);
+    HIP_TRY(h, hipGetLastError());
+    return SFQ_OK;
+}
+
+sfq_status sfq_sample_photon(sfq_handle h, size_t n, const double* gamma, const double* chi,
+                             const double* r, double* gamma_photon_out, double* gamma_emitter_out,
+                             void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_sample_photon: NULL handle");
+    if (n == 0) return SFQ_OK;
+    if (!gamma || !chi || !r || !gamma_photon_out)
+        return fail(h, SFQ_E_ARG, "sfq_sample_photon: NULL array");
+    HIP_TRY(h, hipSetDevice(h->device));
+    if (h->precision == SFQ_MIXED)
+        hipLaunchKernelGGL(sample_photon_kernel<true>, dim3(grid_for(h, n)), dim3(256), 0,
+                           (hipStream_t)stream, h->tb, n, gamma, chi, r, gamma_photon_out,
+                           gamma_emitter_out);
+    else
+        hipLaunchKernelGGL(sample_photon_kernel<false>, dim3(grid_for(h, n)), dim3(256), 0,
+                           (hipStream_t)stream, h->tb, n, gamma, chi, r, gamma_photon_out,
+                           gamma_emitter_out);
+    HIP_TRY(h, hipGetLastError());
+    return SFQ_OK;
+}
+
+sfq_status sfq_sample_pair(sfq_handle h, size_t n, const double* gamma, const double* chi,
+                           const double* r, double* gamma_electron_out,
+                           double* gamma_positron_out, void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_sample_pair: NULL handle");
+    if (n == 0) return SFQ_OK;
+    if (!gamma || !chi || !r || !gamma_electron_out)
+        return fail(h, SFQ_E_ARG, "sfq_sample_pair: NULL array");
+    HIP_TRY(h, hipSetDevice(h->device));
+    if (h->precision == SFQ_MIXED)
+        hipLaunchKernelGGL(sample_pair_kernel<true>, dim3(grid_for(h, n)), dim3(256), 0,
+                           (hipStream_t)stream, h->tb, n, gamma, chi, r, gamma_electron_out,
+                           gamma_positron_out);
+    else
+        hipLaunchKernelGGL(sample_pair_kernel<false>, dim3(grid_for(h, n)), dim3(256), 0,
+                           (hipStream_t)stream, h->tb, n, gamma, chi, r, gamma_electron_out,
+                           gamma_positron_out);
+    HIP_TRY(h, hipGetLastError());
+    return SFQ_OK;
+}
+
+sfq_status sfq_philox(sfq_handle h, size_t n, const uint64_t* uid, uint64_t seed, uint64_t step,
+                      uint32_t purpose, uint64_t* a_out, uint64_t* b_out, void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_philox: NULL handle");
+    if (n == 0) return SFQ_OK;
+    if (!uid || !a_out) return fail(h, SFQ_E_ARG, "sfq_philox: NULL array");
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipLaunchKernelGGL(philox_kernel, dim3(grid_for(h, n)), dim3(256), 0, (hipStream_t)stream, n,
+                       uid, seed, (uint32_t)step, purpose, a_out, b_out);
+    HIP_TRY(h, hipGetLastError());
+    return SFQ_OK;
+}
+
+sfq_status sfq_init_optical_depth(sfq_handle h, size_t n, const uint64_t* uid, uint64_t seed,
+                                  double* tau_out, void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_init_optical_depth: NULL handle");
+    if (n == 0) return SFQ_OK;
+    if (!uid || !tau_out) return fail(h, SFQ_E_ARG, "sfq_init_optical_depth: NULL array");
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipLaunchKernelGGL(init_tau_kernel, dim3(grid_for(h, n)), dim3(256), 0, (hipStream_t)stream, n,
+                       uid, seed, tau_out);
+    HIP_TRY(h, hipGetLastError());
+    return SFQ_OK;
+}
+
+sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_step: NULL handle");
+    if (!desc || !desc->tiles) return fail(h, SFQ_E_ARG, "sfq_step: NULL descriptor");
+    if (desc->ntiles <= 0 || desc->ntiles > SFQ_MAX_TILES)
+        return fail(h, SFQ_E_ARG, "sfq_step: ntiles out of range");
+    if (!desc->counters || !desc->product_counts)
+        return fail(h, SFQ_E_ARG, "sfq_step: NULL counters");
+    const int nt = desc->ntiles;
+    std::vector<uint32_t> off(nt + 1, 0);
+    uint64_t total = 0;
+    for (int t = 0; t < nt; ++t) {
+        const sfq_tile& T = desc->tiles[t];
+        if (T.species < 0 || T.species > 2 || T.reserved != 0)
+            return fail(h, SFQ_E_ARG, "sfq_step: bad tile species (tile " + std::to_string(t) + ")");
+        if (T.n >= (1ull << 32))
+            return fail(h, SFQ_E_CAPACITY, "sfq_step: tile larger than 2^32 - 1 particles");
+        const bool photon = T.species == SFQ_PHOTON;
+        const bool bl = h->blcfa && !photon;
+        if (T.n > 0) {
+            if (!T.px || !T.py || !T.pz || !T.uid)
+                return fail(h, SFQ_E_ARG, "sfq_step: NULL momentum/uid (tile " + std::to_string(t) + ")");
+            if (!bl && (!T.ex || !T.ey || !T.ez || !T.bx || !T.by || !T.bz))
+                return fail(h, SFQ_E_ARG, "sfq_step: NULL field array (tile " + std::to_string(t) + ")");
+            if (!bl && h->decision == SFQ_OPTICAL_DEPTH && !T.tau)
+                return fail(h, SFQ_E_ARG, "sfq_step: NULL tau (tile " + std::to_string(t) + ")");
+            if (photon && !T.alive)
+                return fail(h, SFQ_E_ARG, "sfq_step: photon tiles need an alive array");
+            if (bl && (!T.px_prev || !T.py_prev || !T.pz_prev || !T.fperp || !T.dfperp ||
+                       !T.just_created))
+                return fail(h, SFQ_E_ARG, "sfq_step: beyond-LCFA state missing (tile " +
+                                              std::to_string(t) + ")");
+        }
+        off[t + 1] = off[t] + (uint32_t)((T.n + h->chunk - 1) / h->chunk);
+        total += T.n;
+    }
+    const sfq_products* P[3] = {&desc->photons, &desc->electrons, &desc->positrons};
+    for (int k = 0; k < 3; ++k)
+        if (P[k]->capacity > 0 &&
+            (!P[k]->px || !P[k]->py || !P[k]->pz || !P[k]->tau || !P[k]->uid || !P[k]->parent))
+            return fail(h, SFQ_E_ARG, "sfq_step: NULL product array");
+    const int nchunks = (int)off[nt];
+    if (nchunks == 0) return SFQ_OK;
+
+    std::lock_guard<std::mutex> lock(h->mu);
+    HIP_TRY(h, hipSetDevice(h->device));
+    const int grid = std::max(1, std::min(nchunks, h->num_cus * h->blocks_per_cu));
+    const uint64_t chunks_per_block = (uint64_t)((nchunks + grid - 1) / grid);
+    const uint64_t cap_per_block = chunks_per_block * (uint64_t)h->chunk;
+    const uint64_t entries = cap_per_block * (uint64_t)grid;
+    if (entries > h->queue_entries) {
+        if (h->d_queue) {
+            HIP_TRY(h, hipDeviceSynchronize());
+            HIP_TRY(h, hipFree(h->d_queue));
+            h->d_queue = nullptr;
+            h->queue_entries = 0;
+        }
+        const size_t bytes = entries * (4 + 4 + 8 + 8 + 8);
+        if (hipMalloc(&h->d_queue, bytes) != hipSuccess) {
+            h->d_queue = nullptr;
+            return fail(h, SFQ_E_NOMEM, "sfq_step: cannot allocate the emitter queue");
+        }
+        h->queue_entries = entries;
+    }
+    // descriptors through a ring of pinned staging buffers
+    Staging& S = h->staging[h->next_staging];
+    h->next_staging = (h->next_staging + 1) % N_STAGING;
+    const size_t need = nt * sizeof(sfq_tile) + (nt + 1) * sizeof(uint32_t) + 64;
+    if (need > STAGING_BYTES) return fail(h, SFQ_E_CAPACITY, "sfq_step: too many tiles");
+    if (!S.host) {
+        HIP_TRY(h, hipHostMalloc(&S.host, STAGING_BYTES, hipHostMallocDefault));
+        HIP_TRY(h, hipMalloc(&S.dev, STAGING_BYTES));
+        HIP_TRY(h, hipEventCreateWithFlags(&S.done, hipEventDisableTiming));
+        S.bytes = STAGING_BYTES;
+    } else {
+        HIP_TRY(h, hipEventSynchronize(S.done));
+    }
+    char* hb = (char*)S.host;
+    memcpy(hb, desc->tiles, nt * sizeof(sfq_tile));
+    const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
+    memcpy(hb + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
+    HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, off_pos + (nt + 1) * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, (hipStream_t)stream));
+
+    StepArgs A;
+    A.tb = h->tb;
+    A.ph = h->ph;
+    A.tiles = (const sfq_tile*)S.dev;
+    A.chunk_off = (const uint32_t*)((char*)S.dev + off_pos);
+    A.ntiles = nt;
+    A.nchunks = nchunks;
+    A.chunk = h->chunk;
+    A.decision = h->decision;
+    A.blcfa = h->blcfa;
+    A.step = (uint32_t)desc->step;
+    A.seed = desc->seed;
+    char* q = (char*)h->d_queue;
+    const size_t E = h->queue_entries;
+    A.q_chi = (double*)q;
+    A.q_gamma = (double*)(q + 8 * E);
+    A.q_aux = (double*)(q + 16 * E);
+    A.q_idx = (uint32_t*)(q + 24 * E);
+    A.q_tile = (uint32_t*)(q + 28 * E);
+    A.q_cap_per_block = cap_per_block;
+    A.prod[0] = desc->photons;
+    A.prod[1] = desc->electrons;
+    A.prod[2] = desc->positrons;
+    A.prod_counts = desc->product_counts;
+    A.counters = desc->counters;
+    if (h->precision == SFQ_MIXED)
+        hipLaunchKernelGGL(step_kernel<true>, dim3(grid), dim3(STEP_BLOCK), 0, (hipStream_t)stream, A);
+    else
+        hipLaunchKernelGGL(step_kernel<false>, dim3(grid), dim3(STEP_BLOCK), 0, (hipStream_t)stream, A);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
+    (void)total;
+    return SFQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,350 @@
+"""Python binding of the C ABI in include/sfq.h (argument marshalling only).
+
+Every computation runs in the HIP library ``libsfq.so`` built from ``csrc/sfq.hip``; this
+module only checks tensor shapes/dtypes/devices, passes ``tensor.data_ptr()`` and the current
+HIP stream, and raises on a non-zero status.  There is no CPU fallback: if the library is
+missing, ``load()`` raises.  PyTorch is used for device memory and streams only.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfq.so")
+
+ELECTRON, POSITRON, PHOTON = 0, 1, 2
+FP64, MIXED = 0, 1
+OPTICAL_DEPTH, LOCAL = 0, 1
+P_INIT, P_EMIT, P_CHILD, P_CHILD2, P_LOCAL = 0, 1, 2, 3, 4
+MAX_TILES = 4096
+
+STATUS = {0: "SFQ_OK", 1: "SFQ_E_ARG", 2: "SFQ_E_STATE", 3: "SFQ_E_NOMEM", 4: "SFQ_E_CAPACITY",
+          5: "SFQ_E_DEVICE", 6: "SFQ_E_TABLES"}
+
+# every symbol declared in include/sfq.h
+EXPORTS = ("sfq_create", "sfq_destroy", "sfq_last_error", "sfq_units", "sfq_chi", "sfq_rates",
+           "sfq_sample_photon", "sfq_sample_pair", "sfq_philox", "sfq_init_optical_depth",
+           "sfq_step")
+
+
+class Config(C.Structure):
+    _fields_ = [("ref_omega", C.c_double), ("ref_length", C.c_double), ("dt", C.c_double),
+                ("precision", C.c_int32), ("decision", C.c_int32), ("blcfa", C.c_int32),
+                ("bw_fast", C.c_int32), ("device", C.c_int32), ("reserved", C.c_int32),
+                ("tables_path", C.c_char_p)]
+
+
+_P = C.c_void_p
+
+
+class Tile(C.Structure):
+    _fields_ = [("species", C.c_int32), ("reserved", C.c_int32), ("n", C.c_uint64),
+                ("px", _P), ("py", _P), ("pz", _P), ("ex", _P), ("ey", _P), ("ez", _P),
+                ("bx", _P), ("by", _P), ("bz", _P), ("tau", _P), ("uid", _P), ("alive", _P),
+                ("px_prev", _P), ("py_prev", _P), ("pz_prev", _P), ("fperp", _P),
+                ("dfperp", _P), ("just_created", _P), ("chi_out", _P), ("rate_out", _P)]
+
+
+class ProductsC(C.Structure):
+    _fields_ = [("px", _P), ("py", _P), ("pz", _P), ("tau", _P), ("uid", _P), ("parent", _P),
+                ("capacity", C.c_uint64)]
+
+
+class StepDesc(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("step", C.c_uint64), ("ntiles", C.c_int32),
+                ("reserved", C.c_int32), ("tiles", C.POINTER(Tile)), ("photons", ProductsC),
+                ("electrons", ProductsC), ("positrons", ProductsC), ("product_counts", _P),
+                ("counters", _P)]
+
+
+COUNTER_NAMES = ("processed", "emitted", "converted", "blcfa_rejected", "out_of_domain",
+                 "clamped", "overflow", "reserved")
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsfq.so (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run `python -m paper_2301_07684_amd.build`)")
+    L = C.CDLL(path)
+    st, vp, sz, dp, u64 = C.c_int, C.c_void_p, C.c_size_t, C.c_void_p, C.c_uint64
+    L.sfq_create.restype = st
+    L.sfq_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+    L.sfq_destroy.restype = None
+    L.sfq_destroy.argtypes = [vp]
+    L.sfq_last_error.restype = C.c_char_p
+    L.sfq_last_error.argtypes = [vp]
+    L.sfq_units.restype = st
+    L.sfq_units.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.sfq_chi.restype = st
+    L.sfq_chi.argtypes = [vp, C.c_int, sz] + [dp] * 11 + [vp]
+    L.sfq_rates.restype = st
+    L.sfq_rates.argtypes = [vp, C.c_int, sz, dp, dp, dp, vp]
+    L.sfq_sample_photon.restype = st
+    L.sfq_sample_photon.argtypes = [vp, sz, dp, dp, dp, dp, dp, vp]
+    L.sfq_sample_pair.restype = st
+    L.sfq_sample_pair.argtypes = [vp, sz, dp, dp, dp, dp, dp, vp]
+    L.sfq_philox.restype = st
+    L.sfq_philox.argtypes = [vp, sz, dp, u64, u64, C.c_uint32, dp, dp, vp]
+    L.sfq_init_optical_depth.restype = st
+    L.sfq_init_optical_depth.argtypes = [vp, sz, dp, u64, dp, vp]
+    L.sfq_step.restype = st
+    L.sfq_step.argtypes = [vp, C.POINTER(StepDesc), vp]
+    _lib = L
+    return L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, n=None, name="array"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return t
+
+
+class SFQError(RuntimeError):
+    pass
+
+
+class Handle:
+    """An initialised library context (paper App. A functions 1/2 and 14)."""
+
+    def __init__(self, *, ref_length: float | None = None, ref_omega: float | None = None,
+                 dt: float, precision: int = FP64, decision: int = OPTICAL_DEPTH,
+                 blcfa: bool = False, bw_fast: bool = False, device: int = 0,
+                 tables_path: str | None = None):
+        self._L = load()
+        cfg = Config(ref_omega=ref_omega or 0.0, ref_length=ref_length or 0.0, dt=dt,
+                     precision=precision, decision=decision, blcfa=int(blcfa),
+                     bw_fast=int(bw_fast), device=device, reserved=0,
+                     tables_path=None if tables_path is None else tables_path.encode())
+        h = C.c_void_p()
+        self._check(self._L.sfq_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self.precision, self.decision, self.blcfa, self.bw_fast = precision, decision, blcfa, bw_fast
+        self.device = torch.device("cuda", device)
+        lc, lr = C.c_double(), C.c_double()
+        self._check(self._L.sfq_units(self._h, C.byref(lc), C.byref(lr)))
+        self.lc_over_lr, self.lr_over_lc, self.dt = lc.value, lr.value, dt
+
+    def _check(self, st):
+        if st != 0:
+            msg = self._L.sfq_last_error(None).decode()
+            raise SFQError(f"{STATUS.get(st, st)}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.sfq_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- batched calls ------------------------------------------------------------------------
+    def chi(self, species, p, E, B, stream=None):
+        """p, E, B: sequences of three float64 device tensors.  Returns (gamma, chi)."""
+        n = p[0].numel()
+        arrs = [_dev(a, torch.float64, n, "p/E/B") for a in (*p, *E, *B)]
+        gamma = torch.empty(n, dtype=torch.float64, device=arrs[0].device)
+        chi = torch.empty_like(gamma)
+        self._check(self._L.sfq_chi(self._h, species, n, *[_ptr(a) for a in arrs], _ptr(gamma),
+                                    _ptr(chi), _stream(stream)))
+        return gamma, chi
+
+    def rates(self, species, gamma, chi, out=None, stream=None):
+        n = gamma.numel()
+        _dev(gamma, torch.float64, n, "gamma")
+        _dev(chi, torch.float64, n, "chi")
+        out = torch.empty_like(gamma) if out is None else _dev(out, torch.float64, n, "out")
+        self._check(self._L.sfq_rates(self._h, species, n, _ptr(gamma), _ptr(chi), _ptr(out),
+                                      _stream(stream)))
+        return out
+
+    def sample_photon(self, gamma, chi, r, stream=None):
+        n = gamma.numel()
+        for nm, a in (("gamma", gamma), ("chi", chi), ("r", r)):
+            _dev(a, torch.float64, n, nm)
+        gph, gem = torch.empty_like(gamma), torch.empty_like(gamma)
+        self._check(self._L.sfq_sample_photon(self._h, n, _ptr(gamma), _ptr(chi), _ptr(r),
+                                              _ptr(gph), _ptr(gem), _stream(stream)))
+        return gph, gem
+
+    def sample_pair(self, gamma, chi, r, stream=None):
+        n = gamma.numel()
+        for nm, a in (("gamma", gamma), ("chi", chi), ("r", r)):
+            _dev(a, torch.float64, n, nm)
+        ge, gp = torch.empty_like(gamma), torch.empty_like(gamma)
+        self._check(self._L.sfq_sample_pair(self._h, n, _ptr(gamma), _ptr(chi), _ptr(r),
+                                            _ptr(ge), _ptr(gp), _stream(stream)))
+        return ge, gp
+
+    def philox(self, uid, seed, step, purpose, stream=None):
+        """uid: int64 device tensor (bit pattern of the uint64 ids).  Returns (a, b) int64."""
+        n = uid.numel()
+        _dev(uid, torch.int64, n, "uid")
+        a, b = torch.empty_like(uid), torch.empty_like(uid)
+        self._check(self._L.sfq_philox(self._h, n, _ptr(uid), seed, step, purpose, _ptr(a),
+                                       _ptr(b), _stream(stream)))
+        return a, b
+
+    def init_optical_depth(self, uid, seed, out=None, stream=None):
+        n = uid.numel()
+        _dev(uid, torch.int64, n, "uid")
+        out = torch.empty(n, dtype=torch.float64, device=uid.device) if out is None else out
+        self._check(self._L.sfq_init_optical_depth(self._h, n, _ptr(uid), seed, _ptr(out),
+                                                   _stream(stream)))
+        return out
+
+    def step(self, tiles: Sequence["TileArrays"], *, seed: int, step: int,
+             products: "ProductBuffers", counters: "Counters", stream=None):
+        """One Monte Carlo step over all tiles (one launch sequence on `stream`)."""
+        nt = len(tiles)
+        if nt == 0 or nt > MAX_TILES:
+            raise ValueError("1 <= len(tiles) <= MAX_TILES")
+        arr = (Tile * nt)()
+        for k, t in enumerate(tiles):
+            arr[k] = t.to_c()
+        desc = StepDesc(seed=seed, step=step, ntiles=nt, reserved=0, tiles=arr,
+                        photons=products.photons.to_c(), electrons=products.electrons.to_c(),
+                        positrons=products.positrons.to_c(),
+                        product_counts=_ptr(products.counts), counters=_ptr(counters.t))
+        self._check(self._L.sfq_step(self._h, C.byref(desc), _stream(stream)))
+
+
+@dataclass
+class TileArrays:
+    """Device SoA arrays of one tile (see sfq_tile in include/sfq.h)."""
+    species: int
+    px: torch.Tensor
+    py: torch.Tensor
+    pz: torch.Tensor
+    ex: Optional[torch.Tensor] = None
+    ey: Optional[torch.Tensor] = None
+    ez: Optional[torch.Tensor] = None
+    bx: Optional[torch.Tensor] = None
+    by: Optional[torch.Tensor] = None
+    bz: Optional[torch.Tensor] = None
+    tau: Optional[torch.Tensor] = None
+    uid: Optional[torch.Tensor] = None
+    alive: Optional[torch.Tensor] = None
+    px_prev: Optional[torch.Tensor] = None
+    py_prev: Optional[torch.Tensor] = None
+    pz_prev: Optional[torch.Tensor] = None
+    fperp: Optional[torch.Tensor] = None
+    dfperp: Optional[torch.Tensor] = None
+    just_created: Optional[torch.Tensor] = None
+    chi_out: Optional[torch.Tensor] = None
+    rate_out: Optional[torch.Tensor] = None
+
+    def __post_init__(self):
+        n = self.px.numel()
+        f64 = ("px", "py", "pz", "ex", "ey", "ez", "bx", "by", "bz", "tau", "px_prev", "py_prev",
+               "pz_prev", "chi_out", "rate_out")
+        for nm in f64:
+            a = getattr(self, nm)
+            if a is not None:
+                _dev(a, torch.float64, n, nm)
+        for nm in ("fperp", "dfperp"):
+            a = getattr(self, nm)
+            if a is not None:
+                _dev(a, torch.float64, 3 * n, nm)
+        if self.uid is not None:
+            _dev(self.uid, torch.int64, n, "uid")
+        for nm in ("alive", "just_created"):
+            a = getattr(self, nm)
+            if a is not None:
+                _dev(a, torch.uint8, n, nm)
+
+    @property
+    def n(self):
+        return self.px.numel()
+
+    def to_c(self) -> Tile:
+        t = Tile(species=self.species, reserved=0, n=self.n)
+        for nm, _ in Tile._fields_[3:]:
+            setattr(t, nm, _ptr(getattr(self, nm)))
+        return t
+
+
+@dataclass
+class ProductSpecies:
+    px: torch.Tensor
+    py: torch.Tensor
+    pz: torch.Tensor
+    tau: torch.Tensor
+    uid: torch.Tensor
+    parent: torch.Tensor
+
+    @staticmethod
+    def empty(capacity: int, device) -> "ProductSpecies":
+        f = lambda: torch.empty(max(capacity, 1), dtype=torch.float64, device=device)
+        i = lambda: torch.empty(max(capacity, 1), dtype=torch.int64, device=device)
+        return ProductSpecies(f(), f(), f(), f(), i(), i())
+
+    @property
+    def capacity(self):
+        return self.px.numel()
+
+    def to_c(self) -> ProductsC:
+        return ProductsC(px=_ptr(self.px), py=_ptr(self.py), pz=_ptr(self.pz), tau=_ptr(self.tau),
+                         uid=_ptr(self.uid), parent=_ptr(self.parent), capacity=self.capacity)
+
+
+@dataclass
+class ProductBuffers:
+    photons: ProductSpecies
+    electrons: ProductSpecies
+    positrons: ProductSpecies
+    counts: torch.Tensor = field(default=None)
+
+    @staticmethod
+    def empty(capacity_photons: int, capacity_pairs: int, device) -> "ProductBuffers":
+        pb = ProductBuffers(ProductSpecies.empty(capacity_photons, device),
+                            ProductSpecies.empty(capacity_pairs, device),
+                            ProductSpecies.empty(capacity_pairs, device))
+        pb.counts = torch.zeros(3, dtype=torch.int64, device=device)
+        return pb
+
+    def reset(self):
+        self.counts.zero_()
+
+    def host_counts(self):
+        return [int(v) for v in self.counts.cpu()]
+
+
+class Counters:
+    def __init__(self, device):
+        self.t = torch.zeros(8, dtype=torch.int64, device=device)
+
+    def reset(self):
+        self.t.zero_()
+
+    def as_dict(self):
+        v = self.t.cpu().tolist()
+        return dict(zip(COUNTER_NAMES, v))
