@@ -190,6 +190,13 @@ typedef struct {
 
 #define SFQ_MAX_TILES 4096
 
+/* Launch shape of sfq_step for this handle (used by the autotuner): the streaming kernel runs
+ * blocks_per_cu x (number of compute units) blocks of 256 threads, each taking `chunk`
+ * consecutive particles of one tile at a time (chunk a multiple of 256 in [256, 2^22]).
+ * Results do not depend on the launch shape. */
+sfq_status sfq_set_launch(sfq_handle h, int blocks_per_cu, int chunk);
+sfq_status sfq_get_launch(sfq_handle h, int* blocks_per_cu, int* chunk);
+
 /* The Monte Carlo step (paper Fig. 7 workflow; App. A functions 4-6, 8-11, 15-17): for every
  * alive particle of every tile, gamma and chi (or, for blcfa leptons, the Sec. 5 force update),
  * the LCFA rate, the decision of cfg.decision, and for the particles that emit: Philox draws,

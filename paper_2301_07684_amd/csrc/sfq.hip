@@ -4,12 +4,12 @@
 // equation behind every device function.
 //
 // Kernel design (gfx950, wave64):
-//   step_kernel  one persistent launch per step over all tiles.  Phase 1 streams the SoA
-//                particle arrays (coalesced FP64 loads), computes gamma, chi, the rate from
-//                LDS-staged coefficient tables and the decision; emitters are compacted with a
-//                wave ballot + popcount prefix into the block's own slice of a global queue (one
-//                LDS atomic per wave, no global atomics).  Phase 2 (same launch, after a block
-//                barrier) samples the block's emitters with all lanes busy: Philox draws, the
+//   bulk_kernel  persistent streaming pass over all tiles of a step: coalesced FP64 SoA loads,
+//                gamma, chi, the rate from LDS-staged coefficient tables and the decision;
+//                emitters are compacted with a wave ballot + popcount prefix into the block's
+//                own slice of a queue (one LDS atomic per wave, no global atomics).  It carries
+//                none of the sampling code, so its register footprint allows high occupancy.
+//   emit_kernel  block b samples the slice of block b with all lanes busy: Philox draws, the
 //                inverse-CDF tables (L2-resident), recoil and products (one global atomic per
 //                wave and product buffer).
 //   rates/chi/sample/philox kernels: grid-stride elementwise kernels behind the batched calls.
@@ -58,11 +58,19 @@ struct StepArgs {
     int blcfa;
     uint32_t step;
     uint64_t seed;
+    // emitter queue (SoA).  Block b owns entries [b cap, (b+1) cap): leptons from the start of
+    // the slice upwards, photons from its end downwards.
     uint32_t* q_idx;
     uint32_t* q_tile;
     double* q_chi;
     double* q_gamma;
-    double* q_aux;
+    double* q_px;
+    double* q_py;
+    double* q_pz;
+    uint64_t* q_uid;
+    double* q_aux;              // beyond-LCFA threshold gamma_{gamma,LCFA}
+    double* q_aux2;             // beyond-LCFA: gamma of the pushed momentum minus gamma^{(n)}
+    uint32_t* q_count;          // [2 grid]: lepton and photon emitters queued by each block
     uint64_t q_cap_per_block;
     sfq_products prod[3];       // photons, electrons, positrons
     unsigned long long* prod_counts;
@@ -101,47 +109,70 @@ __device__ __forceinline__ double rate_photon(const void* pair, const Physics& p
     return ph.k_rate / gamma * wt;
 }
 
-// photon emission: s = 3 chi wbar^3/2; FP32 evaluation in MIXED with FP64 where the photon
-// takes more than 0.999 of the energy (s > 999)
+// Energy sampling for one lane; every lane of the wave must call it (cooperative table
+// evaluation).  Lanes with valid == false pass through with a dummy request.
+//   photon emission (pair == false): s = 3 chi wbar^3 / 2 (Eq. (subs_altri)); the photon takes
+//     the energy fraction s/(1+s), the emitter keeps 1/(1+s)
+//   pair creation (pair == true): v = vbar of Eq. (again_pp) and 1 - v without cancellation
+// MIXED evaluates in FP32 and re-evaluates in FP64 the lanes whose energy fraction exceeds
+// 0.999 (photon: s > 999; pair: (1 + v)/2 > 0.999).
 template <bool MIXED>
-__device__ __forceinline__ double photon_s(const Tables& tb, double chi, double r, bool* ood)
+__device__ __forceinline__ void sample_coop(const Tables& tb, bool valid, bool pair, double chi,
+                                            double r, double& s_out, double& v_out,
+                                            double& omv_out, bool& ood)
 {
+    const double u = pair ? fabs(2.0 * r - 1.0) : r;   // 2r - 1 is exact
+    InvReq q;
+    if (!valid) q = photon_req(1.0, 0.25);
+    else if (pair) q = pair_req(chi, u);
+    else q = photon_req(chi, u);
+    ood = valid && q.ood;
+    const int patch = q.patch + (pair ? N_INV_CHI * N_R_SEG : 0);  // pair patches follow
+    bool need64 = true;
     if (MIXED) {
-        const float s = photon_s32(tb.phinv32, chi, r, ood);
-        if (s <= 999.0f) return (double)s;
-    }
-    return photon_s64(tb.phinv, chi, r, ood);
-}
-
-// pair energies for uniform r: electron and positron energies (Eq. (return_to_nrg))
-template <bool MIXED>
-__device__ __forceinline__ void pair_split(const Tables& tb, double chi, double r, double gamma,
-                                           double& ge, double& gp, bool* ood)
-{
-    const double rp = 2.0 * r - 1.0;  // exact
-    const double q = fabs(rp);
-    double v, omv;
-    bool done = false;
-    if (MIXED) {
-        const float y = pair_y32(tb.ppinv32, chi, q, ood);
-        const float eta0 = (float)(8.0 / (3.0 * chi));
-        const float den = y + eta0;
-        const float vf = sqrtf(y / den);
-        if (vf <= 0.998f) {
-            v = (double)vf;
-            omv = (double)((eta0 / den) / (1.0f + vf));
-            done = true;
+        const float f = coop_patch_eval<float>(tb.phinv32, patch, (float)q.Xr, (float)q.Xc);
+        const float uf = (float)u;
+        if (!pair) {
+            const float xbar = q.upper ? expf(f) : (f * uf) * (f * uf) * (f * uf);
+            const float s = 1.5f * (float)chi * xbar;
+            s_out = (double)s;
+            need64 = !(s <= 999.0f);
+        } else {
+            const float y = q.upper ? expf(f) : (f * uf) * (f * uf);
+            const float eta0 = (float)(8.0 / (3.0 * chi));
+            const float den = y + eta0;
+            const float v = sqrtf(y / den);
+            v_out = (double)v;
+            omv_out = (double)((eta0 / den) / (1.0f + v));
+            need64 = !(v <= 0.998f);
         }
+        need64 = need64 && valid;
+        if (__ballot(need64) == 0) return;
     }
-    if (!done) {
-        const double y = pair_y64(tb.ppinv, chi, q, ood);
+    const double f = coop_patch_eval<double>(tb.phinv, need64 ? patch : 0, q.Xr, q.Xc);
+    if (!need64) return;
+    if (!pair) {
+        const double w = f * u;
+        const double xbar = q.upper ? exp(f) : w * w * w;
+        s_out = 1.5 * chi * xbar;
+    } else {
+        const double w = f * u;
+        const double y = q.upper ? exp(f) : w * w;
         const double eta0 = 8.0 / (3.0 * chi);
         const double den = y + eta0;
-        v = sqrt(y / den);
-        omv = (eta0 / den) / (1.0 + v);
+        const double v = sqrt(y / den);
+        v_out = v;
+        omv_out = (eta0 / den) / (1.0 + v);
     }
+}
+
+// electron and positron energies from v (Eq. (return_to_nrg)): the electron takes (1 + v)/2
+// of the photon energy when r' = 2r - 1 >= 0, (1 - v)/2 otherwise
+__device__ __forceinline__ void pair_energies(double gamma, double r, double v, double omv,
+                                              double& ge, double& gp)
+{
     const double hi = 0.5 * gamma * (1.0 + v), lo = 0.5 * gamma * omv;
-    if (rp < 0.0) { ge = lo; gp = hi; } else { ge = hi; gp = lo; }
+    if (2.0 * r - 1.0 < 0.0) { ge = lo; gp = hi; } else { ge = hi; gp = lo; }
 }
 
 __device__ __forceinline__ double lepton_momentum_factor(double g, double pn, bool& clamped)
@@ -155,6 +186,30 @@ __device__ __forceinline__ double lepton_momentum_factor(double g, double pn, bo
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// streaming accesses of the particle arrays: read once per step, so they are marked
+// non-temporal and do not push the emitter queue out of the caches
+#ifndef SFQ_NT
+#define SFQ_NT 1
+#endif
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p)
+{
+#if SFQ_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v)
+{
+#if SFQ_NT
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
 
 // wave-aggregated reservation of `want` slots on a global counter; returns this lane's slot
 __device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* counter, bool want)
@@ -171,27 +226,52 @@ __device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* c
 }
 
 // =============================================================================================
-// The step kernel
+// The step: a streaming kernel over all tiles and an emitter kernel over its compacted queue
 // =============================================================================================
 constexpr int STEP_BLOCK = 256;
+// minimum waves per SIMD requested from the register allocator for the two step kernels
+#ifndef SFQ_BULK_WAVES
+#define SFQ_BULK_WAVES 4
+#endif
+#ifndef SFQ_EMIT_WAVES
+#define SFQ_EMIT_WAVES 3
+#endif
 
 __device__ __forceinline__ int find_tile(const uint32_t* off, int ntiles, int c)
 {
     int lo = 0, hi = ntiles - 1;
-    while (lo < hi) {  // last t with off[t] <= c
+    while (lo < hi) {  // last t with off[t] <= c (tiles without chunks are skipped)
         const int mid = (lo + hi + 1) >> 1;
         if ((int)off[mid] <= c) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
-template <bool MIXED>
-__global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
+__device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
+                                                   sfq_counters* global,
+                                                   const unsigned long long (&vals)[CNT_N])
+{
+#pragma unroll
+    for (int k = 0; k < CNT_N; ++k) {
+        unsigned long long v = vals[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+        if (lane_id() == 0 && v) atomicAdd(&s_cnt[k], v);
+    }
+    __syncthreads();
+    if (threadIdx.x < CNT_N && s_cnt[threadIdx.x])
+        atomicAdd(&global->processed + threadIdx.x, s_cnt[threadIdx.x]);
+}
+
+// Streaming pass: per alive particle gamma, chi (or the beyond-LCFA force update), the rate
+// from LDS-staged tables and the decision; emitters go to the block's queue slice through a
+// wave ballot + popcount prefix and one LDS atomic per wave.
+template <bool MIXED, bool BLCFA>
+__global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepArgs A)
 {
     using RT = typename std::conditional<MIXED, float, double>::type;
     __shared__ RT s_rad[RAD_SIZE];
     __shared__ RT s_pair[PAIR_SIZE];
-    __shared__ unsigned s_qn;
+    __shared__ unsigned s_qn[2];  // lepton, photon emitters of this block
     __shared__ unsigned long long s_cnt[CNT_N];
 
     const int tid = threadIdx.x;
@@ -199,7 +279,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
     const RT* g_pair = MIXED ? (const RT*)A.tb.pair32 : (const RT*)A.tb.pair;
     for (int k = tid; k < RAD_SIZE; k += STEP_BLOCK) s_rad[k] = g_rad[k];
     for (int k = tid; k < PAIR_SIZE; k += STEP_BLOCK) s_pair[k] = g_pair[k];
-    if (tid == 0) s_qn = 0;
+    if (tid < 2) s_qn[tid] = 0;
     if (tid < CNT_N) s_cnt[tid] = 0;
     __syncthreads();
 
@@ -207,33 +287,36 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
     const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
     const double dt = A.ph.dt;
 
-    // ---------------- phase 1: stream particles, rates, decisions, compaction ----------------
     for (int c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
         const int t = find_tile(A.chunk_off, A.ntiles, c);
         const sfq_tile T = A.tiles[t];
         const uint64_t start = (uint64_t)(c - (int)A.chunk_off[t]) * (uint64_t)A.chunk;
         const uint64_t end = min(start + (uint64_t)A.chunk, T.n);
         const bool photon = (T.species == SFQ_PHOTON);
-        const bool blcfa = A.blcfa && !photon;
+        const bool blcfa = BLCFA && !photon;
         for (uint64_t base = start; base < end; base += STEP_BLOCK) {
             const uint64_t i = base + tid;
             bool emit = false;
-            double chi = 0.0, gamma = 0.0, aux = 0.0;
-            if (i < end && (T.alive == nullptr || T.alive[i] != 0)) {
+            double chi = 0.0, gamma = 0.0, aux = 0.0, aux2 = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+            uint64_t quid = 0;
+            if (i < end && (T.alive == nullptr || ld_stream(&T.alive[i]) != 0)) {
                 ++c_proc;
                 bool ood = false;
                 double W;
                 if (!blcfa) {
-                    gamma_chi(photon, T.px[i], T.py[i], T.pz[i], T.ex[i], T.ey[i], T.ez[i],
-                              T.bx[i], T.by[i], T.bz[i], A.ph.lc_over_lr, gamma, chi);
+                    qx = ld_stream(&T.px[i]); qy = ld_stream(&T.py[i]); qz = ld_stream(&T.pz[i]);
+                    quid = ld_stream(&T.uid[i]);
+                    gamma_chi(photon, qx, qy, qz, ld_stream(&T.ex[i]), ld_stream(&T.ey[i]),
+                              ld_stream(&T.ez[i]), ld_stream(&T.bx[i]), ld_stream(&T.by[i]),
+                              ld_stream(&T.bz[i]), A.ph.lc_over_lr, gamma, chi);
                     W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
                                : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
                     if (A.decision == SFQ_OPTICAL_DEPTH) {
-                        const double tau = T.tau[i] - W * dt;
+                        const double tau = ld_stream(&T.tau[i]) - W * dt;
                         emit = tau < 0.0;
-                        if (!emit) T.tau[i] = tau;  // emitters get a fresh depth in phase 2
+                        if (!emit) st_stream(&T.tau[i], tau);  // emitters get a fresh depth later
                     } else {
-                        const Draw d = philox_draw(A.seed, T.uid[i], A.step, SFQ_P_LOCAL);
+                        const Draw d = philox_draw(A.seed, quid, A.step, SFQ_P_LOCAL);
                         emit = W * dt > uniform53(d.a);
                     }
                 } else {
@@ -241,6 +324,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
                     const uint64_t n = T.n;
                     const double ux = T.px[i], uy = T.py[i], uz = T.pz[i];
                     const double vx = T.px_prev[i], vy = T.py_prev[i], vz = T.pz_prev[i];
+                    qx = ux; qy = uy; qz = uz;
+                    quid = T.uid[i];
                     const double flx = (ux - vx) / dt, fly = (uy - vy) / dt, flz = (uz - vz) / dt;
                     const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
                     const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
@@ -267,9 +352,12 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
                         T.fperp[i] = Fx; T.fperp[n + i] = Fy; T.fperp[2 * n + i] = Fz;
                         T.dfperp[i] = ax; T.dfperp[n + i] = ay; T.dfperp[2 * n + i] = az;
                         const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
-                        const Draw d = philox_draw(A.seed, T.uid[i], A.step, SFQ_P_LOCAL);
+                        const Draw d = philox_draw(A.seed, quid, A.step, SFQ_P_LOCAL);
                         emit = W * dt > uniform53(d.a);
                         if (emit) {
+                            // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
+                            const double pu2 = ux * ux + uy * uy + uz * uz;
+                            aux2 = (pu2 - (g2 - 1.0)) / (sqrt(1.0 + pu2) + gamma);
                             if (flag) {
                                 const double tau_ratio = 2.0 * PI * sqrt(F2 / delta);
                                 const double arg = chi / (8.0 * gamma) * tau_ratio;
@@ -288,57 +376,101 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
                 if (T.rate_out) T.rate_out[i] = W;
                 c_ood += ood ? 1 : 0;
             }
-            // wave ballot + popcount prefix into the block's queue slice
+            // compaction: the whole iteration is one tile, hence one species
             const unsigned long long mask = __ballot(emit);
             if (mask) {
                 const int lane = lane_id();
                 const int leader = __ffsll((long long)mask) - 1;
                 unsigned off = 0;
-                if (lane == leader) off = atomicAdd(&s_qn, (unsigned)__popcll(mask));
+                if (lane == leader) off = atomicAdd(&s_qn[photon ? 1 : 0], (unsigned)__popcll(mask));
                 off = __shfl(off, leader);
                 if (emit) {
-                    const uint64_t slot =
-                        qbase + off + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+                    const unsigned rank = off + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+                    const uint64_t slot = photon ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
                     A.q_idx[slot] = (uint32_t)i;
                     A.q_tile[slot] = (uint32_t)t;
                     A.q_chi[slot] = chi;
                     A.q_gamma[slot] = gamma;
-                    if (blcfa) A.q_aux[slot] = aux;
+                    A.q_px[slot] = qx;
+                    A.q_py[slot] = qy;
+                    A.q_pz[slot] = qz;
+                    A.q_uid[slot] = quid;
+                    if (blcfa) {
+                        A.q_aux[slot] = aux;
+                        A.q_aux2[slot] = aux2;
+                    }
                 }
             }
         }
     }
     __syncthreads();
+    if (tid < 2) A.q_count[2 * blockIdx.x + tid] = s_qn[tid];
+    const unsigned long long vals[CNT_N] = {c_proc, 0, 0, 0, c_ood, 0, 0};
+    block_add_counters(s_cnt, A.counters, vals);
+}
 
-    // ---------------- phase 2: the block's emitters ----------------
-    const unsigned nq = s_qn;
-    unsigned long long c_emit = 0, c_conv = 0, c_rej = 0, c_clamp = 0, c_over = 0;
-    for (unsigned b0 = 0; b0 < nq; b0 += STEP_BLOCK) {
+// Emitter pass: block b samples the queue slice written by block b of the streaming pass, with
+// every lane busy: Philox draws, inverse-CDF tables, recoil and products (one global atomic per
+// wave and product buffer).
+template <bool MIXED, bool BLCFA>
+__global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepArgs A)
+{
+    __shared__ unsigned long long s_cnt[CNT_N];
+    __shared__ unsigned long long s_base[3];
+    const int tid = threadIdx.x;
+    if (tid < CNT_N) s_cnt[tid] = 0;
+    const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
+    const unsigned nl = A.q_count[2 * blockIdx.x], np = A.q_count[2 * blockIdx.x + 1];
+    // product slots of the whole block, reserved once: one photon per lepton emitter and one
+    // electron-positron pair per converting photon (beyond-LCFA rejections leave no product, so
+    // that mode reserves per wave instead)
+    if (tid == 0) {
+        s_base[0] = (!BLCFA && nl) ? atomicAdd(&A.prod_counts[0], (unsigned long long)nl) : 0;
+        s_base[1] = np ? atomicAdd(&A.prod_counts[1], (unsigned long long)np) : 0;
+        s_base[2] = np ? atomicAdd(&A.prod_counts[2], (unsigned long long)np) : 0;
+    }
+    __syncthreads();
+    const unsigned total = nl + np;
+    unsigned long long c_emit = 0, c_conv = 0, c_rej = 0, c_clamp = 0, c_over = 0, c_ood = 0;
+    for (unsigned b0 = 0; b0 < total; b0 += STEP_BLOCK) {
         const unsigned e = b0 + tid;
-        const bool valid = e < nq;
+        const bool valid = e < total;
         bool want_ph = false, want_pair = false;
         double pgx = 0, pgy = 0, pgz = 0, tau_a = 0, pbx = 0, pby = 0, pbz = 0, tau_b = 0;
         uint64_t uid_a = 0, uid_b = 0, parent = 0;
+        // gather this lane's emitter from the queue (contiguous reads)
+        const bool pair = valid && e >= nl;
+        const unsigned rank = pair ? e - nl : e;
+        const uint64_t slot = pair ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
+        uint64_t i = 0, uid = 0;
+        int t = 0;
+        double chi = 1.0, gamma = 1.0, r = 0.5, px = 0, py = 0, pz = 0;
+        Draw d1{0, 0}, d2{0, 0};
         if (valid) {
-            const uint64_t slot = qbase + e;
-            const uint64_t i = A.q_idx[slot];
-            const int t = (int)A.q_tile[slot];
-            const double chi = A.q_chi[slot], gamma = A.q_gamma[slot];
+            i = A.q_idx[slot];
+            t = (int)A.q_tile[slot];
+            chi = A.q_chi[slot];
+            gamma = A.q_gamma[slot];
+            px = A.q_px[slot];
+            py = A.q_py[slot];
+            pz = A.q_pz[slot];
+            uid = A.q_uid[slot];
+            d1 = philox_draw(A.seed, uid, A.step, SFQ_P_EMIT);
+            d2 = philox_draw(A.seed, uid, A.step, SFQ_P_CHILD);
+            r = uniform53(d1.a);
+        }
+        double s = 0.0, v = 0.0, omv = 1.0;
+        bool ood = false;
+        sample_coop<MIXED>(A.tb, valid, pair, chi, r, s, v, omv, ood);
+        if (valid) {
             const sfq_tile& T = A.tiles[t];
-            const uint64_t uid = T.uid[i];
             parent = uid;
-            const Draw d1 = philox_draw(A.seed, uid, A.step, SFQ_P_EMIT);
-            const Draw d2 = philox_draw(A.seed, uid, A.step, SFQ_P_CHILD);
-            const double r = uniform53(d1.a);
-            const double px = T.px[i], py = T.py[i], pz = T.pz[i];
             const double pn = sqrt(fma(px, px, fma(py, py, pz * pz)));
-            bool ood = false;
-            if (T.species != SFQ_PHOTON) {
-                const double s = photon_s<MIXED>(A.tb, chi, r, &ood);
+            if (!pair) {
                 const double gph = gamma * (s / (1.0 + s));
                 bool accept = true;
-                double gem;
-                if (A.blcfa) {
+                double gem = gamma / (1.0 + s);
+                if (BLCFA) {
                     const double limit = A.q_aux[slot];
                     if (!(gph > limit)) {  // Eq. (rej_cond)
                         const Draw dl = philox_draw(A.seed, uid, A.step, SFQ_P_LOCAL);
@@ -347,14 +479,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
                         const double lp_l = log_photon_pdf(A.tb.ka, A.tb.kb, limit, gamma, chi);
                         accept = log(r2) + lp_s <= lp_l;
                     }
-                    // recoil of the pushed momentum by the photon energy
-                    const double gpush = sqrt(1.0 + pn * pn);
-                    const double plx = 0.5 * (px + T.px_prev[i]), ply = 0.5 * (py + T.py_prev[i]),
-                                 plz = 0.5 * (pz + T.pz_prev[i]);
-                    const double dg = (pn * pn - (plx * plx + ply * ply + plz * plz)) / (gpush + gamma);
-                    gem = dg + gamma / (1.0 + s);
-                } else {
-                    gem = gamma / (1.0 + s);
+                    // the pushed momentum recoils by the photon energy
+                    gem += A.q_aux2[slot];
                 }
                 if (accept) {
                     bool cl;
@@ -374,7 +500,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
             } else {
                 const Draw d3 = philox_draw(A.seed, uid, A.step, SFQ_P_CHILD2);
                 double ge, gp;
-                pair_split<MIXED>(A.tb, chi, r, gamma, ge, gp, &ood);
+                pair_energies(gamma, r, v, omv, ge, gp);
                 bool c1, c2;
                 const double fe = lepton_momentum_factor(ge, pn, c1);
                 const double fp = lepton_momentum_factor(gp, pn, c2);
@@ -391,9 +517,9 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
             }
             c_ood += ood ? 1 : 0;
         }
-        // products: one global atomic per wave and buffer
         {
-            const unsigned long long k = wave_reserve(&A.prod_counts[0], want_ph);
+            const unsigned long long k =
+                BLCFA ? wave_reserve(&A.prod_counts[0], want_ph) : s_base[0] + rank;
             if (want_ph) {
                 const sfq_products& P = A.prod[0];
                 if (k < P.capacity) {
@@ -404,41 +530,27 @@ __global__ __launch_bounds__(STEP_BLOCK) void step_kernel(StepArgs A)
                 }
             }
         }
-        {
-            const unsigned long long ke = wave_reserve(&A.prod_counts[1], want_pair);
-            const unsigned long long kp = wave_reserve(&A.prod_counts[2], want_pair);
-            if (want_pair) {
-                const sfq_products& E = A.prod[1];
-                if (ke < E.capacity) {
-                    E.px[ke] = pgx; E.py[ke] = pgy; E.pz[ke] = pgz; E.tau[ke] = tau_a;
-                    E.uid[ke] = uid_a; E.parent[ke] = parent;
-                } else {
-                    ++c_over;
-                }
-                const sfq_products& P = A.prod[2];
-                if (kp < P.capacity) {
-                    P.px[kp] = pbx; P.py[kp] = pby; P.pz[kp] = pbz; P.tau[kp] = tau_b;
-                    P.uid[kp] = uid_b; P.parent[kp] = parent;
-                } else {
-                    ++c_over;
-                }
+        if (want_pair) {
+            const unsigned long long ke = s_base[1] + rank, kp = s_base[2] + rank;
+            const sfq_products& E = A.prod[1];
+            if (ke < E.capacity) {
+                E.px[ke] = pgx; E.py[ke] = pgy; E.pz[ke] = pgz; E.tau[ke] = tau_a;
+                E.uid[ke] = uid_a; E.parent[ke] = parent;
+            } else {
+                ++c_over;
+            }
+            const sfq_products& P = A.prod[2];
+            if (kp < P.capacity) {
+                P.px[kp] = pbx; P.py[kp] = pby; P.pz[kp] = pbz; P.tau[kp] = tau_b;
+                P.uid[kp] = uid_b; P.parent[kp] = parent;
+            } else {
+                ++c_over;
             }
         }
     }
-
-    // ---------------- counters: block reduction, one global atomic per counter ----------------
-    const unsigned long long vals[CNT_N] = {c_proc, c_emit, c_conv, c_rej, c_ood, c_clamp, c_over};
-#pragma unroll
-    for (int k = 0; k < CNT_N; ++k) {
-        unsigned long long v = vals[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-        if (lane_id() == 0 && v) atomicAdd(&s_cnt[k], v);
-    }
     __syncthreads();
-    if (tid < CNT_N && s_cnt[tid]) {
-        unsigned long long* dst = &A.counters->processed + tid;
-        atomicAdd(dst, s_cnt[tid]);
-    }
+    const unsigned long long vals[CNT_N] = {0, c_emit, c_conv, c_rej, c_ood, c_clamp, c_over};
+    block_add_counters(s_cnt, A.counters, vals);
 }
 
 // =============================================================================================
@@ -481,19 +593,26 @@ __global__ __launch_bounds__(256) void chi_kernel(int photon, size_t n, const do
     }
 }
 
+// uniform loops: every lane of a wave takes part in the cooperative table evaluation
 template <bool MIXED>
 __global__ __launch_bounds__(256) void sample_photon_kernel(Tables tb, size_t n,
                                                             const double* gamma,
                                                             const double* chi, const double* r,
                                                             double* gph, double* gem)
 {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        bool ood = false;
-        const double s = photon_s<MIXED>(tb, chi[i], r[i], &ood);
-        const double g = gamma[i];
-        gph[i] = g * (s / (1.0 + s));
-        if (gem) gem[i] = g / (1.0 + s);
+    for (size_t base = blockIdx.x * (size_t)blockDim.x; base < n;
+         base += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        double s = 0, v, omv;
+        bool ood;
+        sample_coop<MIXED>(tb, valid, false, valid ? chi[i] : 1.0, valid ? r[i] : 0.5, s, v, omv,
+                           ood);
+        if (valid) {
+            const double g = gamma[i];
+            gph[i] = g * (s / (1.0 + s));
+            if (gem) gem[i] = g / (1.0 + s);
+        }
     }
 }
 
@@ -502,13 +621,20 @@ __global__ __launch_bounds__(256) void sample_pair_kernel(Tables tb, size_t n, c
                                                           const double* chi, const double* r,
                                                           double* ge, double* gp)
 {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        bool ood = false;
-        double a, b;
-        pair_split<MIXED>(tb, chi[i], r[i], gamma[i], a, b, &ood);
-        ge[i] = a;
-        if (gp) gp[i] = b;
+    for (size_t base = blockIdx.x * (size_t)blockDim.x; base < n;
+         base += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        double s, v = 0, omv = 1;
+        bool ood;
+        const double ri = valid ? r[i] : 0.5;
+        sample_coop<MIXED>(tb, valid, true, valid ? chi[i] : 1.0, ri, s, v, omv, ood);
+        if (valid) {
+            double a, b;
+            pair_energies(gamma[i], ri, v, omv, a, b);
+            ge[i] = a;
+            if (gp) gp[i] = b;
+        }
     }
 }
 
@@ -564,10 +690,11 @@ struct sfq_ctx {
     std::mutex mu;
     void* d_queue = nullptr;
     size_t queue_entries = 0;
+    int queue_blocks = 0;
     Staging staging[N_STAGING];
     int next_staging = 0;
     // launch shape of the step kernel (tunable)
-    int blocks_per_cu = 4;
+    int blocks_per_cu = 8;
     int chunk = 2048;
 };
 
@@ -614,7 +741,7 @@ static sfq_status load_tables(sfq_ctx* h, const char* path_in)
     }
     size_t pos = 0;
     auto need = [&](size_t k) { return pos + k <= buf.size(); };
-    if (!need(8 + 16) || memcmp(buf.data(), "SFQTAB02", 8) != 0)
+    if (!need(8 + 16) || memcmp(buf.data(), "SFQTAB03", 8) != 0)
         return fail(h, SFQ_E_TABLES, "bad table file magic in " + path);
     pos = 8;
     uint32_t version, narr;
@@ -624,15 +751,16 @@ static sfq_status load_tables(sfq_ctx* h, const char* path_in)
     memcpy(&hash, &buf[pos + 8], 8);
     pos += 16;
     (void)hash;
-    const int expect_geom[18] = {RATE_DEG, CHI_OCT_LO, CHI_OCT_HI, N_CHI_SEG, PAIR_OCT_LO,
+    const int expect_geom[22] = {RATE_DEG, CHI_OCT_LO, CHI_OCT_HI, N_CHI_SEG, PAIR_OCT_LO,
                                  N_PAIR_SEG, KA_DEG, N_KA, KB_DEG, KB_OCT_LO, KB_OCT_HI, INV_NC,
-                                 INV_NR, N_LO_SEG, T_OCT_LO, T_OCT_HI, N_HI_SEG, N_R_SEG};
-    if (version != 2 || narr != 6 || !need(sizeof(expect_geom)))
+                                 INV_NR, N_LO_SEG, T_OCT_LO, T_OCT_HI, N_HI_SEG, N_R_SEG, SUB,
+                                 INV_CHI_OCT_LO, N_INV_CHI, N_PAIR_INV_CHI};
+    if (version != 3 || narr != 6 || !need(sizeof(expect_geom)))
         return fail(h, SFQ_E_TABLES, "unsupported table file version in " + path);
-    int geom[18];
+    int geom[22];
     memcpy(geom, &buf[pos], sizeof(geom));
     pos += sizeof(geom);
-    for (int k = 0; k < 18; ++k)
+    for (int k = 0; k < 22; ++k)
         if (geom[k] != expect_geom[k])
             return fail(h, SFQ_E_TABLES, "table geometry mismatch (field " + std::to_string(k) +
                                              ") in " + path + ": rebuild the tables");
@@ -877,6 +1005,27 @@ sfq_status sfq_init_optical_depth(sfq_handle h, size_t n, const uint64_t* uid, u
     return SFQ_OK;
 }
 
+sfq_status sfq_set_launch(sfq_handle h, int blocks_per_cu, int chunk)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_set_launch: NULL handle");
+    if (blocks_per_cu < 1 || blocks_per_cu > 64 || chunk < STEP_BLOCK || chunk > (1 << 22) ||
+        chunk % STEP_BLOCK != 0)
+        return fail(h, SFQ_E_ARG, "sfq_set_launch: blocks_per_cu in [1, 64], chunk a multiple of "
+                                  "256 in [256, 2^22]");
+    std::lock_guard<std::mutex> lock(h->mu);
+    h->blocks_per_cu = blocks_per_cu;
+    h->chunk = chunk;
+    return SFQ_OK;
+}
+
+sfq_status sfq_get_launch(sfq_handle h, int* blocks_per_cu, int* chunk)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_get_launch: NULL handle");
+    if (blocks_per_cu) *blocks_per_cu = h->blocks_per_cu;
+    if (chunk) *chunk = h->chunk;
+    return SFQ_OK;
+}
+
 sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
 {
     if (!h) return fail(h, SFQ_E_STATE, "sfq_step: NULL handle");
@@ -927,19 +1076,20 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     const uint64_t chunks_per_block = (uint64_t)((nchunks + grid - 1) / grid);
     const uint64_t cap_per_block = chunks_per_block * (uint64_t)h->chunk;
     const uint64_t entries = cap_per_block * (uint64_t)grid;
-    if (entries > h->queue_entries) {
+    if (entries > h->queue_entries || grid > h->queue_blocks) {
         if (h->d_queue) {
             HIP_TRY(h, hipDeviceSynchronize());
             HIP_TRY(h, hipFree(h->d_queue));
             h->d_queue = nullptr;
             h->queue_entries = 0;
         }
-        const size_t bytes = entries * (4 + 4 + 8 + 8 + 8);
+        const size_t bytes = entries * (4 + 4 + 8 * 9) + 8 * (size_t)grid + 256;
         if (hipMalloc(&h->d_queue, bytes) != hipSuccess) {
             h->d_queue = nullptr;
             return fail(h, SFQ_E_NOMEM, "sfq_step: cannot allocate the emitter queue");
         }
         h->queue_entries = entries;
+        h->queue_blocks = grid;
     }
     // descriptors through a ring of pinned staging buffers
     Staging& S = h->staging[h->next_staging];
@@ -977,19 +1127,40 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     const size_t E = h->queue_entries;
     A.q_chi = (double*)q;
     A.q_gamma = (double*)(q + 8 * E);
-    A.q_aux = (double*)(q + 16 * E);
-    A.q_idx = (uint32_t*)(q + 24 * E);
-    A.q_tile = (uint32_t*)(q + 28 * E);
+    A.q_px = (double*)(q + 16 * E);
+    A.q_py = (double*)(q + 24 * E);
+    A.q_pz = (double*)(q + 32 * E);
+    A.q_uid = (uint64_t*)(q + 40 * E);
+    A.q_aux = (double*)(q + 48 * E);
+    A.q_aux2 = (double*)(q + 56 * E);
+    A.q_idx = (uint32_t*)(q + 64 * E);
+    A.q_tile = (uint32_t*)(q + 68 * E);
+    A.q_count = (uint32_t*)(q + 72 * E);
     A.q_cap_per_block = cap_per_block;
     A.prod[0] = desc->photons;
     A.prod[1] = desc->electrons;
     A.prod[2] = desc->positrons;
     A.prod_counts = desc->product_counts;
     A.counters = desc->counters;
-    if (h->precision == SFQ_MIXED)
-        hipLaunchKernelGGL(step_kernel<true>, dim3(grid), dim3(STEP_BLOCK), 0, (hipStream_t)stream, A);
-    else
-        hipLaunchKernelGGL(step_kernel<false>, dim3(grid), dim3(STEP_BLOCK), 0, (hipStream_t)stream, A);
+    const hipStream_t st = (hipStream_t)stream;
+    const dim3 g(grid), b(STEP_BLOCK);
+    if (h->precision == SFQ_MIXED) {
+        if (h->blcfa) {
+            hipLaunchKernelGGL((bulk_kernel<true, true>), g, b, 0, st, A);
+            hipLaunchKernelGGL((emit_kernel<true, true>), g, b, 0, st, A);
+        } else {
+            hipLaunchKernelGGL((bulk_kernel<true, false>), g, b, 0, st, A);
+            hipLaunchKernelGGL((emit_kernel<true, false>), g, b, 0, st, A);
+        }
+    } else {
+        if (h->blcfa) {
+            hipLaunchKernelGGL((bulk_kernel<false, true>), g, b, 0, st, A);
+            hipLaunchKernelGGL((emit_kernel<false, true>), g, b, 0, st, A);
+        } else {
+            hipLaunchKernelGGL((bulk_kernel<false, false>), g, b, 0, st, A);
+            hipLaunchKernelGGL((emit_kernel<false, false>), g, b, 0, st, A);
+        }
+    }
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
     (void)total;

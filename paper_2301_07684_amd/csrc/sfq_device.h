@@ -27,10 +27,14 @@ constexpr int PAIR_OCT_LO = -7;
 constexpr int N_PAIR_SEG = CHI_OCT_HI - PAIR_OCT_LO;
 constexpr int KA_DEG = 20, N_KA = 4;
 constexpr int KB_DEG = 18, KB_OCT_LO = 1, KB_OCT_HI = 18;
-constexpr int INV_NC = 16, INV_NR = 12;
-constexpr int N_LO_SEG = 4;
+constexpr int INV_NC = 8, INV_NR = 8;
+constexpr int SUB = 4;                  // quarter-octave segments of the inverse tables
+constexpr int INV_CHI_OCT_LO = -10;
+constexpr int N_INV_CHI = 1 + SUB * (CHI_OCT_HI - INV_CHI_OCT_LO);
+constexpr int N_PAIR_INV_CHI = SUB * (CHI_OCT_HI - PAIR_OCT_LO);
+constexpr int N_LO_SEG = 8;
 constexpr int T_OCT_LO = -1, T_OCT_HI = 6;
-constexpr int N_HI_SEG = 2 * (T_OCT_HI - T_OCT_LO);
+constexpr int N_HI_SEG = SUB * (T_OCT_HI - T_OCT_LO);
 constexpr int N_R_SEG = N_LO_SEG + N_HI_SEG;
 constexpr int INV_PATCH = INV_NR * INV_NC;
 
@@ -38,8 +42,8 @@ constexpr int RAD_SIZE = N_CHI_SEG * RATE_DEG;
 constexpr int PAIR_SIZE = N_PAIR_SEG * RATE_DEG;
 constexpr int KA_SIZE = N_KA * 2 * KA_DEG;
 constexpr int KB_SIZE = (KB_OCT_HI - KB_OCT_LO) * 2 * KB_DEG;
-constexpr int PHINV_SIZE = N_CHI_SEG * N_R_SEG * INV_PATCH;
-constexpr int PPINV_SIZE = N_PAIR_SEG * N_R_SEG * INV_PATCH;
+constexpr int PHINV_SIZE = N_INV_CHI * N_R_SEG * INV_PATCH;
+constexpr int PPINV_SIZE = N_PAIR_INV_CHI * N_R_SEG * INV_PATCH;
 
 // ---------------------------------------------------------------------------------------------
 // Physical constants (CODATA 2018) and derived numbers.
@@ -91,11 +95,11 @@ __device__ __forceinline__ double uniform53(uint64_t a)
 __device__ __forceinline__ double optical_depth(uint64_t a) { return -log(1.0 - uniform53(a)); }
 
 // ---------------------------------------------------------------------------------------------
-// chi and gamma.  With n = p/|p|, E_par = n.E, E_perp = E - E_par n, f = E_perp + n x B and
-// d = gamma - |p| = m^2/(gamma + |p|) (m = 1 leptons, 0 photons):
-//   (gamma E + p x B)^2 - (p.E)^2 = | |p| f + d E_perp |^2 + m^2 E_par^2,
-// a sum of squares, so chi has no catastrophic cancellation for nearly co-propagating
-// particles (where gamma E + p x B -> E/(gamma+|p|)).
+// chi and gamma.  With E_par = p.E/|p|, E_perp = E - (p.E/|p|^2) p and d = gamma - |p| =
+// m^2/(gamma + |p|) (m = 1 leptons, 0 photons):
+//   (gamma E + p x B)^2 - (p.E)^2 = | |p| E_perp + p x B + d E_perp |^2 + m^2 E_par^2,
+// a sum of squares with gamma - |p| never formed by subtraction, so co-propagating particles
+// (where gamma E + p x B -> E/(gamma+|p|)) keep their accuracy.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ void gamma_chi(bool photon, double px, double py, double pz, double ex,
                                           double ey, double ez, double bx, double by, double bz,
@@ -108,18 +112,22 @@ __device__ __forceinline__ void gamma_chi(bool photon, double px, double py, dou
         chi = photon ? 0.0 : lc_over_lr * sqrt(fma(ex, ex, fma(ey, ey, ez * ez)));
         return;
     }
-    // correctly rounded quotients: an axis-aligned momentum gives an exact unit vector, so the
-    // exactly co-propagating case (E_perp + n x B = 0) cancels exactly
-    const double nx = px / pn, ny = py / pn, nz = pz / pn;
-    const double epar = fma(nx, ex, fma(ny, ey, nz * ez));
-    const double eqx = fma(-epar, nx, ex), eqy = fma(-epar, ny, ey), eqz = fma(-epar, nz, ez);
-    const double fx = eqx + (ny * bz - nz * by);
-    const double fy = eqy + (nz * bx - nx * bz);
-    const double fz = eqz + (nx * by - ny * bx);
-    const double d = photon ? 0.0 : 1.0 / (gamma + pn);
-    const double vx = fma(pn, fx, d * eqx), vy = fma(pn, fy, d * eqy), vz = fma(pn, fz, d * eqz);
+    const double pe = fma(px, ex, fma(py, ey, pz * ez));
+    const double q = pe / p2;                       // E_par^2 = q pe, E_perp = E - q p
+    const double eqx = fma(-q, px, ex), eqy = fma(-q, py, ey), eqz = fma(-q, pz, ez);
+    double ux, uy, uz;
+    {
+        // |p| E_perp + p x B, each product rounded on its own: for an exactly co-propagating
+        // particle (|p| == p_x) the two terms cancel exactly
+#pragma clang fp contract(off)
+        ux = pn * eqx + (py * bz - pz * by);
+        uy = pn * eqy + (pz * bx - px * bz);
+        uz = pn * eqz + (px * by - py * bx);
+    }
+    const double d = photon ? 0.0 : 1.0 / (gamma + pn);  // gamma - |p| without cancellation
+    const double vx = fma(d, eqx, ux), vy = fma(d, eqy, uy), vz = fma(d, eqz, uz);
     double rad = fma(vx, vx, fma(vy, vy, vz * vz));
-    if (!photon) rad = fma(epar, epar, rad);
+    if (!photon) rad = fma(q, pe, rad);
     chi = lc_over_lr * sqrt(rad);
 }
 
@@ -230,116 +238,138 @@ __device__ __forceinline__ T wtilde_pair(const P* pair, T chi, bool* ood)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Inverse-CDF tables.  r-segment from r in (0, 1): lower region r <= 1/2 in N_LO_SEG equal
-// segments (local variable linear in r); upper region r > 1/2 by half-octaves of
-// t = -ln(1 - r) (t in [2^e, 2^e sqrt2) or [2^e sqrt2, 2^{e+1})).
+// Inverse-CDF tables: patches of 8 x 8 Chebyshev coefficients, row-major [r index][chi index],
+// on quarter-octave segments of chi and of t = -ln(1 - r).  The local variable of a
+// quarter-octave [2^o q_k, 2^o q_{k+1}) (q_k = 2^{k/4}) is X = (2m - q_k - q_{k+1})/(q_{k+1} - q_k)
+// with m the mantissa in [1, 2): the segment is the exponent plus three comparisons.
+// Lower region r <= 1/2 (or |r'| <= 1/2): N_LO_SEG equal segments, linear in r.
 // ---------------------------------------------------------------------------------------------
-struct RSeg {
-    int seg;
-    double X;
-    bool upper;
+__device__ __forceinline__ double subq(int k)
+{
+    return k == 0 ? 1.0 : k == 1 ? 1.189207115002721 : k == 2 ? 1.4142135623730951
+         : k == 3 ? 1.681792830507429 : 2.0;
+}
+
+// octave o, quarter k and local variable X of x > 0
+__device__ __forceinline__ void quarter_locate(double x, int& o, int& k, double& X)
+{
+    int e;
+    const double m = 2.0 * frexp(x, &e);   // x = m 2^(e-1), m in [1, 2)
+    o = e - 1;
+    k = (m >= 1.189207115002721 ? 1 : 0) + (m >= 1.4142135623730951 ? 1 : 0) +
+        (m >= 1.681792830507429 ? 1 : 0);
+    const double a = subq(k), b = subq(k + 1);
+    X = (2.0 * m - a - b) / (b - a);
+}
+
+// a request for one inverse-table evaluation: patch offset (same in the FP64 and FP32 tables)
+// and local variables along r and chi
+struct InvReq {
+    int patch;     // index of the patch in its table
+    double Xr, Xc;
+    bool upper;    // upper region: the table holds a logarithm
+    bool ood;      // chi beyond the table
 };
 
-__device__ __forceinline__ RSeg r_segment(double r)
+__device__ __forceinline__ void r_locate(double r, int& seg, double& X, bool& upper)
 {
-    RSeg s;
     if (r <= 0.5) {
         int k = (int)(r * (2 * N_LO_SEG));
         k = k > N_LO_SEG - 1 ? N_LO_SEG - 1 : (k < 0 ? 0 : k);
-        s.seg = k;
-        s.X = fma(r, 4.0 * N_LO_SEG, -(2.0 * k + 1.0));
-        s.upper = false;
-        return s;
+        seg = k;
+        X = fma(r, 4.0 * N_LO_SEG, -(2.0 * k + 1.0));
+        upper = false;
+        return;
     }
     const double t = -log(1.0 - r);  // 1 - r is exact for r >= 1/2
-    int e;
-    const double m2 = frexp(t, &e);   // t = m2 2^e, m2 in [0.5, 1)
-    int o = e - 1;
-    const double m = 2.0 * m2;        // t = m 2^o, m in [1, 2)
-    const int half = m >= SQRT2 ? 1 : 0;
-    if (o < T_OCT_LO) o = T_OCT_LO;   // not reached: t >= ln 2
-    if (o > T_OCT_HI - 1) o = T_OCT_HI - 1;
-    const double a = ldexp(half ? SQRT2 : 1.0, o);
-    const double b = ldexp(half ? 2.0 : SQRT2, o);
-    s.seg = N_LO_SEG + 2 * (o - T_OCT_LO) + half;
-    s.X = (2.0 * t - a - b) / (b - a);
-    s.upper = true;
-    return s;
+    int o, k;
+    quarter_locate(t, o, k, X);
+    if (o < T_OCT_LO) { o = T_OCT_LO; k = 0; X = -1.0; }          // not reached: t >= ln 2
+    if (o > T_OCT_HI - 1) { o = T_OCT_HI - 1; k = SUB - 1; X = 1.0; }
+    seg = N_LO_SEG + SUB * (o - T_OCT_LO) + k;
+    upper = true;
 }
 
-// 2D patch evaluation: inner Clenshaw along chi for every r row, then along r (App. B,
-// Eqs. (back_rec_2d), (start_cl_2)).
-template <typename T, typename P>
-__device__ __forceinline__ T patch_eval(const P* c, T Xc, T Xr)
+// photon emission (inverse of Eq. (again)); u = r
+__device__ __forceinline__ InvReq photon_req(double chi, double r)
 {
-    T d[INV_NR];
+    InvReq q;
+    int cs;
+    q.ood = false;
+    if (chi < 0x1p-10) {
+        cs = 0;
+        q.Xc = fma(chi, 0x1p11, -1.0);
+    } else {
+        int o, k;
+        quarter_locate(chi, o, k, q.Xc);
+        cs = 1 + SUB * (o - INV_CHI_OCT_LO) + k;
+        if (cs > N_INV_CHI - 1) { cs = N_INV_CHI - 1; q.Xc = 1.0; q.ood = true; }
+    }
+    int rs;
+    r_locate(r, rs, q.Xr, q.upper);
+    q.patch = cs * N_R_SEG + rs;
+    return q;
+}
+
+// pair creation (inverse of Eq. (again_pp)); u = |r'| = |2r - 1|
+__device__ __forceinline__ InvReq pair_req(double chi, double u)
+{
+    InvReq q;
+    int o, k;
+    quarter_locate(chi, o, k, q.Xc);
+    int cs = SUB * (o - PAIR_OCT_LO) + k;
+    q.ood = false;
+    if (!(cs >= 0)) { cs = 0; q.Xc = -1.0; }
+    if (cs > N_PAIR_INV_CHI - 1) { cs = N_PAIR_INV_CHI - 1; q.Xc = 1.0; q.ood = true; }
+    int rs;
+    r_locate(u, rs, q.Xr, q.upper);
+    q.patch = cs * N_R_SEG + rs;
+    return q;
+}
+
+// Chebyshev polynomial T_m(x) for 0 <= m < 8 by the three-term recurrence
+template <typename T>
+__device__ __forceinline__ T cheb_T(int m, T x)
+{
+    T t0 = T(1), t1 = x, out = m == 0 ? t0 : t1;
 #pragma unroll
-    for (int i = 0; i < INV_NR; ++i) d[i] = clenshaw<INV_NC>(c + i * INV_NC, Xc);
-    return clenshaw<INV_NR>(d, Xr);
-}
-
-// Photon sample: returns s = 3 chi wbar^3 / 2 (Eq. (subs_altri)); the photon takes the energy
-// fraction s/(1+s) and the emitter keeps 1/(1+s).
-__device__ __forceinline__ double photon_s64(const double* tab, double chi, double r, bool* ood)
-{
-    int cs;
-    double Xc;
-    if (chi_segment(chi, cs, Xc)) *ood = true;
-    const RSeg rs = r_segment(r);
-    const double f = patch_eval(tab + (cs * N_R_SEG + rs.seg) * INV_PATCH, Xc, rs.X);
-    double xbar;
-    if (rs.upper) {
-        xbar = exp(f);               // the table holds ln(wbar^3)
-    } else {
-        const double w = f * r;      // the table holds wbar / r
-        xbar = w * w * w;
+    for (int k = 2; k < 8; ++k) {
+        const T t2 = fma(x + x, t1, -t0);
+        out = (m == k) ? t2 : out;
+        t0 = t1;
+        t1 = t2;
     }
-    return 1.5 * chi * xbar;
+    return out;
 }
 
-__device__ __forceinline__ float photon_s32(const float* tab, double chi_d, double r, bool* ood)
+// Cooperative evaluation of one patch per lane (all 64 lanes of the wave must call it).
+// In round b the 8 lanes of group g evaluate the patch of lane 8b + g: lane (g, m) loads
+// column m (8 coefficients, one per r index; the group reads 64 contiguous bytes per row),
+// runs Clenshaw's recurrence along r, weights by T_m(Xc) and the group sums over m.  Each
+// load instruction touches 8 rows of 8 different patches instead of 64 scattered lines.
+template <typename T>
+__device__ __forceinline__ T coop_patch_eval(const T* table, int patch, T Xr, T Xc)
 {
-    const float chi = (float)chi_d;
-    int cs;
-    float Xc;
-    if (chi_segment(chi, cs, Xc)) *ood = true;
-    const RSeg rs = r_segment(r);     // segment selection and t in double (exact 1 - r)
-    const float f = patch_eval(tab + (cs * N_R_SEG + rs.seg) * INV_PATCH, Xc, (float)rs.X);
-    float xbar;
-    if (rs.upper) {
-        xbar = expf(f);
-    } else {
-        const float w = f * (float)r;
-        xbar = w * w * w;
+    const int L = __lane_id();
+    const int g = L >> 3, m = L & 7;
+    T result = T(0);
+#pragma unroll 1
+    for (int b = 0; b < 8; ++b) {
+        const int src = (b << 3) | g;
+        const int pt = __shfl(patch, src);
+        const T xr = __shfl(Xr, src), xc = __shfl(Xc, src);
+        const T* c = table + (size_t)pt * INV_PATCH + m;
+        T col[INV_NR];
+#pragma unroll
+        for (int i = 0; i < INV_NR; ++i) col[i] = c[i * INV_NC];
+        T v = clenshaw<INV_NR>(col, xr) * cheb_T(m, xc);
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        const T got = __shfl(v, (L & 7) << 3);
+        if ((L >> 3) == b) result = got;
     }
-    return 1.5f * chi * xbar;
-}
-
-// Pair sample: returns y = eta_v - eta0 for |r'| = |2r - 1| (the table variable), from which
-// v^2 = y/(y + eta0) and 1 - v^2 = eta0/(y + eta0).
-__device__ __forceinline__ double pair_y64(const double* tab, double chi, double q, bool* ood)
-{
-    int cs;
-    double Xc;
-    if (pair_segment(chi, cs, Xc)) *ood = true;
-    const RSeg rs = r_segment(q);
-    const double f = patch_eval(tab + (cs * N_R_SEG + rs.seg) * INV_PATCH, Xc, rs.X);
-    if (rs.upper) return exp(f);     // ln y
-    const double u = f * q;          // sqrt(y) / q
-    return u * u;
-}
-
-__device__ __forceinline__ float pair_y32(const float* tab, double chi_d, double q, bool* ood)
-{
-    const float chi = (float)chi_d;
-    int cs;
-    float Xc;
-    if (pair_segment(chi, cs, Xc)) *ood = true;
-    const RSeg rs = r_segment(q);
-    const float f = patch_eval(tab + (cs * N_R_SEG + rs.seg) * INV_PATCH, Xc, (float)rs.X);
-    if (rs.upper) return expf(f);
-    const float u = f * (float)q;
-    return u * u;
+    return result;
 }
 
 // ---------------------------------------------------------------------------------------------

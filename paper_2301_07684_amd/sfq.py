@@ -29,7 +29,7 @@ STATUS = {0: "SFQ_OK", 1: "SFQ_E_ARG", 2: "SFQ_E_STATE", 3: "SFQ_E_NOMEM", 4: "S
 # every symbol declared in include/sfq.h
 EXPORTS = ("sfq_create", "sfq_destroy", "sfq_last_error", "sfq_units", "sfq_chi", "sfq_rates",
            "sfq_sample_photon", "sfq_sample_pair", "sfq_philox", "sfq_init_optical_depth",
-           "sfq_step")
+           "sfq_step", "sfq_set_launch", "sfq_get_launch")
 
 
 class Config(C.Structure):
@@ -100,6 +100,10 @@ def load(path: str = LIB_PATH):
     L.sfq_init_optical_depth.argtypes = [vp, sz, dp, u64, dp, vp]
     L.sfq_step.restype = st
     L.sfq_step.argtypes = [vp, C.POINTER(StepDesc), vp]
+    L.sfq_set_launch.restype = st
+    L.sfq_set_launch.argtypes = [vp, C.c_int, C.c_int]
+    L.sfq_get_launch.restype = st
+    L.sfq_get_launch.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     _lib = L
     return L
 
@@ -165,6 +169,14 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+    def set_launch(self, blocks_per_cu: int, chunk: int):
+        self._check(self._L.sfq_set_launch(self._h, blocks_per_cu, chunk))
+
+    def get_launch(self):
+        a, b = C.c_int(), C.c_int()
+        self._check(self._L.sfq_get_launch(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     # ---- batched calls ------------------------------------------------------------------------
     def chi(self, species, p, E, B, stream=None):

@@ -51,16 +51,24 @@ N_KA = 4
 KB_DEG = 18            # x in [2^1, 2^18): one segment per octave
 KB_OCT_LO, KB_OCT_HI = 1, 18
 
-# 2D inverse-CDF tables: [chi segment][r segment][N_R][N_C]
-INV_NC = 16            # Chebyshev terms along chi (per chi segment)
-INV_NR = 12            # Chebyshev terms along the r variable (per r segment)
-N_LO_SEG = 4           # lower region r (or q) in (0, 1/2]: 4 equal segments in r
-T_OCT_LO, T_OCT_HI = -1, 6   # upper region t in [2^-1, 2^6): two segments per octave of t
-N_HI_SEG = 2 * (T_OCT_HI - T_OCT_LO)
+# 2D inverse-CDF tables: [chi segment][r segment][N_R][N_C] patches of 8 x 8 coefficients
+# (512 bytes, one patch = four 128-byte cache lines).  Segments are quarter-octaves of chi and
+# of t = -ln(1 - r): the segment index is the floating-point exponent plus three comparisons
+# of the mantissa with 2^{1/4}, 2^{1/2}, 2^{3/4}.
+INV_NC = 8             # Chebyshev terms along chi (per chi segment)
+INV_NR = 8             # Chebyshev terms along the r variable (per r segment)
+SUB = 4                # sub-segments per octave
+SUBQ = (1.0, 1.189207115002721, 1.4142135623730951, 1.681792830507429, 2.0)  # 2^{k/4}
+INV_CHI_OCT_LO = -10   # photon inverse: chi < 2^-10 is the linear segment 0
+N_INV_CHI = 1 + SUB * (CHI_OCT_HI - INV_CHI_OCT_LO)
+N_PAIR_INV_CHI = SUB * (CHI_OCT_HI - PAIR_OCT_LO)   # pair inverse: quarter-octaves from 2^-7
+N_LO_SEG = 8           # lower region r (or q) in (0, 1/2]: 8 equal segments in r
+T_OCT_LO, T_OCT_HI = -1, 6   # upper region t in [2^-1, 2^6): quarter-octaves of t
+N_HI_SEG = SUB * (T_OCT_HI - T_OCT_LO)
 N_R_SEG = N_LO_SEG + N_HI_SEG
 T_MAX = 2.0 ** T_OCT_HI
 
-MAGIC = b"SFQTAB02"
+MAGIC = b"SFQTAB03"
 
 
 # ------------------------------------------------------------------------------------------------
@@ -398,22 +406,52 @@ def photon_xbar(bt, chi, rvar, region):
     return wb ** 3 - rvar
 
 
+def _quarter(o, k):
+    """[2^o 2^{k/4}, 2^o 2^{(k+1)/4})"""
+    return math.ldexp(SUBQ[k], o), math.ldexp(SUBQ[k + 1], o)
+
+
 def _r_segment_bounds(seg):
-    """Lower segments: r in [seg/8, (seg+1)/8); upper: t in [2^o, 2^o sqrt2) or [2^o sqrt2, 2^{o+1})."""
+    """Lower segments: r in [seg/16, (seg+1)/16); upper: quarter-octaves of t = -ln(1-r)."""
     if seg < N_LO_SEG:
         return "L", 0.5 * seg / N_LO_SEG, 0.5 * (seg + 1) / N_LO_SEG
     h = seg - N_LO_SEG
-    o = T_OCT_LO + h // 2
-    a = 2.0 ** o * (math.sqrt(2.0) if h % 2 else 1.0)
-    b = 2.0 ** (o + 1) if h % 2 else 2.0 ** o * math.sqrt(2.0)
+    a, b = _quarter(T_OCT_LO + h // SUB, h % SUB)
     return "U", a, b
+
+
+def _inv_chi_segment_bounds(seg):
+    if seg == 0:
+        return 0.0, 2.0 ** INV_CHI_OCT_LO
+    h = seg - 1
+    return _quarter(INV_CHI_OCT_LO + h // SUB, h % SUB)
+
+
+def _pair_inv_chi_segment_bounds(seg):
+    return _quarter(PAIR_OCT_LO + seg // SUB, seg % SUB)
+
+
+def _sub_of_mantissa(m):
+    """index of the quarter-octave of a mantissa m in [1, 2)"""
+    return ((m >= SUBQ[1]).astype(int) + (m >= SUBQ[2]).astype(int) + (m >= SUBQ[3]).astype(int))
+
+
+def _quarter_locate(x):
+    """(octave, sub-segment, X) of positive x, X the local variable of the quarter-octave."""
+    m2, e = np.frexp(x)
+    o = e - 1
+    m = 2.0 * m2
+    k = _sub_of_mantissa(m)
+    a = np.array(SUBQ)[k]
+    b = np.array(SUBQ)[k + 1]
+    return o, k, (2.0 * m - a - b) / (b - a)
 
 
 def build_photon_inverse(bt, verbose=False):
     ndc, ndr = cheb_nodes(INV_NC), cheb_nodes(INV_NR)
-    tab = np.zeros((N_CHI_SEG, N_R_SEG, INV_NR, INV_NC))
-    for cs in range(N_CHI_SEG):
-        ca, cb = _chi_segment_bounds(cs)
+    tab = np.zeros((N_INV_CHI, N_R_SEG, INV_NR, INV_NC))
+    for cs in range(N_INV_CHI):
+        ca, cb = _inv_chi_segment_bounds(cs)
         chis = 0.5 * (ca + cb) + 0.5 * (cb - ca) * ndc
         vals = np.zeros((N_R_SEG, INV_NR, INV_NC))
         for j, chi in enumerate(chis):
@@ -429,35 +467,34 @@ def build_photon_inverse(bt, verbose=False):
         c = cheb_coeffs_from_values(vals, axis=1)
         tab[cs] = cheb_coeffs_from_values(c, axis=2)
         if verbose:
-            print(f"  photon inverse: chi segment {cs + 1}/{N_CHI_SEG}", flush=True)
+            print(f"  photon inverse: chi segment {cs + 1}/{N_INV_CHI}", flush=True)
     return tab
 
 
 def chi_segment(chi):
+    """segment and local variable of chi in the photon inverse table"""
     chi = np.asarray(chi, dtype=np.float64)
-    seg = np.where(chi < 2.0 ** CHI_OCT_LO, 0,
-                   np.floor(np.log2(np.maximum(chi, 1e-300))).astype(int) - CHI_OCT_LO + 1)
-    seg = np.clip(seg, 0, N_CHI_SEG - 1)
-    a = np.where(seg == 0, 0.0, 2.0 ** (seg - 1 + CHI_OCT_LO))
-    b = np.where(seg == 0, 2.0 ** CHI_OCT_LO, 2 * a)
-    return seg, to_unit(chi, a, b)
+    low = chi < 2.0 ** INV_CHI_OCT_LO
+    o, k, X = _quarter_locate(np.where(low, 1.0, chi))
+    seg = 1 + SUB * (o - INV_CHI_OCT_LO) + k
+    over = seg > N_INV_CHI - 1
+    seg = np.where(over, N_INV_CHI - 1, seg)
+    X = np.where(over, 1.0, X)
+    Xl = chi * 2.0 ** (1 - INV_CHI_OCT_LO) - 1.0
+    return np.where(low, 0, seg), np.where(low, Xl, X)
 
 
 def r_segment(r):
     """(segment, local variable X, is_upper, t) for an array of r in (0, 1)."""
     r = np.asarray(r, dtype=np.float64)
     upper = r > 0.5
-    t = -np.log1p(-r)
+    t = -np.log1p(-np.where(upper, r, 0.0))
     segl = np.minimum((r * 2 * N_LO_SEG).astype(int), N_LO_SEG - 1)
     al = 0.5 * segl / N_LO_SEG
     Xl = to_unit(r, al, al + 0.5 / N_LO_SEG)
-    tt = np.where(upper, t, 1.0)
-    o = np.clip(np.floor(np.log2(tt)).astype(int), T_OCT_LO, T_OCT_HI - 1)
-    half = (tt >= 2.0 ** o * math.sqrt(2.0)).astype(int)
-    au = 2.0 ** o * np.where(half == 1, math.sqrt(2.0), 1.0)
-    bu = np.where(half == 1, 2.0 ** (o + 1), 2.0 ** o * math.sqrt(2.0))
-    Xu = to_unit(tt, au, bu)
-    seg = np.where(upper, N_LO_SEG + 2 * (o - T_OCT_LO) + half, segl)
+    o, k, Xu = _quarter_locate(np.where(upper, t, 1.0))
+    o = np.clip(o, T_OCT_LO, T_OCT_HI - 1)
+    seg = np.where(upper, N_LO_SEG + SUB * (o - T_OCT_LO) + k, segl)
     X = np.where(upper, Xu, Xl)
     return seg, X, upper, t
 
@@ -545,17 +582,11 @@ class PairSpectrum:
         return u
 
 
-def _pair_chi_segment_bounds(seg):
-    """Pair tables cover chi in [2^PAIR_OCT_LO, 2^CHI_OCT_HI) by octaves."""
-    a = 2.0 ** (PAIR_OCT_LO + seg)
-    return a, 2 * a
-
-
 def build_pair_inverse(bt, verbose=False):
     ndc, ndr = cheb_nodes(INV_NC), cheb_nodes(INV_NR)
-    tab = np.zeros((N_PAIR_SEG, N_R_SEG, INV_NR, INV_NC))
-    for cs in range(N_PAIR_SEG):
-        ca, cb = _pair_chi_segment_bounds(cs)
+    tab = np.zeros((N_PAIR_INV_CHI, N_R_SEG, INV_NR, INV_NC))
+    for cs in range(N_PAIR_INV_CHI):
+        ca, cb = _pair_inv_chi_segment_bounds(cs)
         chis = 0.5 * (ca + cb) + 0.5 * (cb - ca) * ndc
         vals = np.zeros((N_R_SEG, INV_NR, INV_NC))
         for j, chi in enumerate(chis):
@@ -570,15 +601,18 @@ def build_pair_inverse(bt, verbose=False):
         c = cheb_coeffs_from_values(vals, axis=1)
         tab[cs] = cheb_coeffs_from_values(c, axis=2)
         if verbose:
-            print(f"  pair inverse: chi segment {cs + 1}/{N_PAIR_SEG}", flush=True)
+            print(f"  pair inverse: chi segment {cs + 1}/{N_PAIR_INV_CHI}", flush=True)
     return tab
 
 
 def pair_chi_segment(chi):
     chi = np.asarray(chi, dtype=np.float64)
-    o = np.clip(np.floor(np.log2(chi)).astype(int), PAIR_OCT_LO, CHI_OCT_HI - 1)
-    a = 2.0 ** o
-    return o - PAIR_OCT_LO, to_unit(chi, a, 2 * a)
+    o, k, X = _quarter_locate(chi)
+    seg = SUB * (o - PAIR_OCT_LO) + k
+    lo, hi = seg < 0, seg > N_PAIR_INV_CHI - 1
+    seg = np.clip(seg, 0, N_PAIR_INV_CHI - 1)
+    X = np.where(lo, -1.0, np.where(hi, 1.0, X))
+    return seg, X
 
 
 def eval_pair_y(tab, chi, r):
@@ -597,7 +631,8 @@ def eval_pair_y(tab, chi, r):
 # ------------------------------------------------------------------------------------------------
 GEOMETRY = ("RATE_DEG", "CHI_OCT_LO", "CHI_OCT_HI", "N_CHI_SEG", "PAIR_OCT_LO", "N_PAIR_SEG",
             "KA_DEG", "N_KA", "KB_DEG", "KB_OCT_LO", "KB_OCT_HI", "INV_NC", "INV_NR", "N_LO_SEG",
-            "T_OCT_LO", "T_OCT_HI", "N_HI_SEG", "N_R_SEG")
+            "T_OCT_LO", "T_OCT_HI", "N_HI_SEG", "N_R_SEG", "SUB", "INV_CHI_OCT_LO", "N_INV_CHI",
+            "N_PAIR_INV_CHI")
 
 
 def source_hash() -> int:
@@ -608,7 +643,7 @@ def source_hash() -> int:
 def _photon_segment(cs):
     bt = BesselTables()
     ndc, ndr = cheb_nodes(INV_NC), cheb_nodes(INV_NR)
-    ca, cb = _chi_segment_bounds(cs)
+    ca, cb = _inv_chi_segment_bounds(cs)
     chis = 0.5 * (ca + cb) + 0.5 * (cb - ca) * ndc
     vals = np.zeros((N_R_SEG, INV_NR, INV_NC))
     for j, chi in enumerate(chis):
@@ -627,7 +662,7 @@ def _photon_segment(cs):
 def _pair_segment(cs):
     bt = BesselTables()
     ndc, ndr = cheb_nodes(INV_NC), cheb_nodes(INV_NR)
-    ca, cb = _pair_chi_segment_bounds(cs)
+    ca, cb = _pair_inv_chi_segment_bounds(cs)
     chis = 0.5 * (ca + cb) + 0.5 * (cb - ca) * ndc
     vals = np.zeros((N_R_SEG, INV_NR, INV_NC))
     for j, chi in enumerate(chis):
@@ -650,9 +685,9 @@ def _check_segment(args):
     rng = np.random.default_rng(seed)
     worst = 0.0
     if kind == "photon":
-        ca, cb = _chi_segment_bounds(cs)
+        ca, cb = _inv_chi_segment_bounds(cs)
     else:
-        ca, cb = _pair_chi_segment_bounds(cs)
+        ca, cb = _pair_inv_chi_segment_bounds(cs)
     for chi in rng.uniform(ca, cb, 3):
         chi = max(chi, 1e-12)
         omr = np.exp(rng.uniform(np.log(2.0 ** -52), np.log(0.5), 40))
@@ -680,13 +715,13 @@ def build_all(jobs=8, verbose=True):
     bt = BesselTables()
     rad, pair = build_rate_tables()
     with ProcessPoolExecutor(max_workers=jobs) as ex:
-        ph = list(ex.map(_photon_segment, range(N_CHI_SEG)))
-        pp = list(ex.map(_pair_segment, range(N_PAIR_SEG)))
+        ph = list(ex.map(_photon_segment, range(N_INV_CHI)))
+        pp = list(ex.map(_pair_segment, range(N_PAIR_INV_CHI)))
         phinv, ppinv = np.stack(ph), np.stack(pp)
         if verbose:
             print(f"tables fitted in {time.time() - t0:.1f} s", flush=True)
-        checks = [("photon", cs, phinv, 100 + cs) for cs in range(N_CHI_SEG)]
-        checks += [("pair", cs, ppinv, 200 + cs) for cs in range(N_PAIR_SEG)]
+        checks = [("photon", cs, phinv, 100 + cs) for cs in range(N_INV_CHI)]
+        checks += [("pair", cs, ppinv, 1000 + cs) for cs in range(N_PAIR_INV_CHI)]
         errs = list(ex.map(_check_segment, checks))
     chi = np.concatenate([np.geomspace(1e-9, 2.0 ** CHI_OCT_HI * 0.999, 500),
                           np.linspace(0, 2.0 ** CHI_OCT_LO, 60)[1:]])
@@ -709,7 +744,7 @@ def write_blob(path, tables):
     g = globals()
     with open(path + ".tmp", "wb") as f:
         f.write(MAGIC)
-        f.write(struct.pack("<IIQ", 2, len(ARRAY_ORDER), source_hash()))
+        f.write(struct.pack("<IIQ", 3, len(ARRAY_ORDER), source_hash()))
         f.write(struct.pack("<%di" % len(GEOMETRY), *[int(g[k]) for k in GEOMETRY]))
         for name in ARRAY_ORDER:
             a = np.ascontiguousarray(tables[name], dtype="<f8")
@@ -737,7 +772,8 @@ def main(argv=None):
     import json
 
     argv = sys.argv[1:] if argv is None else argv
-    out = argv[0] if argv else default_path()
+    paths = [a for a in argv if not a.startswith("--")]
+    out = paths[0] if paths else default_path()
     force = "--force" in argv
     if not force and read_blob_hash(out) == source_hash():
         print(f"tables up to date: {out}")

@@ -75,8 +75,13 @@ def test_table_geometry_matches_the_generator():
 
     dev = _device_constants()
     for k in ("RATE_DEG", "CHI_OCT_LO", "CHI_OCT_HI", "PAIR_OCT_LO", "KA_DEG", "N_KA", "KB_DEG",
-              "KB_OCT_LO", "KB_OCT_HI", "INV_NC", "INV_NR", "N_LO_SEG", "T_OCT_LO", "T_OCT_HI"):
+              "KB_OCT_LO", "KB_OCT_HI", "INV_NC", "INV_NR", "N_LO_SEG", "T_OCT_LO", "T_OCT_HI",
+              "SUB", "INV_CHI_OCT_LO"):
         assert int(dev[k]) == getattr(T, k), k
+    # the quarter-octave boundaries 2^{k/4} are the same double literals on both sides
+    src = open(DEVICE_H).read()
+    for q in T.SUBQ[1:4]:
+        assert repr(q) in src
 
 
 def test_physical_constants_agree_between_sides():

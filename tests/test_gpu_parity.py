@@ -239,9 +239,15 @@ def check_step_against_oracle(w, tile, tau0, prods, h, *, seed, step, tol_rate, 
     chi = tile.chi_out.cpu().numpy()
     rate = tile.rate_out.cpu().numpy()
     assert np.max(rel(chi, oc)) < (TOL_CHI if tol_rate == TOL_RATE else tol_rate)
-    pos = W > 0
-    assert np.array_equal(rate == 0, W == 0)
-    assert np.max(rel(rate[pos], W[pos])) < tol_rate
+    if tol_rate == TOL_RATE:
+        pos = W > 0
+        assert np.array_equal(rate == 0, W == 0)
+        assert np.max(rel(rate[pos], W[pos])) < tol_rate
+    else:
+        # FP32: where e^{-8/(3chi)} of the pair rate underflows, an absolute tolerance applies
+        tiny = np.finfo(np.float32).tiny * h.lr_over_lc
+        ok = (np.abs(rate - W) <= tol_rate * np.abs(W)) | (np.abs(rate - W) <= tiny)
+        assert np.all(ok)
     # decisions: the oracle's emitter set, outside the band
     thr = W * h.dt
     emit_or = tau0 - thr < 0
