@@ -102,6 +102,8 @@ def lib():
             "orc_result_size": (l, []), "orc_product_size": (l, []),
             "orc_decide_batch": (None, [C.POINTER(StepCfg), l, _dp, _dp, C.POINTER(u64),
                                         C.POINTER(C.c_int32)]),
+            "orc_step_blcfa_batch": (None, [C.POINTER(StepCfg), l] + [_dp] * 8 +
+                                     [C.POINTER(C.c_uint8), C.POINTER(u64), C.POINTER(Result)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -346,6 +348,35 @@ def blcfa_update(p_prev, p_push, dt, tau_c, Fperp, dF, just_created):
                                   C.byref(g), C.byref(c), C.byref(de), C.byref(fs))
     return (bool(flag), g.value, c.value, de.value, bool(fs.value), list(F), list(D),
             bool(jc.value))
+
+
+def step_blcfa(p_prev, p_push, fperp, dfperp, just_created, uid, *, dt, lc_over_lr, seed, step):
+    """One beyond-LCFA step (local decision) for n leptons.  p_prev, p_push: (3, n); fperp,
+    dfperp: (3n,) component-major state (updated copies are returned); just_created: (n,) uint8.
+    Returns a dict like step() plus the new state and a `rejected` flag array."""
+    pp, pu = _f64(p_prev), _f64(p_push)
+    n = pu.shape[1]
+    F, D = _f64(fperp).copy(), _f64(dfperp).copy()
+    jc = np.ascontiguousarray(np.asarray(just_created, dtype=np.uint8)).copy()
+    uid = np.ascontiguousarray(np.asarray(uid, dtype=np.uint64))
+    cfg = StepCfg(dt=float(dt), lc_over_lr=float(lc_over_lr), seed=int(seed), step=int(step),
+                  decision=LOCAL, bw_fast=0, pad=0)
+    out = (Result * max(n, 1))()
+    cols = [np.ascontiguousarray(a[k]) for a in (pp, pu) for k in range(3)]
+    lib().orc_step_blcfa_batch(C.byref(cfg), n, *[_ptr(c) for c in cols], _ptr(F), _ptr(D),
+                               jc.ctypes.data_as(C.POINTER(C.c_uint8)),
+                               uid.ctypes.data_as(C.POINTER(C.c_uint64)), out)
+    d = {nm: np.array([getattr(r, nm) for r in out[:n]]) for nm in
+         ("chi", "gamma", "rate", "emitted", "clamped", "r_energy", "xi_or_v")}
+    d["rejected"] = d["clamped"] < 0
+    d["clamped"] = np.maximum(d["clamped"], 0)
+    d["p"] = np.stack([np.array([r.px for r in out[:n]]), np.array([r.py for r in out[:n]]),
+                       np.array([r.pz for r in out[:n]])])
+    d["products"] = [dict(species=q.species, px=q.px, py=q.py, pz=q.pz, tau=q.tau, uid=q.uid,
+                          parent=q.parent, gamma=q.gamma)
+                     for r in out[:n] for q in r.prod if q.valid]
+    d["fperp"], d["dfperp"], d["just_created"] = F, D, jc
+    return d
 
 
 def blcfa_threshold(Fperp, delta, gamma, chi):

@@ -820,6 +820,73 @@ int orc_blcfa_accept(double gbar, double limit, double gamma, double chi, double
            orc_photon_pdf_energy(limit, gamma, chi);
 }
 
+/* One beyond-LCFA step of a lepton (paper Sec. 5 with the local decision of Sec. 2).
+ * p_prev = p^{(n-1/2)}, p_push = p_L^{(n+1/2)}; the state (Fperp, dF, just_created) is updated.
+ * Readings where the paper is silent: a particle that was just created stores its force and
+ * cannot emit; when the condition below Eq. (condit) fails, a particle with chi > zeta emits by
+ * the LCFA (threshold 0) and one with chi <= zeta does not emit; the energy of the emitted photon
+ * is taken from the pushed momentum, gamma' = sqrt(1 + p_push^2) - gamma_photon, and the
+ * emitter keeps its direction.  Draws: P_LOCAL a decides, P_EMIT a samples the energy, P_LOCAL b
+ * accepts (Eq. (rej_cond)); the photon product takes P_CHILD (a: optical depth, b: uid). */
+void orc_step_blcfa_one(const orc_step_cfg* cfg, const double p_prev[3], const double p_push[3],
+                        double Fperp[3], double dF[3], int* just_created, uint64_t uid,
+                        orc_result* res)
+{
+    memset(res, 0, sizeof(*res));
+    res->px = p_push[0]; res->py = p_push[1]; res->pz = p_push[2];
+    res->alive_out = 1;
+    double gamma, chi, delta;
+    int first;
+    const double tau_c = cfg->lc_over_lr;
+    int flag = orc_blcfa_update(p_prev, p_push, cfg->dt, tau_c, Fperp, dF, just_created, &gamma,
+                                &chi, &delta, &first);
+    double W = orc_rate_compton(gamma, chi, 1.0 / cfg->lc_over_lr);
+    res->chi = chi;
+    res->gamma = gamma;
+    res->rate = W;
+    if (first) return;
+    uint64_t la, lb;
+    orc_draw(cfg->seed, uid, cfg->step, ORC_P_LOCAL, &la, &lb);
+    if (!(W * cfg->dt > orc_uniform(la))) return;
+    double limit;
+    const double zeta = 2.220446049250313e-16;
+    if (flag) {
+        limit = orc_blcfa_threshold(Fperp, delta, gamma, chi);
+        if (!(limit < 0.75 * gamma)) return;
+    } else if (chi > zeta) {
+        limit = 0.0;
+    } else {
+        return;
+    }
+    uint64_t e_a, e_b, c_a, c_b;
+    orc_draw(cfg->seed, uid, cfg->step, ORC_P_EMIT, &e_a, &e_b);
+    orc_draw(cfg->seed, uid, cfg->step, ORC_P_CHILD, &c_a, &c_b);
+    double r = orc_uniform(e_a);
+    res->r_energy = r;
+    double gph, gem, wb;
+    orc_sample_photon(gamma, chi, r, &gph, &gem, &wb);
+    res->xi_or_v = gph / gamma;
+    if (!orc_blcfa_accept(gph, limit, gamma, chi, orc_uniform(lb))) {
+        res->clamped = -1; /* marks a rejection */
+        return;
+    }
+    res->emitted = 1;
+    double pn = sqrt(p_push[0] * p_push[0] + p_push[1] * p_push[1] + p_push[2] * p_push[2]);
+    double g_after = sqrt(1.0 + pn * pn) - gph;
+    double pnew[3], pph[3];
+    res->clamped = collinear(p_push, pn, g_after, 0, pnew);
+    collinear(p_push, pn, gph, 1, pph);
+    res->px = pnew[0]; res->py = pnew[1]; res->pz = pnew[2];
+    orc_product* q = &res->prod[0];
+    q->px = pph[0]; q->py = pph[1]; q->pz = pph[2];
+    q->tau = orc_optical_depth(c_a);
+    q->uid = c_b;
+    q->parent = uid;
+    q->gamma = gph;
+    q->species = ORC_PHOTON;
+    q->valid = 1;
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* Batched entry points (OpenMP over particles) used by the Python wrapper.                   */
 /* ------------------------------------------------------------------------------------------ */
@@ -895,6 +962,24 @@ void orc_step_batch(const orc_step_cfg* cfg, int species, long n, const double* 
         double p[3] = {px[i], py[i], pz[i]}, E[3] = {ex[i], ey[i], ez[i]},
                B[3] = {bx[i], by[i], bz[i]};
         orc_step_one(cfg, species, p, E, B, tau[i], uid[i], alive ? alive[i] : 1, &out[i]);
+    }
+}
+
+/* state arrays component-major: Fperp[k*n + i] */
+void orc_step_blcfa_batch(const orc_step_cfg* cfg, long n, const double* pxp, const double* pyp,
+                          const double* pzp, const double* px, const double* py, const double* pz,
+                          double* Fperp, double* dF, uint8_t* just_created, const uint64_t* uid,
+                          orc_result* out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < n; ++i) {
+        double pp[3] = {pxp[i], pyp[i], pzp[i]}, pu[3] = {px[i], py[i], pz[i]};
+        double F[3] = {Fperp[i], Fperp[n + i], Fperp[2 * n + i]};
+        double D[3] = {dF[i], dF[n + i], dF[2 * n + i]};
+        int jc = just_created[i];
+        orc_step_blcfa_one(cfg, pp, pu, F, D, &jc, uid[i], &out[i]);
+        for (int k = 0; k < 3; ++k) { Fperp[k * n + i] = F[k]; dF[k * n + i] = D[k]; }
+        just_created[i] = (uint8_t)jc;
     }
 }
 

@@ -1,0 +1,136 @@
+"""Parity of the beyond-LCFA step (paper Sec. 5, local decision) with the CPU oracle.
+
+Each step is checked on its own: the oracle receives exactly the GPU's inputs of that step
+(p^{(n-1/2)}, the pushed p_L^{(n+1/2)} and the stored F_perp / Delta F state), so the comparison
+does not depend on earlier steps.  Tolerances: chi, rates and the stored force state <= 1e-12
+relative; decisions identical outside a 1e-9 band; acceptance decisions identical; emitter
+energies after recoil <= 1e-9 relative to the pushed energy.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2301_07684_amd import inputs, sfq
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def kicks(n, step, scale):
+    """Deterministic random momentum kicks with a new direction every step: a rapidly varying
+    transverse force, so that the beyond-LCFA threshold is a sizeable part of the spectrum."""
+    u = [inputs.uniforms(7, 100 + 3 * step + k, np.arange(n)) for k in range(3)]
+    ct = 2 * u[0] - 1
+    ph = 2 * math.pi * u[1]
+    st = np.sqrt(1 - ct * ct)
+    mag = scale * (0.2 + u[2])
+    return np.stack([st * np.cos(ph), st * np.sin(ph), ct]) * mag
+
+
+def test_blcfa_steps_match_oracle(dev):
+    n = 2048
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.LOCAL, blcfa=True)
+    idx = np.arange(n)
+    gamma = 10.0 ** (3 + 1.5 * inputs.uniforms(8, 0, idx))
+    p = np.stack([gamma, np.zeros(n), np.zeros(n)])
+    uid = inputs.ids(8, idx)
+    # force of order chi / (tau_C gamma) for chi ~ 1 .. 30, times dt
+    scale = 10.0 / (h.lc_over_lr * gamma) * h.dt
+    fperp = torch.zeros(3 * n, dtype=torch.float64, device=dev)
+    dfperp = torch.zeros_like(fperp)
+    jc = torch.ones(n, dtype=torch.uint8, device=dev)
+    tot_emit = tot_rej = 0
+    for step in range(1, 6):
+        p_prev = p
+        p_push = p_prev + kicks(n, step, scale)
+        state_before = (fperp.cpu().numpy().copy(), dfperp.cpu().numpy().copy(),
+                        jc.cpu().numpy().copy())
+        pu = [T(p_push[k], dev) for k in range(3)]
+        tile = sfq.TileArrays(sfq.ELECTRON, *pu, uid=T(uid, dev),
+                              px_prev=T(p_prev[0], dev), py_prev=T(p_prev[1], dev),
+                              pz_prev=T(p_prev[2], dev), fperp=fperp, dfperp=dfperp,
+                              just_created=jc,
+                              chi_out=torch.zeros(n, dtype=torch.float64, device=dev),
+                              rate_out=torch.zeros(n, dtype=torch.float64, device=dev))
+        prods = sfq.ProductBuffers.empty(n, 1, dev)
+        cnt = sfq.Counters(dev)
+        h.step([tile], seed=4, step=step, products=prods, counters=cnt)
+        torch.cuda.synchronize()
+        ref = O.step_blcfa(p_prev, p_push, state_before[0], state_before[1], state_before[2],
+                           uid.view(np.uint64), dt=h.dt, lc_over_lr=h.lc_over_lr, seed=4,
+                           step=step)
+        chi, rate = tile.chi_out.cpu().numpy(), tile.rate_out.cpu().numpy()
+        assert np.allclose(chi, ref["chi"], rtol=1e-12, atol=0)
+        assert np.allclose(rate, ref["rate"], rtol=1e-12, atol=0)
+        # the component of F_perp along p_L cancels to ~0: compare against the force scale
+        fscale = np.max(np.abs(ref["fperp"]))
+        assert np.allclose(fperp.cpu().numpy(), ref["fperp"], rtol=1e-12, atol=1e-12 * fscale)
+        assert np.allclose(dfperp.cpu().numpy(), ref["dfperp"], rtol=1e-9, atol=1e-12 * fscale)
+        assert np.array_equal(jc.cpu().numpy(), ref["just_created"])
+        c = cnt.as_dict()
+        if step == 1:  # newly created particles store their force and never emit
+            assert c["emitted"] == 0 and c["blcfa_rejected"] == 0
+            assert np.all(dfperp.cpu().numpy() == 0)
+        # decisions outside the band
+        r1 = np.array([O.uniform(O.draw(4, int(u), step, O.P_LOCAL)[0]) for u in uid.view(np.uint64)])
+        band = np.abs(ref["rate"] * h.dt - r1) <= 1e-9 * r1
+        k = prods.host_counts()[0]
+        parents = prods.photons.parent[:k].cpu().numpy().view(np.uint64)
+        emit_gpu = np.isin(uid.view(np.uint64), parents)
+        assert not np.any((emit_gpu != ref["emitted"].astype(bool)) & ~band)
+        assert abs(c["blcfa_rejected"] - int(ref["rejected"].sum())) <= int(band.sum())
+        # recoil of the emitters and their photons
+        pg = np.stack([t.cpu().numpy() for t in (tile.px, tile.py, tile.pz)])
+        em = ref["emitted"].astype(bool) & emit_gpu
+        g_push = np.sqrt(1 + np.sum(p_push ** 2, axis=0))
+        g_gpu = np.sqrt(1 + np.sum(pg ** 2, axis=0))
+        g_ref = np.sqrt(1 + np.sum(ref["p"] ** 2, axis=0))
+        assert np.all(np.abs(g_gpu[em] - g_ref[em]) <= 1e-9 * g_push[em])
+        assert np.array_equal(pg[:, ~emit_gpu], p_push[:, ~emit_gpu])  # others untouched
+        tot_emit += c["emitted"]
+        tot_rej += c["blcfa_rejected"]
+        p = pg
+    assert tot_emit > 100 and tot_rej > 10  # the acceptance test was exercised
+
+
+def test_blcfa_handle_requires_local_decision():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    with pytest.raises(sfq.SFQError):
+        sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.OPTICAL_DEPTH,
+                   blcfa=True)
+
+
+def test_local_decision_photons_match_oracle(dev):
+    n = 4096
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.LOCAL)
+    w = inputs.plane_wave(1 << 20, idx=np.arange(n) * 64, species=sfq.PHOTON)
+    t = sfq.TileArrays(sfq.PHOTON, *[T(w["p"][k], dev) for k in range(3)],
+                       *[T(w["E"][k], dev) for k in range(3)], *[T(w["B"][k], dev) for k in range(3)],
+                       uid=T(w["uid"], dev), alive=torch.ones(n, dtype=torch.uint8, device=dev),
+                       rate_out=torch.zeros(n, dtype=torch.float64, device=dev))
+    prods = sfq.ProductBuffers.empty(1, n, dev)
+    cnt = sfq.Counters(dev)
+    h.step([t], seed=6, step=2, products=prods, counters=cnt)
+    torch.cuda.synchronize()
+    ref = O.step(O.PHOTON, w["p"], w["E"], w["B"], np.zeros(n), w["uid"].view(np.uint64),
+                 dt=h.dt, lc_over_lr=h.lc_over_lr, seed=6, step=2, decision=O.LOCAL)
+    uid = w["uid"].view(np.uint64)
+    r1 = np.array([O.uniform(O.draw(6, int(u), 2, O.P_LOCAL)[0]) for u in uid])
+    band = np.abs(ref["rate"] * h.dt - r1) <= 1e-9 * r1
+    alive = t.alive.cpu().numpy()
+    assert not np.any(((alive == 0) != ref["emitted"].astype(bool)) & ~band)
+    assert cnt.as_dict()["converted"] > 0
