@@ -208,6 +208,33 @@ sfq_status sfq_get_launch(sfq_handle h, int* blocks_per_cu, int* chunk);
  * same result. */
 sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream);
 
+/* ------------------------------------------------------------------------------------------ */
+/* Plans: a fixed set of tiles stepped repeatedly.  The descriptors are uploaded once, the plan
+ * owns its emitter queue, and the Philox step index lives in device memory and advances by one
+ * after every step, so a plan launch enqueues kernels only (no host copies, no allocation) and
+ * a sequence of launches can be captured in a HIP graph and replayed.                          */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct sfq_plan_t* sfq_plan;
+
+/* Creates a plan for the tiles and buffers of `desc` (pointers are kept, the tile array is
+ * copied; desc->step is the first step index).  zero_product_counts = 1 zeroes
+ * desc->product_counts at the start of every step (with a kernel).  The handle's launch shape
+ * (sfq_set_launch) at creation time is used.  The plan must be destroyed before the handle. */
+sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_product_counts,
+                           sfq_plan* out);
+void sfq_plan_destroy(sfq_plan p);
+
+/* One step of the plan on `stream` (same results as sfq_step with the current step index). */
+sfq_status sfq_plan_launch(sfq_plan p, void* stream);
+
+/* Sets the device step index of the plan (enqueued on `stream`). */
+sfq_status sfq_plan_set_step(sfq_plan p, uint64_t step, void* stream);
+
+/* Captures `steps` consecutive plan steps into a HIP graph (replacing a previous one) and
+ * replays it: one graph launch advances the plan by `steps` steps. */
+sfq_status sfq_plan_capture(sfq_plan p, int steps);
+sfq_status sfq_plan_replay(sfq_plan p, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,106 @@
+"""Launch-shape autotuner for the step kernels.
+
+For a given set of tiles it times each candidate launch shape (blocks per compute unit x chunk
+length, see sfq_set_launch) on the real data with a plan, keeps the fastest and caches the
+choice in a JSON file keyed by the device, the precision and a coarse signature of the workload
+(total particles and number of tiles rounded to powers of two, species mix).  The particle
+state is snapshotted before tuning and restored afterwards, so a tuned run gives the same
+results as an untuned one (results never depend on the launch shape).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Dict, List, Sequence, Tuple
+
+import torch
+
+from . import sfq
+
+DEFAULT_CANDIDATES = [(2, 4096), (4, 2048), (4, 4096), (8, 1024), (8, 2048), (16, 1024)]
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "autotune.json")
+
+_STATE_FIELDS = ("px", "py", "pz", "tau", "alive", "fperp", "dfperp", "just_created")
+
+
+def signature(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays]) -> str:
+    total = sum(t.n for t in tiles)
+    species = sorted({int(t.species) for t in tiles})
+    props = torch.cuda.get_device_properties(handle.device)
+    b = lambda v: 2 ** max(0, math.ceil(math.log2(max(v, 1))))
+    return (f"{props.name}|cu{props.multi_processor_count}|prec{handle.precision}|"
+            f"blcfa{int(handle.blcfa)}|n{b(total)}|t{b(len(tiles))}|s{'-'.join(map(str, species))}")
+
+
+def _snapshot(tiles):
+    return [{f: getattr(t, f).clone() for f in _STATE_FIELDS if getattr(t, f) is not None}
+            for t in tiles]
+
+
+def _restore(tiles, snap):
+    for t, s in zip(tiles, snap):
+        for f, v in s.items():
+            getattr(t, f).copy_(v)
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, List[int]]:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(cache, path: str = DEFAULT_CACHE):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], products: sfq.ProductBuffers,
+         counters: sfq.Counters, *, seed: int = 0, step: int = 1,
+         candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 4,
+         cache_path: str | None = DEFAULT_CACHE, force: bool = False) -> Dict:
+    """Sets the fastest launch shape on `handle` and returns {'shape', 'ms', 'timings', ...}."""
+    key = signature(handle, tiles)
+    cache = load_cache(cache_path) if cache_path else {}
+    if not force and key in cache:
+        bpc, chunk = cache[key]["shape"]
+        handle.set_launch(bpc, chunk)
+        return dict(cache[key], cached=True, key=key)
+    snap = _snapshot(tiles)
+    counts0 = products.counts.clone()
+    cnt0 = counters.t.clone()
+    stream = torch.cuda.current_stream()
+    timings = {}
+    for bpc, chunk in candidates:
+        handle.set_launch(bpc, chunk)
+        plan = handle.plan(tiles, seed=seed, step=step, products=products, counters=counters)
+        plan.launch()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(repeats + 1)]
+        ev[0].record(stream)
+        for k in range(repeats):
+            plan.launch()
+            ev[k + 1].record(stream)
+        torch.cuda.synchronize()
+        ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(repeats))
+        timings[f"{bpc}x{chunk}"] = ms[len(ms) // 2]
+        plan.close()
+        _restore(tiles, snap)
+    best = min(timings, key=timings.get)
+    bpc, chunk = (int(v) for v in best.split("x"))
+    handle.set_launch(bpc, chunk)
+    products.counts.copy_(counts0)
+    counters.t.copy_(cnt0)
+    torch.cuda.synchronize()
+    entry = {"shape": [bpc, chunk], "ms": timings[best], "timings": timings,
+             "when": time.strftime("%Y-%m-%dT%H:%M:%S")}
+    if cache_path:
+        cache[key] = entry
+        save_cache(cache, cache_path)
+    return dict(entry, cached=False, key=key)

@@ -57,6 +57,7 @@ struct StepArgs {
     int decision;
     int blcfa;
     uint32_t step;
+    const unsigned long long* step_ptr;  // if set, the step index is read from device memory
     uint64_t seed;
     // emitter queue (SoA).  Block b owns entries [b cap, (b+1) cap): leptons from the start of
     // the slice upwards, photons from its end downwards.
@@ -286,6 +287,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepAr
     unsigned long long c_proc = 0, c_ood = 0;
     const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
     const double dt = A.ph.dt;
+    const uint32_t step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
 
     for (int c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
         const int t = find_tile(A.chunk_off, A.ntiles, c);
@@ -316,7 +318,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepAr
                         emit = tau < 0.0;
                         if (!emit) st_stream(&T.tau[i], tau);  // emitters get a fresh depth later
                     } else {
-                        const Draw d = philox_draw(A.seed, quid, A.step, SFQ_P_LOCAL);
+                        const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
                         emit = W * dt > uniform53(d.a);
                     }
                 } else {
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepAr
                         T.fperp[i] = Fx; T.fperp[n + i] = Fy; T.fperp[2 * n + i] = Fz;
                         T.dfperp[i] = ax; T.dfperp[n + i] = ay; T.dfperp[2 * n + i] = az;
                         const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
-                        const Draw d = philox_draw(A.seed, quid, A.step, SFQ_P_LOCAL);
+                        const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
                         emit = W * dt > uniform53(d.a);
                         if (emit) {
                             // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
@@ -421,6 +423,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
     if (tid < CNT_N) s_cnt[tid] = 0;
     const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
     const unsigned nl = A.q_count[2 * blockIdx.x], np = A.q_count[2 * blockIdx.x + 1];
+    const uint32_t step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
     // product slots of the whole block, reserved once: one photon per lepton emitter and one
     // electron-positron pair per converting photon (beyond-LCFA rejections leave no product, so
     // that mode reserves per wave instead)
@@ -455,8 +458,8 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
             py = A.q_py[slot];
             pz = A.q_pz[slot];
             uid = A.q_uid[slot];
-            d1 = philox_draw(A.seed, uid, A.step, SFQ_P_EMIT);
-            d2 = philox_draw(A.seed, uid, A.step, SFQ_P_CHILD);
+            d1 = philox_draw(A.seed, uid, step, SFQ_P_EMIT);
+            d2 = philox_draw(A.seed, uid, step, SFQ_P_CHILD);
             r = uniform53(d1.a);
         }
         double s = 0.0, v = 0.0, omv = 1.0;
@@ -473,7 +476,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
                 if (BLCFA) {
                     const double limit = A.q_aux[slot];
                     if (!(gph > limit)) {  // Eq. (rej_cond)
-                        const Draw dl = philox_draw(A.seed, uid, A.step, SFQ_P_LOCAL);
+                        const Draw dl = philox_draw(A.seed, uid, step, SFQ_P_LOCAL);
                         const double r2 = uniform53(dl.b);
                         const double lp_s = log_photon_pdf(A.tb.ka, A.tb.kb, gph, gamma, chi);
                         const double lp_l = log_photon_pdf(A.tb.ka, A.tb.kb, limit, gamma, chi);
@@ -498,7 +501,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
                     ++c_rej;
                 }
             } else {
-                const Draw d3 = philox_draw(A.seed, uid, A.step, SFQ_P_CHILD2);
+                const Draw d3 = philox_draw(A.seed, uid, step, SFQ_P_CHILD2);
                 double ge, gp;
                 pair_energies(gamma, r, v, omv, ge, gp);
                 bool c1, c2;
@@ -551,6 +554,23 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
     __syncthreads();
     const unsigned long long vals[CNT_N] = {0, c_emit, c_conv, c_rej, c_ood, c_clamp, c_over};
     block_add_counters(s_cnt, A.counters, vals);
+}
+
+// plan helpers: zero the product counts (a kernel, not a memset, so graphs replay it safely)
+// and advance the device step counter after a step
+__global__ void zero_counts_kernel(unsigned long long* counts)
+{
+    if (threadIdx.x < 3) counts[threadIdx.x] = 0;
+}
+
+__global__ void advance_step_kernel(unsigned long long* step)
+{
+    if (threadIdx.x == 0) *step += 1;
+}
+
+__global__ void set_step_kernel(unsigned long long* step, unsigned long long value)
+{
+    if (threadIdx.x == 0) *step = value;
 }
 
 // =============================================================================================
@@ -697,6 +717,8 @@ struct sfq_ctx {
     int blocks_per_cu = 8;
     int chunk = 2048;
 };
+
+struct sfq_plan_t;
 
 static sfq_status fail(sfq_ctx* h, sfq_status st, const std::string& msg)
 {
@@ -1026,105 +1048,77 @@ sfq_status sfq_get_launch(sfq_handle h, int* blocks_per_cu, int* chunk)
     return SFQ_OK;
 }
 
-sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Step plumbing shared by sfq_step and the plans
+// ---------------------------------------------------------------------------------------------
+static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vector<uint32_t>& off,
+                                int chunk)
 {
-    if (!h) return fail(h, SFQ_E_STATE, "sfq_step: NULL handle");
     if (!desc || !desc->tiles) return fail(h, SFQ_E_ARG, "sfq_step: NULL descriptor");
     if (desc->ntiles <= 0 || desc->ntiles > SFQ_MAX_TILES)
         return fail(h, SFQ_E_ARG, "sfq_step: ntiles out of range");
     if (!desc->counters || !desc->product_counts)
         return fail(h, SFQ_E_ARG, "sfq_step: NULL counters");
     const int nt = desc->ntiles;
-    std::vector<uint32_t> off(nt + 1, 0);
-    uint64_t total = 0;
+    off.assign(nt + 1, 0);
     for (int t = 0; t < nt; ++t) {
         const sfq_tile& T = desc->tiles[t];
+        const std::string tn = " (tile " + std::to_string(t) + ")";
         if (T.species < 0 || T.species > 2 || T.reserved != 0)
-            return fail(h, SFQ_E_ARG, "sfq_step: bad tile species (tile " + std::to_string(t) + ")");
+            return fail(h, SFQ_E_ARG, "sfq_step: bad tile species" + tn);
         if (T.n >= (1ull << 32))
             return fail(h, SFQ_E_CAPACITY, "sfq_step: tile larger than 2^32 - 1 particles");
         const bool photon = T.species == SFQ_PHOTON;
         const bool bl = h->blcfa && !photon;
         if (T.n > 0) {
             if (!T.px || !T.py || !T.pz || !T.uid)
-                return fail(h, SFQ_E_ARG, "sfq_step: NULL momentum/uid (tile " + std::to_string(t) + ")");
+                return fail(h, SFQ_E_ARG, "sfq_step: NULL momentum/uid" + tn);
             if (!bl && (!T.ex || !T.ey || !T.ez || !T.bx || !T.by || !T.bz))
-                return fail(h, SFQ_E_ARG, "sfq_step: NULL field array (tile " + std::to_string(t) + ")");
+                return fail(h, SFQ_E_ARG, "sfq_step: NULL field array" + tn);
             if (!bl && h->decision == SFQ_OPTICAL_DEPTH && !T.tau)
-                return fail(h, SFQ_E_ARG, "sfq_step: NULL tau (tile " + std::to_string(t) + ")");
+                return fail(h, SFQ_E_ARG, "sfq_step: NULL tau" + tn);
             if (photon && !T.alive)
-                return fail(h, SFQ_E_ARG, "sfq_step: photon tiles need an alive array");
+                return fail(h, SFQ_E_ARG, "sfq_step: photon tiles need an alive array" + tn);
             if (bl && (!T.px_prev || !T.py_prev || !T.pz_prev || !T.fperp || !T.dfperp ||
                        !T.just_created))
-                return fail(h, SFQ_E_ARG, "sfq_step: beyond-LCFA state missing (tile " +
-                                              std::to_string(t) + ")");
+                return fail(h, SFQ_E_ARG, "sfq_step: beyond-LCFA state missing" + tn);
         }
-        off[t + 1] = off[t] + (uint32_t)((T.n + h->chunk - 1) / h->chunk);
-        total += T.n;
+        const uint64_t nch = (T.n + chunk - 1) / chunk;
+        if ((uint64_t)off[t] + nch >= (1ull << 31))
+            return fail(h, SFQ_E_CAPACITY, "sfq_step: too many particles in one step");
+        off[t + 1] = off[t] + (uint32_t)nch;
     }
     const sfq_products* P[3] = {&desc->photons, &desc->electrons, &desc->positrons};
     for (int k = 0; k < 3; ++k)
         if (P[k]->capacity > 0 &&
             (!P[k]->px || !P[k]->py || !P[k]->pz || !P[k]->tau || !P[k]->uid || !P[k]->parent))
             return fail(h, SFQ_E_ARG, "sfq_step: NULL product array");
-    const int nchunks = (int)off[nt];
-    if (nchunks == 0) return SFQ_OK;
+    return SFQ_OK;
+}
 
-    std::lock_guard<std::mutex> lock(h->mu);
-    HIP_TRY(h, hipSetDevice(h->device));
-    const int grid = std::max(1, std::min(nchunks, h->num_cus * h->blocks_per_cu));
-    const uint64_t chunks_per_block = (uint64_t)((nchunks + grid - 1) / grid);
-    const uint64_t cap_per_block = chunks_per_block * (uint64_t)h->chunk;
-    const uint64_t entries = cap_per_block * (uint64_t)grid;
-    if (entries > h->queue_entries || grid > h->queue_blocks) {
-        if (h->d_queue) {
-            HIP_TRY(h, hipDeviceSynchronize());
-            HIP_TRY(h, hipFree(h->d_queue));
-            h->d_queue = nullptr;
-            h->queue_entries = 0;
-        }
-        const size_t bytes = entries * (4 + 4 + 8 * 9) + 8 * (size_t)grid + 256;
-        if (hipMalloc(&h->d_queue, bytes) != hipSuccess) {
-            h->d_queue = nullptr;
-            return fail(h, SFQ_E_NOMEM, "sfq_step: cannot allocate the emitter queue");
-        }
-        h->queue_entries = entries;
-        h->queue_blocks = grid;
-    }
-    // descriptors through a ring of pinned staging buffers
-    Staging& S = h->staging[h->next_staging];
-    h->next_staging = (h->next_staging + 1) % N_STAGING;
-    const size_t need = nt * sizeof(sfq_tile) + (nt + 1) * sizeof(uint32_t) + 64;
-    if (need > STAGING_BYTES) return fail(h, SFQ_E_CAPACITY, "sfq_step: too many tiles");
-    if (!S.host) {
-        HIP_TRY(h, hipHostMalloc(&S.host, STAGING_BYTES, hipHostMallocDefault));
-        HIP_TRY(h, hipMalloc(&S.dev, STAGING_BYTES));
-        HIP_TRY(h, hipEventCreateWithFlags(&S.done, hipEventDisableTiming));
-        S.bytes = STAGING_BYTES;
-    } else {
-        HIP_TRY(h, hipEventSynchronize(S.done));
-    }
-    char* hb = (char*)S.host;
-    memcpy(hb, desc->tiles, nt * sizeof(sfq_tile));
-    const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
-    memcpy(hb + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
-    HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, off_pos + (nt + 1) * sizeof(uint32_t),
-                              hipMemcpyHostToDevice, (hipStream_t)stream));
+struct QueueShape {
+    int grid;
+    uint64_t cap_per_block, entries;
+};
 
-    StepArgs A;
-    A.tb = h->tb;
-    A.ph = h->ph;
-    A.tiles = (const sfq_tile*)S.dev;
-    A.chunk_off = (const uint32_t*)((char*)S.dev + off_pos);
-    A.ntiles = nt;
-    A.nchunks = nchunks;
-    A.chunk = h->chunk;
-    A.decision = h->decision;
-    A.blcfa = h->blcfa;
-    A.step = (uint32_t)desc->step;
-    A.seed = desc->seed;
-    char* q = (char*)h->d_queue;
-    const size_t E = h->queue_entries;
+static QueueShape queue_shape(const sfq_ctx* h, int nchunks, int blocks_per_cu, int chunk)
+{
+    QueueShape q;
+    q.grid = std::max(1, std::min(nchunks, h->num_cus * blocks_per_cu));
+    const uint64_t chunks_per_block = (uint64_t)((nchunks + q.grid - 1) / q.grid);
+    q.cap_per_block = chunks_per_block * (uint64_t)chunk;
+    q.entries = q.cap_per_block * (uint64_t)q.grid;
+    return q;
+}
+
+static size_t queue_bytes(const QueueShape& q) { return q.entries * (4 + 4 + 8 * 9) + 8 * (size_t)q.grid + 256; }
+
+static void bind_queue(StepArgs& A, void* mem, const QueueShape& qs)
+{
+    char* q = (char*)mem;
+    const size_t E = qs.entries;
     A.q_chi = (double*)q;
     A.q_gamma = (double*)(q + 8 * E);
     A.q_px = (double*)(q + 16 * E);
@@ -1136,13 +1130,31 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     A.q_idx = (uint32_t*)(q + 64 * E);
     A.q_tile = (uint32_t*)(q + 68 * E);
     A.q_count = (uint32_t*)(q + 72 * E);
-    A.q_cap_per_block = cap_per_block;
+    A.q_cap_per_block = qs.cap_per_block;
+}
+
+static void fill_args(const sfq_ctx* h, const sfq_step_desc* desc, StepArgs& A, int nchunks,
+                      int chunk)
+{
+    A.tb = h->tb;
+    A.ph = h->ph;
+    A.ntiles = desc->ntiles;
+    A.nchunks = nchunks;
+    A.chunk = chunk;
+    A.decision = h->decision;
+    A.blcfa = h->blcfa;
+    A.step = (uint32_t)desc->step;
+    A.step_ptr = nullptr;
+    A.seed = desc->seed;
     A.prod[0] = desc->photons;
     A.prod[1] = desc->electrons;
     A.prod[2] = desc->positrons;
     A.prod_counts = desc->product_counts;
     A.counters = desc->counters;
-    const hipStream_t st = (hipStream_t)stream;
+}
+
+static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, hipStream_t st)
+{
     const dim3 g(grid), b(STEP_BLOCK);
     if (h->precision == SFQ_MIXED) {
         if (h->blcfa) {
@@ -1161,9 +1173,196 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
             hipLaunchKernelGGL((emit_kernel<false, false>), g, b, 0, st, A);
         }
     }
+}
+
+struct sfq_plan_t {
+    sfq_ctx* h = nullptr;
+    StepArgs A{};
+    int grid = 0;
+    int zero_counts = 0;
+    void* d_mem = nullptr;                // descriptors, chunk offsets, step counter, queue
+    unsigned long long* d_step = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_steps = 0;
+};
+
+static void plan_release(sfq_plan_t* p)
+{
+    if (!p) return;
+    if (p->h) (void)hipSetDevice(p->h->device);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->d_mem) (void)hipFree(p->d_mem);
+    delete p;
+}
+
+static void plan_enqueue(sfq_plan_t* p, hipStream_t st)
+{
+    if (p->zero_counts) hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, st, p->A.prod_counts);
+    launch_step_kernels(p->h, p->A, p->grid, st);
+    hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, p->d_step);
+}
+
+extern "C" {
+
+sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_step: NULL handle");
+    std::lock_guard<std::mutex> lock(h->mu);
+    std::vector<uint32_t> off;
+    const int chunk = h->chunk;
+    const sfq_status v = validate_desc(h, desc, off, chunk);
+    if (v != SFQ_OK) return v;
+    const int nt = desc->ntiles;
+    const int nchunks = (int)off[nt];
+    if (nchunks == 0) return SFQ_OK;
+    HIP_TRY(h, hipSetDevice(h->device));
+    const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk);
+    if (qs.entries > h->queue_entries || qs.grid > h->queue_blocks) {
+        if (h->d_queue) {
+            HIP_TRY(h, hipDeviceSynchronize());
+            HIP_TRY(h, hipFree(h->d_queue));
+            h->d_queue = nullptr;
+            h->queue_entries = 0;
+            h->queue_blocks = 0;
+        }
+        if (hipMalloc(&h->d_queue, queue_bytes(qs)) != hipSuccess) {
+            h->d_queue = nullptr;
+            return fail(h, SFQ_E_NOMEM, "sfq_step: cannot allocate the emitter queue");
+        }
+        h->queue_entries = qs.entries;
+        h->queue_blocks = qs.grid;
+    }
+    // descriptors through a ring of pinned staging buffers
+    Staging& S = h->staging[h->next_staging];
+    h->next_staging = (h->next_staging + 1) % N_STAGING;
+    const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
+    if (off_pos + (nt + 1) * sizeof(uint32_t) > STAGING_BYTES)
+        return fail(h, SFQ_E_CAPACITY, "sfq_step: too many tiles");
+    if (!S.host) {
+        HIP_TRY(h, hipHostMalloc(&S.host, STAGING_BYTES, hipHostMallocDefault));
+        HIP_TRY(h, hipMalloc(&S.dev, STAGING_BYTES));
+        HIP_TRY(h, hipEventCreateWithFlags(&S.done, hipEventDisableTiming));
+        S.bytes = STAGING_BYTES;
+    } else {
+        HIP_TRY(h, hipEventSynchronize(S.done));
+    }
+    char* hb = (char*)S.host;
+    memcpy(hb, desc->tiles, nt * sizeof(sfq_tile));
+    memcpy(hb + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
+    HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, off_pos + (nt + 1) * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, (hipStream_t)stream));
+    // the queue shape must describe the allocation actually bound
+    QueueShape bound = qs;
+    bound.entries = h->queue_entries;
+    StepArgs A;
+    fill_args(h, desc, A, nchunks, chunk);
+    A.tiles = (const sfq_tile*)S.dev;
+    A.chunk_off = (const uint32_t*)((char*)S.dev + off_pos);
+    bind_queue(A, h->d_queue, bound);
+    A.q_cap_per_block = qs.cap_per_block;
+    launch_step_kernels(h, A, qs.grid, (hipStream_t)stream);
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
-    (void)total;
+    return SFQ_OK;
+}
+
+sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_product_counts,
+                           sfq_plan* out)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_plan_create: NULL handle");
+    if (!out) return fail(h, SFQ_E_ARG, "sfq_plan_create: NULL output");
+    *out = nullptr;
+    std::lock_guard<std::mutex> lock(h->mu);
+    std::vector<uint32_t> off;
+    const int chunk = h->chunk;
+    const sfq_status v = validate_desc(h, desc, off, chunk);
+    if (v != SFQ_OK) return v;
+    const int nt = desc->ntiles;
+    const int nchunks = (int)off[nt];
+    if (nchunks == 0) return fail(h, SFQ_E_ARG, "sfq_plan_create: no particles");
+    HIP_TRY(h, hipSetDevice(h->device));
+    const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk);
+    const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
+    const size_t step_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t q_pos = step_pos + 256;
+    sfq_plan_t* p = new sfq_plan_t();
+    p->h = h;
+    p->zero_counts = zero_product_counts ? 1 : 0;
+    if (hipMalloc(&p->d_mem, q_pos + queue_bytes(qs)) != hipSuccess) {
+        p->d_mem = nullptr;
+        plan_release(p);
+        return fail(h, SFQ_E_NOMEM, "sfq_plan_create: cannot allocate the plan");
+    }
+    std::vector<char> hostbuf(step_pos + 8, 0);
+    memcpy(hostbuf.data(), desc->tiles, nt * sizeof(sfq_tile));
+    memcpy(hostbuf.data() + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
+    const unsigned long long step0 = desc->step;
+    memcpy(hostbuf.data() + step_pos, &step0, 8);
+    if (hipMemcpy(p->d_mem, hostbuf.data(), step_pos + 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        plan_release(p);
+        return fail(h, SFQ_E_DEVICE, "sfq_plan_create: device setup failed");
+    }
+    p->grid = qs.grid;
+    p->d_step = (unsigned long long*)((char*)p->d_mem + step_pos);
+    fill_args(h, desc, p->A, nchunks, chunk);
+    p->A.tiles = (const sfq_tile*)p->d_mem;
+    p->A.chunk_off = (const uint32_t*)((char*)p->d_mem + off_pos);
+    p->A.step_ptr = p->d_step;
+    bind_queue(p->A, (char*)p->d_mem + q_pos, qs);
+    *out = p;
+    return SFQ_OK;
+}
+
+void sfq_plan_destroy(sfq_plan p) { plan_release(p); }
+
+sfq_status sfq_plan_launch(sfq_plan p, void* stream)
+{
+    if (!p) return fail(nullptr, SFQ_E_STATE, "sfq_plan_launch: NULL plan");
+    HIP_TRY(p->h, hipSetDevice(p->h->device));
+    plan_enqueue(p, (hipStream_t)stream);
+    HIP_TRY(p->h, hipGetLastError());
+    return SFQ_OK;
+}
+
+sfq_status sfq_plan_set_step(sfq_plan p, uint64_t step, void* stream)
+{
+    if (!p) return fail(nullptr, SFQ_E_STATE, "sfq_plan_set_step: NULL plan");
+    HIP_TRY(p->h, hipSetDevice(p->h->device));
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, p->d_step,
+                       (unsigned long long)step);
+    HIP_TRY(p->h, hipGetLastError());
+    return SFQ_OK;
+}
+
+sfq_status sfq_plan_capture(sfq_plan p, int steps)
+{
+    if (!p) return fail(nullptr, SFQ_E_STATE, "sfq_plan_capture: NULL plan");
+    if (steps < 1 || steps > 4096) return fail(p->h, SFQ_E_ARG, "sfq_plan_capture: steps in [1, 4096]");
+    HIP_TRY(p->h, hipSetDevice(p->h->device));
+    if (p->exec) { HIP_TRY(p->h, hipGraphExecDestroy(p->exec)); p->exec = nullptr; }
+    if (p->graph) { HIP_TRY(p->h, hipGraphDestroy(p->graph)); p->graph = nullptr; }
+    HIP_TRY(p->h, hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < steps; ++k) plan_enqueue(p, p->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(p->cap_stream, &g);
+    if (e1 != hipSuccess) return fail(p->h, SFQ_E_DEVICE, std::string("sfq_plan_capture: ") + hipGetErrorString(e1));
+    p->graph = g;
+    HIP_TRY(p->h, hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    p->graph_steps = steps;
+    return SFQ_OK;
+}
+
+sfq_status sfq_plan_replay(sfq_plan p, void* stream)
+{
+    if (!p) return fail(nullptr, SFQ_E_STATE, "sfq_plan_replay: NULL plan");
+    if (!p->exec) return fail(p->h, SFQ_E_STATE, "sfq_plan_replay: no graph captured");
+    HIP_TRY(p->h, hipSetDevice(p->h->device));
+    HIP_TRY(p->h, hipGraphLaunch(p->exec, (hipStream_t)stream));
     return SFQ_OK;
 }
 

@@ -29,7 +29,8 @@ STATUS = {0: "SFQ_OK", 1: "SFQ_E_ARG", 2: "SFQ_E_STATE", 3: "SFQ_E_NOMEM", 4: "S
 # every symbol declared in include/sfq.h
 EXPORTS = ("sfq_create", "sfq_destroy", "sfq_last_error", "sfq_units", "sfq_chi", "sfq_rates",
            "sfq_sample_photon", "sfq_sample_pair", "sfq_philox", "sfq_init_optical_depth",
-           "sfq_step", "sfq_set_launch", "sfq_get_launch")
+           "sfq_step", "sfq_set_launch", "sfq_get_launch", "sfq_plan_create", "sfq_plan_destroy",
+           "sfq_plan_launch", "sfq_plan_set_step", "sfq_plan_capture", "sfq_plan_replay")
 
 
 class Config(C.Structure):
@@ -104,6 +105,18 @@ def load(path: str = LIB_PATH):
     L.sfq_set_launch.argtypes = [vp, C.c_int, C.c_int]
     L.sfq_get_launch.restype = st
     L.sfq_get_launch.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.sfq_plan_create.restype = st
+    L.sfq_plan_create.argtypes = [vp, C.POINTER(StepDesc), C.c_int, C.POINTER(vp)]
+    L.sfq_plan_destroy.restype = None
+    L.sfq_plan_destroy.argtypes = [vp]
+    L.sfq_plan_launch.restype = st
+    L.sfq_plan_launch.argtypes = [vp, vp]
+    L.sfq_plan_set_step.restype = st
+    L.sfq_plan_set_step.argtypes = [vp, u64, vp]
+    L.sfq_plan_capture.restype = st
+    L.sfq_plan_capture.argtypes = [vp, C.c_int]
+    L.sfq_plan_replay.restype = st
+    L.sfq_plan_replay.argtypes = [vp, vp]
     _lib = L
     return L
 
@@ -233,9 +246,8 @@ class Handle:
                                                    _stream(stream)))
         return out
 
-    def step(self, tiles: Sequence["TileArrays"], *, seed: int, step: int,
-             products: "ProductBuffers", counters: "Counters", stream=None):
-        """One Monte Carlo step over all tiles (one launch sequence on `stream`)."""
+    @staticmethod
+    def _desc(tiles, seed, step, products, counters):
         nt = len(tiles)
         if nt == 0 or nt > MAX_TILES:
             raise ValueError("1 <= len(tiles) <= MAX_TILES")
@@ -246,7 +258,57 @@ class Handle:
                         photons=products.photons.to_c(), electrons=products.electrons.to_c(),
                         positrons=products.positrons.to_c(),
                         product_counts=_ptr(products.counts), counters=_ptr(counters.t))
+        return desc, arr
+
+    def step(self, tiles: Sequence["TileArrays"], *, seed: int, step: int,
+             products: "ProductBuffers", counters: "Counters", stream=None):
+        """One Monte Carlo step over all tiles (one launch sequence on `stream`)."""
+        desc, _keep = self._desc(tiles, seed, step, products, counters)
         self._check(self._L.sfq_step(self._h, C.byref(desc), _stream(stream)))
+
+    def plan(self, tiles, *, seed: int, step: int, products: "ProductBuffers",
+             counters: "Counters", zero_product_counts: bool = True) -> "Plan":
+        return Plan(self, tiles, seed=seed, step=step, products=products, counters=counters,
+                    zero_product_counts=zero_product_counts)
+
+
+class Plan:
+    """A fixed set of tiles stepped repeatedly (sfq_plan_*): kernels only per launch, the step
+    index advancing on the device, optionally captured in a HIP graph."""
+
+    def __init__(self, handle: Handle, tiles, *, seed, step, products, counters,
+                 zero_product_counts=True):
+        self._handle = handle
+        self._L = handle._L
+        self.tiles, self.products, self.counters = list(tiles), products, counters
+        desc, _keep = Handle._desc(self.tiles, seed, step, products, counters)
+        p = C.c_void_p()
+        handle._check(self._L.sfq_plan_create(handle._h, C.byref(desc), int(zero_product_counts),
+                                              C.byref(p)))
+        self._p = p
+
+    def launch(self, stream=None):
+        self._handle._check(self._L.sfq_plan_launch(self._p, _stream(stream)))
+
+    def set_step(self, step, stream=None):
+        self._handle._check(self._L.sfq_plan_set_step(self._p, step, _stream(stream)))
+
+    def capture(self, steps: int):
+        self._handle._check(self._L.sfq_plan_capture(self._p, steps))
+
+    def replay(self, stream=None):
+        self._handle._check(self._L.sfq_plan_replay(self._p, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_p", None):
+            self._L.sfq_plan_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 @dataclass

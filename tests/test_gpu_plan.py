@@ -1,0 +1,138 @@
+"""Plans, graph capture and the autotuner: the same results as plain sfq_step calls.
+
+A plan launch and a graph replay must give bit-identical particle states and the same set of
+products as the equivalent sequence of sfq_step calls (the arithmetic is the same; only launch
+plumbing differs).  Graph replays are checked after every replay, with eager work and
+synchronisations in between.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2301_07684_amd import autotune, inputs, sfq
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def make_tiles(dev, h, sizes=(5000, 1, 3000, 700)):
+    tiles = []
+    for k, n in enumerate(sizes):
+        sp = [sfq.ELECTRON, sfq.PHOTON, sfq.POSITRON, sfq.PHOTON][k % 4]
+        w = inputs.plain_compton(n, seed=500 + k, species=sp)
+        uid = T(w["uid"], dev)
+        tau = h.init_optical_depth(uid, seed=3) * 0.2
+        tiles.append(sfq.TileArrays(sp, *[T(w["p"][i], dev) for i in range(3)],
+                                    *[T(w["E"][i], dev) for i in range(3)],
+                                    *[T(w["B"][i], dev) for i in range(3)], tau=tau, uid=uid,
+                                    alive=torch.ones(n, dtype=torch.uint8, device=dev)))
+    return tiles
+
+
+def clone_tiles(tiles):
+    out = []
+    for t in tiles:
+        kw = {f: (getattr(t, f).clone() if getattr(t, f) is not None else None)
+              for f in ("px", "py", "pz", "tau", "alive")}
+        out.append(sfq.TileArrays(t.species, kw["px"], kw["py"], kw["pz"], t.ex, t.ey, t.ez, t.bx,
+                                  t.by, t.bz, tau=kw["tau"], uid=t.uid, alive=kw["alive"]))
+    return out
+
+
+def state(tiles):
+    return [torch.cat([t.px, t.py, t.pz, t.tau]).cpu().numpy() for t in tiles] + \
+           [t.alive.cpu().numpy() for t in tiles]
+
+
+def product_set(pb):
+    """Products of the last step per species, sorted by (parent, uid): their order in the
+    buffers depends on block scheduling, their contents do not."""
+    c = pb.host_counts()
+    out = []
+    for k, name in enumerate(("photons", "electrons", "positrons")):
+        ps = getattr(pb, name)
+        n = min(c[k], ps.capacity)
+        uid, parent = ps.uid[:n].cpu().numpy(), ps.parent[:n].cpu().numpy()
+        order = np.lexsort((uid, parent))
+        out.append(np.stack([uid, parent])[:, order])
+        out.append(np.stack([getattr(ps, f)[:n].cpu().numpy() for f in ("px", "py", "pz", "tau")])
+                   [:, order])
+    return out
+
+
+def same(a, b):
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("precision", [sfq.FP64, sfq.MIXED])
+def test_plan_and_graph_match_step(dev, precision):
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=precision)
+    base = make_tiles(dev, h)
+    eager, planned, graphed = clone_tiles(base), clone_tiles(base), clone_tiles(base)
+    pe, pp, pg = (sfq.ProductBuffers.empty(20000, 20000, dev) for _ in range(3))
+    ce, cp, cg = sfq.Counters(dev), sfq.Counters(dev), sfq.Counters(dev)
+    plan = h.plan(planned, seed=9, step=10, products=pp, counters=cp)
+    gplan = h.plan(graphed, seed=9, step=10, products=pg, counters=cg)
+    gplan.capture(2)  # one replay = two steps
+    for rep in range(3):
+        for k in range(2):
+            pe.reset()
+            h.step(eager, seed=9, step=10 + 2 * rep + k, products=pe, counters=ce)
+            plan.launch()
+            torch.cuda.synchronize()
+            assert same(state(eager), state(planned)), (rep, k)
+            assert same(product_set(pe), product_set(pp))
+        gplan.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device=dev).sum().item()  # eager work between replays
+        assert same(state(eager), state(graphed)), rep
+        assert same(product_set(pe), product_set(pg)), rep  # the last step's products
+    assert ce.as_dict() == cp.as_dict() == cg.as_dict()
+    plan.close()
+    gplan.close()
+
+
+def test_plan_set_step(dev):
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    base = make_tiles(dev, h, sizes=(3000,))
+    a, b = clone_tiles(base), clone_tiles(base)
+    pa, pb = sfq.ProductBuffers.empty(5000, 1, dev), sfq.ProductBuffers.empty(5000, 1, dev)
+    ca, cb = sfq.Counters(dev), sfq.Counters(dev)
+    plan = h.plan(a, seed=1, step=0, products=pa, counters=ca)
+    plan.set_step(77)
+    plan.launch()
+    h.step(b, seed=1, step=77, products=pb, counters=cb)
+    torch.cuda.synchronize()
+    assert same(state(a), state(b))
+
+
+def test_autotune_restores_state_and_picks_a_candidate(dev, tmp_path):
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=sfq.MIXED)
+    base = make_tiles(dev, h, sizes=(40000, 20000, 30000))
+    tuned, ref = clone_tiles(base), clone_tiles(base)
+    pt, pr = sfq.ProductBuffers.empty(90000, 90000, dev), sfq.ProductBuffers.empty(90000, 90000, dev)
+    ct, cr = sfq.Counters(dev), sfq.Counters(dev)
+    cache = str(tmp_path / "tune.json")
+    res = autotune.tune(h, tuned, pt, ct, cache_path=cache, repeats=2)
+    assert tuple(res["shape"]) in autotune.DEFAULT_CANDIDATES and not res["cached"]
+    assert h.get_launch() == tuple(res["shape"])
+    assert same(state(tuned), state(base))  # tuning left the particles as they were
+    assert ct.as_dict()["processed"] == 0 and pt.host_counts() == [0, 0, 0]
+    res2 = autotune.tune(h, tuned, pt, ct, cache_path=cache)
+    assert res2["cached"] and res2["shape"] == res["shape"]
+    h.step(tuned, seed=2, step=5, products=pt, counters=ct)
+    h.set_launch(4, 2048)
+    h.step(ref, seed=2, step=5, products=pr, counters=cr)
+    torch.cuda.synchronize()
+    assert same(state(tuned), state(ref))  # launch shapes never change results
+    assert same(product_set(pt), product_set(pr))
