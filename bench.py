@@ -3,22 +3,28 @@
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 
-Workload (the plain FP64 form at scale): 2^24 electrons + 2^24 photons counter-propagating
-through a linearly polarised plane wave (a ~ U[10, 500], random phase, gamma log-uniform
-[1e2, 1e5]), nonlinear Compton and Breit-Wheeler both active, optical-depth decisions,
-dt = 0.01 fs, FP64 SoA arrays resident in HBM.  A step is one sfq_step over both tiles
-(chi, rates, decisions, sampling, recoil, products).  The same is then timed in the MIXED form
-on the skewed-chi ensemble (chi log-uniform [1e-4, 1e3]).
+Headline workload (the plain FP64 form at scale): 2^24 electrons + 2^24 photons
+counter-propagating through a linearly polarised plane wave (a ~ U[10, 500], random phase,
+gamma log-uniform [1e2, 1e5]), nonlinear Compton and Breit-Wheeler both active, optical-depth
+decisions, dt = 0.01 fs, FP64 SoA arrays resident in HBM.  A step is one sfq_step over both
+tiles (chi, rates, decisions, sampling, recoil, products).  Then, on the same GPU:
+  * the MIXED form on the skewed-chi ensemble (chi log-uniform [1e-4, 1e3]);
+  * the batched form: 64 uneven tiles of mixed species (sizes log-uniform 1e3..4e6, static-B
+    geometry, chi log-uniform [1e-3, 1e2]), MIXED, launch shape from the autotuner, each step
+    one replay of a HIP graph captured from a plan.
 
-Prints ONE JSON line: value = FP64 particle-updates/s; p50/p99 step latency; the MIXED form's
-numbers; the HBM roofline of the step kernel (algorithmic bytes / kernel time, measured with HIP
-events on the launch stream); and the CPU oracle timed on a bounded sample on the host cores.
+Prints ONE JSON line: value = FP64 particle-updates/s over the timed steps; p50/p99 step
+latency; the roofline of the dominant (streaming) kernel from its own duration measured with HIP
+events on its launch stream; the other forms' numbers; and the CPU oracle timed on a bounded
+sample on the host cores.  `--copy-calibration` instead times a plain device copy of known size
+(the reference for HBM counter scaling) and exits.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,32 +35,39 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-updates/sec (Compton+BW MC step) FP32 vs FP64; p99 step latency"
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_kernel_plane_wave_fp64.md")
 
 
-def algorithmic_bytes(processed, emitted, converted):
-    """Bytes a perfect implementation must move for one step.
-    Per alive particle: read p, E, B (72), tau (8), uid (8), alive (1); write tau (8) = 97.
-    Per Compton emission: write the emitter momentum (24) and a photon product
-    (p 24, tau 8, uid 8, parent 8 = 48).  Per conversion: write alive (1) and two lepton
-    products (96)."""
-    return 97 * processed + (24 + 48) * emitted + (1 + 96) * converted
+def stream_kernel_bytes(n_total, processed, emitted, converted):
+    """Algorithmic bytes of the streaming kernel for one step.  Every particle slot: its alive
+    flag (1 B).  Every live particle: p (24), E and B (48), uid (8), optical depth read (8).
+    Every live particle that does not emit: optical depth written back (8); emitters get a fresh
+    depth in the emitter kernel."""
+    return n_total + 88 * processed + 8 * (processed - emitted - converted)
 
 
-def build_state(dev, sfq, inputs, n, workload):
+def emit_kernel_bytes(emitted, converted):
+    """Algorithmic bytes of the emitter kernel for one step.  A Compton emission writes the
+    emitter's momentum and optical depth (32) and one photon product (p 24, tau 8, uid 8,
+    parent 8 = 48).  A conversion writes the photon's alive flag (1) and two lepton products
+    (96)."""
+    return 80 * emitted + 97 * converted
+
+
+def device_tiles(dev, sfq, h, workloads):
     import torch
 
-    tiles, keep = [], []
-    for species in (sfq.ELECTRON, sfq.PHOTON):
-        if workload == "plane_wave":
-            w = inputs.plane_wave(n, species=species)
-        else:
-            w = inputs.plane_wave(n, seed=inputs.SEED_SKEW, species=species, chi_range=(1e-4, 1e3))
-        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-        arrs = dict(p=[t(w["p"][k]) for k in range(3)], E=[t(w["E"][k]) for k in range(3)],
-                    B=[t(w["B"][k]) for k in range(3)], uid=t(w["uid"]))
-        del w
-        keep.append(arrs)
-    return keep
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    tiles = []
+    for w in workloads:
+        n = len(w["uid"])
+        uid = t(w["uid"])
+        tiles.append(sfq.TileArrays(int(w["species"]), *[t(w["p"][k]) for k in range(3)],
+                                    *[t(w["E"][k]) for k in range(3)],
+                                    *[t(w["B"][k]) for k in range(3)],
+                                    tau=h.init_optical_depth(uid, seed=0), uid=uid,
+                                    alive=torch.ones(n, dtype=torch.uint8, device=dev)))
+    return tiles
 
 
 def run_form(precision, workload, n, steps, warmup, dev):
@@ -63,21 +76,25 @@ def run_form(precision, workload, n, steps, warmup, dev):
     from paper_2301_07684_amd import inputs, sfq
 
     h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=precision)
-    state = build_state(dev, sfq, inputs, n, workload)
     tiles = []
-    for species, a in zip((sfq.ELECTRON, sfq.PHOTON), state):
-        tau = h.init_optical_depth(a["uid"], seed=0)
-        alive = torch.ones(n, dtype=torch.uint8, device=dev)
-        tiles.append(sfq.TileArrays(species, *a["p"], *a["E"], *a["B"], tau=tau, uid=a["uid"],
-                                    alive=alive))
+    for species in (sfq.ELECTRON, sfq.PHOTON):
+        if workload == "plane_wave":
+            w = inputs.plane_wave(n, species=species)
+        else:
+            w = inputs.plane_wave(n, seed=inputs.SEED_SKEW, species=species, chi_range=(1e-4, 1e3))
+        tiles += device_tiles(dev, sfq, h, [w])
+        del w
     prods = sfq.ProductBuffers.empty(n // 4, n // 16, dev)
     cnt = sfq.Counters(dev)
+    h.reserve(2 * n, 2)
     stream = torch.cuda.current_stream()
     for s in range(warmup):
         prods.reset()
         h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt)
     torch.cuda.synchronize()
     cnt.reset()
+    h.profile(True)
+    h.profile_read()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     torch.cuda.synchronize()
@@ -89,17 +106,61 @@ def run_form(precision, workload, n, steps, warmup, dev):
         ev[s][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    bulk_ms, emit_ms, nprof = h.profile_read()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
     c = cnt.as_dict()
     if c["overflow"]:
         raise RuntimeError("product buffers overflowed during the benchmark")
     h.close()
-    del tiles, state, prods
+    del tiles, prods
     torch.cuda.empty_cache()
-    return dict(wall=wall, step_ms=step_ms, counters=c)
+    return dict(wall=wall, step_ms=step_ms, counters=c, n_total=2 * n,
+                bulk_ms=bulk_ms / nprof, emit_ms=emit_ms / nprof)
 
 
-def cpu_baseline(n_sample=4096):
+def run_batched(steps, warmup, dev):
+    """64 uneven tiles, MIXED, autotuned launch shape, one graph replay per step."""
+    import torch
+
+    from paper_2301_07684_amd import autotune, inputs, sfq
+
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=sfq.MIXED)
+    tiles = []
+    for w in inputs.tiles():
+        tiles += device_tiles(dev, sfq, h, [w])
+    n_total = sum(t.n for t in tiles)
+    n_lep = sum(t.n for t in tiles if t.species != sfq.PHOTON)
+    prods = sfq.ProductBuffers.empty(n_lep // 3 + 1, (n_total - n_lep) // 8 + 1, dev)
+    cnt = sfq.Counters(dev)
+    tuned = autotune.tune(h, tiles, prods, cnt, seed=0, step=1, repeats=3)
+    plan = h.plan(tiles, seed=0, step=1, products=prods, counters=cnt)
+    plan.capture(1)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.replay()
+    torch.cuda.synchronize()
+    cnt.reset()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ev[s][0].record(stream)
+        plan.replay()
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    c = cnt.as_dict()
+    if c["overflow"]:
+        raise RuntimeError("product buffers overflowed during the batched benchmark")
+    plan.close()
+    h.close()
+    del tiles, prods
+    torch.cuda.empty_cache()
+    return dict(wall=wall, step_ms=step_ms, counters=c, n_total=n_total, tuned=tuned)
+
+
+def cpu_baseline(n_sample=24576):
     """The oracle as it stands on a bounded sample of the FP64 workload (all host cores)."""
     from oracle import oracle as O
     from paper_2301_07684_amd import inputs
@@ -117,8 +178,41 @@ def cpu_baseline(n_sample=4096):
         done += uid.size
     dt = time.perf_counter() - t0
     return dict(value=done / dt, unit="particle-updates/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{done} particles ({n_sample // 2} electrons + {n_sample // 2} photons) of "
-                       f"the FP64 plane-wave workload, one full step each, {dt:.1f} s")
+                sample=f"{done} particles ({n_sample // 2} electrons + {n_sample // 2} photons, "
+                       f"seeded random indices) of the FP64 plane-wave workload, one full step "
+                       f"each, {dt:.1f} s")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the streaming kernel from the committed counter summary, or None
+    when the kernels changed since the counters were taken."""
+    from paper_2301_07684_amd import build
+
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    get = lambda k: re.search(rf"^{k}:\s*(\S+)\s*$", txt, re.M)
+    h, f, w = get("source_hash"), get("fetch_bytes_per_launch"), get("write_bytes_per_launch")
+    if not (h and f and w) or h.group(1) != build.kernel_source_hash():
+        return None
+    return float(f.group(1)) + float(w.group(1))
+
+
+def copy_calibration(dev, nbytes=1 << 31, reps=5):
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps + 1,
+                      "GB_per_s": 2 * nbytes / dt / 1e9}), flush=True)
 
 
 def main():
@@ -129,6 +223,8 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 24, help="particles per species")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the QED step is independent per particle and this "
@@ -138,25 +234,39 @@ def main():
     import torch
 
     dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        copy_calibration(dev)
+        return
     f64 = run_form(0, "plane_wave", args.n, args.steps, args.warmup, dev)
+    print(f"# fp64 form done: {f64['wall'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
+          flush=True)
     mixed = None if args.no_mixed else run_form(1, "plane_wave_skewed", args.n, args.steps,
                                                 args.warmup, dev)
+    if mixed is not None:
+        print(f"# mixed form done: {mixed['wall'] / args.steps * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
+    batched = None if args.no_batched else run_batched(args.steps, args.warmup, dev)
+    if batched is not None:
+        print(f"# batched form done: {batched['wall'] / args.steps * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
 
     c = f64["counters"]
-    updates = c["processed"]
-    value = updates / f64["wall"]
-    ms = f64["wall"] / args.steps * 1e3
-    kern_s = float(np.mean(f64["step_ms"])) * 1e-3
-    bytes_per_step = algorithmic_bytes(c["processed"], c["emitted"], c["converted"]) / args.steps
-    achieved = bytes_per_step / kern_s
+    K = args.steps
+    value = c["processed"] / f64["wall"]
+    per = lambda k: c[k] / K
+    bulk_bytes = stream_kernel_bytes(f64["n_total"], per("processed"), per("emitted"),
+                                     per("converted"))
+    emit_bytes = emit_kernel_bytes(per("emitted"), per("converted"))
+    bulk_s, emit_s = f64["bulk_ms"] * 1e-3, f64["emit_ms"] * 1e-3
+    achieved = bulk_bytes / bulk_s
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "particle-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": f64["wall"] / K * 1e3,
         "p50_step_ms": float(np.percentile(f64["step_ms"], 50)),
         "p99_step_ms": float(np.percentile(f64["step_ms"], 99)),
         "higher_is_better": True,
@@ -166,27 +276,52 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plane-wave FP64 plain form: 2^24 electrons + 2^24 photons, "
                                "Compton + Breit-Wheeler, optical depth, dt = 0.01 fs",
-                   "particles_per_step": 2 * args.n, "precision": "fp64"},
-        "emitted_per_step": c["emitted"] / args.steps,
-        "converted_per_step": c["converted"] / args.steps,
+                   "particles_per_step": f64["n_total"], "precision": "fp64"},
+        "emitted_per_step": per("emitted"),
+        "converted_per_step": per("converted"),
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None,
-                     "kernel": "step_kernel<false>", "kernel_ms": kern_s * 1e3,
-                     "algorithmic_bytes_per_launch": bytes_per_step},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": measured_traffic(),
+                     "kernel": "bulk_kernel<false, false> (streaming pass)",
+                     "kernel_ms": f64["bulk_ms"], "algorithmic_bytes_per_launch": bulk_bytes},
+        "emit_kernel": {"kernel": "emit_kernel<false, false>", "kernel_ms": f64["emit_ms"],
+                        "algorithmic_bytes_per_launch": emit_bytes,
+                        "achieved_GB_per_s": emit_bytes / emit_s / 1e9},
+        "step_roofline_frac": (bulk_bytes + emit_bytes) / (float(np.mean(f64["step_ms"])) * 1e-3)
+                              / HBM_PEAK,
     }
     if mixed is not None:
         cm = mixed["counters"]
-        km = float(np.mean(mixed["step_ms"])) * 1e-3
-        bm = algorithmic_bytes(cm["processed"], cm["emitted"], cm["converted"]) / args.steps
+        pm = lambda k: cm[k] / K
+        bb = stream_kernel_bytes(mixed["n_total"], pm("processed"), pm("emitted"), pm("converted"))
         out["mixed"] = {"value": cm["processed"] / mixed["wall"], "unit": "particle-updates/s",
                         "dtype": "f32 (f64 chi, optical depth and tails)",
                         "workload": "plane-wave skewed chi log-uniform [1e-4, 1e3], 2^24 + 2^24",
-                        "ms_per_step": mixed["wall"] / args.steps * 1e3,
+                        "ms_per_step": mixed["wall"] / K * 1e3,
                         "p50_step_ms": float(np.percentile(mixed["step_ms"], 50)),
                         "p99_step_ms": float(np.percentile(mixed["step_ms"], 99)),
-                        "roofline_frac": bm / km / HBM_PEAK,
-                        "emitted_per_step": cm["emitted"] / args.steps,
-                        "converted_per_step": cm["converted"] / args.steps}
+                        "bulk_kernel_ms": mixed["bulk_ms"], "emit_kernel_ms": mixed["emit_ms"],
+                        "bulk_roofline_frac": bb / (mixed["bulk_ms"] * 1e-3) / HBM_PEAK,
+                        "emitted_per_step": pm("emitted"),
+                        "converted_per_step": pm("converted")}
+    if batched is not None:
+        cb = batched["counters"]
+        pb = lambda k: cb[k] / K
+        sb = stream_kernel_bytes(batched["n_total"], pb("processed"), pb("emitted"),
+                                 pb("converted")) + emit_kernel_bytes(pb("emitted"),
+                                                                      pb("converted"))
+        out["batched"] = {"value": cb["processed"] / batched["wall"], "unit": "particle-updates/s",
+                          "dtype": "f32 (f64 chi, optical depth and tails)",
+                          "workload": f"64 uneven tiles, {batched['n_total']} particles, "
+                                      "e-/e+/photon, static B, chi log-uniform [1e-3, 1e2]",
+                          "ms_per_step": batched["wall"] / K * 1e3,
+                          "p50_step_ms": float(np.percentile(batched["step_ms"], 50)),
+                          "p99_step_ms": float(np.percentile(batched["step_ms"], 99)),
+                          "launch_shape": batched["tuned"]["shape"],
+                          "autotune_ms": batched["tuned"].get("timings"),
+                          "step_roofline_frac": sb / (float(np.mean(batched["step_ms"])) * 1e-3)
+                                                / HBM_PEAK,
+                          "emitted_per_step": pb("emitted"),
+                          "converted_per_step": pb("converted")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -235,6 +235,23 @@ sfq_status sfq_plan_set_step(sfq_plan p, uint64_t step, void* stream);
 sfq_status sfq_plan_capture(sfq_plan p, int steps);
 sfq_status sfq_plan_replay(sfq_plan p, void* stream);
 
+/* ------------------------------------------------------------------------------------------ */
+/* Scratch sizing and kernel timing                                                            */
+/* ------------------------------------------------------------------------------------------ */
+/* Pre-sizes the handle's emitter queue (device scratch owned by the handle) for sfq_step calls
+ * of up to `max_particles` particles in up to `max_tiles` tiles with the current launch shape,
+ * so that such calls allocate nothing.  A larger step, or one after a change of launch shape,
+ * still grows the queue, which waits for the device.  SFQ_E_NOMEM if the allocation fails. */
+sfq_status sfq_reserve(sfq_handle h, uint64_t max_particles, int max_tiles);
+
+/* Kernel timing (instrumentation).  With enable = 1, every sfq_step and sfq_plan_launch on this
+ * handle records HIP events on its stream before the streaming kernel, between it and the
+ * emitter kernel, and after that (not inside sfq_plan_capture).  sfq_profile_read waits for the
+ * recorded events, returns the summed durations in ms of the streaming and emitter kernels and
+ * the number of steps timed since the previous read, and clears them.  Any output may be NULL. */
+sfq_status sfq_profile_enable(sfq_handle h, int enable);
+sfq_status sfq_profile_read(sfq_handle h, double* stream_ms, double* emit_ms, uint64_t* steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,6 +7,7 @@ compiles csrc/sfq.hip into libsfq.so next to this file (hipcc, --offload-arch=gf
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -17,6 +18,16 @@ LIB = os.path.join(HERE, "libsfq.so")
 SOURCES = [os.path.join(HERE, "csrc", "sfq.hip")]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources and the ABI header (identifies the kernels a profile was taken of)."""
+    h = hashlib.sha256()
+    for f in (*SOURCES, os.path.join(HERE, "csrc", "sfq_device.h"),
+              os.path.join(os.path.dirname(HERE), "include", "sfq.h")):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def hipcc() -> str:

@@ -697,6 +697,10 @@ constexpr size_t STAGING_BYTES = 1 << 20;
 
 }  // namespace
 
+struct ProfEvents {
+    hipEvent_t e[3];
+};
+
 struct sfq_ctx {
     int device = 0;
     int precision = SFQ_FP64, decision = SFQ_OPTICAL_DEPTH, blcfa = 0, bw_fast = 0;
@@ -716,6 +720,9 @@ struct sfq_ctx {
     // launch shape of the step kernel (tunable)
     int blocks_per_cu = 8;
     int chunk = 2048;
+    // kernel timing (sfq_profile_*): events around the two step kernels of each timed step
+    int prof = 0;
+    std::vector<ProfEvents> prof_used, prof_free;
 };
 
 struct sfq_plan_t;
@@ -838,6 +845,9 @@ static void release(sfq_ctx* h)
         if (s.host) (void)hipHostFree(s.host);
         if (s.dev) (void)hipFree(s.dev);
     }
+    for (auto* v : {&h->prof_used, &h->prof_free})
+        for (auto& pe : *v)
+            for (auto& e : pe.e) (void)hipEventDestroy(e);
     if (h->d_queue) (void)hipFree(h->d_queue);
     if (h->d_tab64) (void)hipFree(h->d_tab64);
     if (h->d_tab32) (void)hipFree(h->d_tab32);
@@ -1153,26 +1163,43 @@ static void fill_args(const sfq_ctx* h, const sfq_step_desc* desc, StepArgs& A, 
     A.counters = desc->counters;
 }
 
-static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, hipStream_t st)
+// A set of timing events for one step (caller holds h->mu); nullptr when timing is off or the
+// events cannot be created (timing is instrumentation: it never fails a step).
+static ProfEvents* prof_events(sfq_ctx* h)
+{
+    if (!h->prof) return nullptr;
+    if (h->prof_free.empty()) {
+        ProfEvents pe{};
+        for (auto& e : pe.e)
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->prof_free.push_back(pe);
+    }
+    h->prof_used.push_back(h->prof_free.back());
+    h->prof_free.pop_back();
+    return &h->prof_used.back();
+}
+
+static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, hipStream_t st,
+                                const ProfEvents* pe = nullptr)
 {
     const dim3 g(grid), b(STEP_BLOCK);
+    if (pe) (void)hipEventRecord(pe->e[0], st);
     if (h->precision == SFQ_MIXED) {
-        if (h->blcfa) {
-            hipLaunchKernelGGL((bulk_kernel<true, true>), g, b, 0, st, A);
-            hipLaunchKernelGGL((emit_kernel<true, true>), g, b, 0, st, A);
-        } else {
-            hipLaunchKernelGGL((bulk_kernel<true, false>), g, b, 0, st, A);
-            hipLaunchKernelGGL((emit_kernel<true, false>), g, b, 0, st, A);
-        }
+        if (h->blcfa) hipLaunchKernelGGL((bulk_kernel<true, true>), g, b, 0, st, A);
+        else hipLaunchKernelGGL((bulk_kernel<true, false>), g, b, 0, st, A);
     } else {
-        if (h->blcfa) {
-            hipLaunchKernelGGL((bulk_kernel<false, true>), g, b, 0, st, A);
-            hipLaunchKernelGGL((emit_kernel<false, true>), g, b, 0, st, A);
-        } else {
-            hipLaunchKernelGGL((bulk_kernel<false, false>), g, b, 0, st, A);
-            hipLaunchKernelGGL((emit_kernel<false, false>), g, b, 0, st, A);
-        }
+        if (h->blcfa) hipLaunchKernelGGL((bulk_kernel<false, true>), g, b, 0, st, A);
+        else hipLaunchKernelGGL((bulk_kernel<false, false>), g, b, 0, st, A);
     }
+    if (pe) (void)hipEventRecord(pe->e[1], st);
+    if (h->precision == SFQ_MIXED) {
+        if (h->blcfa) hipLaunchKernelGGL((emit_kernel<true, true>), g, b, 0, st, A);
+        else hipLaunchKernelGGL((emit_kernel<true, false>), g, b, 0, st, A);
+    } else {
+        if (h->blcfa) hipLaunchKernelGGL((emit_kernel<false, true>), g, b, 0, st, A);
+        else hipLaunchKernelGGL((emit_kernel<false, false>), g, b, 0, st, A);
+    }
+    if (pe) (void)hipEventRecord(pe->e[2], st);
 }
 
 struct sfq_plan_t {
@@ -1199,14 +1226,81 @@ static void plan_release(sfq_plan_t* p)
     delete p;
 }
 
-static void plan_enqueue(sfq_plan_t* p, hipStream_t st)
+static void plan_enqueue(sfq_plan_t* p, hipStream_t st, const ProfEvents* pe = nullptr)
 {
     if (p->zero_counts) hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, st, p->A.prod_counts);
-    launch_step_kernels(p->h, p->A, p->grid, st);
+    launch_step_kernels(p->h, p->A, p->grid, st, pe);
     hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, p->d_step);
 }
 
+// Grows the handle's emitter queue to hold a step of shape qs (caller holds h->mu).  Growing
+// waits for the device, since in-flight steps may still use the old queue.
+static sfq_status ensure_queue(sfq_ctx* h, const QueueShape& qs, const char* who)
+{
+    if (qs.entries <= h->queue_entries && qs.grid <= h->queue_blocks) return SFQ_OK;
+    QueueShape want = qs;
+    want.entries = std::max<uint64_t>(qs.entries, h->queue_entries);
+    want.grid = std::max(qs.grid, h->queue_blocks);
+    if (h->d_queue) {
+        HIP_TRY(h, hipDeviceSynchronize());
+        HIP_TRY(h, hipFree(h->d_queue));
+        h->d_queue = nullptr;
+        h->queue_entries = 0;
+        h->queue_blocks = 0;
+    }
+    if (hipMalloc(&h->d_queue, queue_bytes(want)) != hipSuccess) {
+        h->d_queue = nullptr;
+        return fail(h, SFQ_E_NOMEM, std::string(who) + ": cannot allocate the emitter queue");
+    }
+    h->queue_entries = want.entries;
+    h->queue_blocks = want.grid;
+    return SFQ_OK;
+}
+
 extern "C" {
+
+sfq_status sfq_reserve(sfq_handle h, uint64_t max_particles, int max_tiles)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_reserve: NULL handle");
+    if (max_tiles < 1 || max_tiles > SFQ_MAX_TILES)
+        return fail(h, SFQ_E_ARG, "sfq_reserve: max_tiles in [1, SFQ_MAX_TILES]");
+    std::lock_guard<std::mutex> lock(h->mu);
+    const uint64_t nch = (max_particles + h->chunk - 1) / h->chunk + (uint64_t)max_tiles;
+    if (nch >= (1ull << 31)) return fail(h, SFQ_E_CAPACITY, "sfq_reserve: too many particles");
+    HIP_TRY(h, hipSetDevice(h->device));
+    return ensure_queue(h, queue_shape(h, (int)nch, h->blocks_per_cu, h->chunk), "sfq_reserve");
+}
+
+sfq_status sfq_profile_enable(sfq_handle h, int enable)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_profile_enable: NULL handle");
+    std::lock_guard<std::mutex> lock(h->mu);
+    h->prof = enable ? 1 : 0;
+    return SFQ_OK;
+}
+
+sfq_status sfq_profile_read(sfq_handle h, double* stream_ms, double* emit_ms, uint64_t* steps)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_profile_read: NULL handle");
+    std::lock_guard<std::mutex> lock(h->mu);
+    HIP_TRY(h, hipSetDevice(h->device));
+    double a = 0, b = 0;
+    const uint64_t n = h->prof_used.size();
+    for (auto& pe : h->prof_used) {
+        HIP_TRY(h, hipEventSynchronize(pe.e[2]));
+        float t1 = 0, t2 = 0;
+        HIP_TRY(h, hipEventElapsedTime(&t1, pe.e[0], pe.e[1]));
+        HIP_TRY(h, hipEventElapsedTime(&t2, pe.e[1], pe.e[2]));
+        a += t1;
+        b += t2;
+    }
+    h->prof_free.insert(h->prof_free.end(), h->prof_used.begin(), h->prof_used.end());
+    h->prof_used.clear();
+    if (stream_ms) *stream_ms = a;
+    if (emit_ms) *emit_ms = b;
+    if (steps) *steps = n;
+    return SFQ_OK;
+}
 
 sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
 {
@@ -1221,20 +1315,9 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     if (nchunks == 0) return SFQ_OK;
     HIP_TRY(h, hipSetDevice(h->device));
     const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk);
-    if (qs.entries > h->queue_entries || qs.grid > h->queue_blocks) {
-        if (h->d_queue) {
-            HIP_TRY(h, hipDeviceSynchronize());
-            HIP_TRY(h, hipFree(h->d_queue));
-            h->d_queue = nullptr;
-            h->queue_entries = 0;
-            h->queue_blocks = 0;
-        }
-        if (hipMalloc(&h->d_queue, queue_bytes(qs)) != hipSuccess) {
-            h->d_queue = nullptr;
-            return fail(h, SFQ_E_NOMEM, "sfq_step: cannot allocate the emitter queue");
-        }
-        h->queue_entries = qs.entries;
-        h->queue_blocks = qs.grid;
+    {
+        const sfq_status q = ensure_queue(h, qs, "sfq_step");
+        if (q != SFQ_OK) return q;
     }
     // descriptors through a ring of pinned staging buffers
     Staging& S = h->staging[h->next_staging];
@@ -1264,7 +1347,7 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     A.chunk_off = (const uint32_t*)((char*)S.dev + off_pos);
     bind_queue(A, h->d_queue, bound);
     A.q_cap_per_block = qs.cap_per_block;
-    launch_step_kernels(h, A, qs.grid, (hipStream_t)stream);
+    launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, prof_events(h));
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
     return SFQ_OK;
@@ -1324,7 +1407,8 @@ sfq_status sfq_plan_launch(sfq_plan p, void* stream)
 {
     if (!p) return fail(nullptr, SFQ_E_STATE, "sfq_plan_launch: NULL plan");
     HIP_TRY(p->h, hipSetDevice(p->h->device));
-    plan_enqueue(p, (hipStream_t)stream);
+    std::lock_guard<std::mutex> lock(p->h->mu);
+    plan_enqueue(p, (hipStream_t)stream, prof_events(p->h));
     HIP_TRY(p->h, hipGetLastError());
     return SFQ_OK;
 }

@@ -30,7 +30,8 @@ STATUS = {0: "SFQ_OK", 1: "SFQ_E_ARG", 2: "SFQ_E_STATE", 3: "SFQ_E_NOMEM", 4: "S
 EXPORTS = ("sfq_create", "sfq_destroy", "sfq_last_error", "sfq_units", "sfq_chi", "sfq_rates",
            "sfq_sample_photon", "sfq_sample_pair", "sfq_philox", "sfq_init_optical_depth",
            "sfq_step", "sfq_set_launch", "sfq_get_launch", "sfq_plan_create", "sfq_plan_destroy",
-           "sfq_plan_launch", "sfq_plan_set_step", "sfq_plan_capture", "sfq_plan_replay")
+           "sfq_plan_launch", "sfq_plan_set_step", "sfq_plan_capture", "sfq_plan_replay",
+           "sfq_reserve", "sfq_profile_enable", "sfq_profile_read")
 
 
 class Config(C.Structure):
@@ -117,6 +118,13 @@ def load(path: str = LIB_PATH):
     L.sfq_plan_capture.argtypes = [vp, C.c_int]
     L.sfq_plan_replay.restype = st
     L.sfq_plan_replay.argtypes = [vp, vp]
+    L.sfq_reserve.restype = st
+    L.sfq_reserve.argtypes = [vp, u64, C.c_int]
+    L.sfq_profile_enable.restype = st
+    L.sfq_profile_enable.argtypes = [vp, C.c_int]
+    L.sfq_profile_read.restype = st
+    L.sfq_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_uint64)]
     _lib = L
     return L
 
@@ -190,6 +198,20 @@ class Handle:
         a, b = C.c_int(), C.c_int()
         self._check(self._L.sfq_get_launch(self._h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def reserve(self, max_particles: int, max_tiles: int = 1):
+        """Pre-size the emitter queue so steps within these limits allocate nothing."""
+        self._check(self._L.sfq_reserve(self._h, max_particles, max_tiles))
+
+    def profile(self, enable: bool = True):
+        """Start/stop timing the two step kernels of every step with HIP events."""
+        self._check(self._L.sfq_profile_enable(self._h, int(enable)))
+
+    def profile_read(self):
+        """(stream-kernel ms, emitter-kernel ms, steps) summed since the previous read."""
+        a, b, n = C.c_double(), C.c_double(), C.c_uint64()
+        self._check(self._L.sfq_profile_read(self._h, C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
 
     # ---- batched calls ------------------------------------------------------------------------
     def chi(self, species, p, E, B, stream=None):

@@ -136,3 +136,31 @@ def test_autotune_restores_state_and_picks_a_candidate(dev, tmp_path):
     torch.cuda.synchronize()
     assert same(state(tuned), state(ref))  # launch shapes never change results
     assert same(product_set(pt), product_set(pr))
+
+
+def test_reserve_and_kernel_timing(dev):
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    h.reserve(50000, 4)
+    base = make_tiles(dev, h)
+    a, b = clone_tiles(base), clone_tiles(base)
+    pa, pb = sfq.ProductBuffers.empty(20000, 20000, dev), sfq.ProductBuffers.empty(20000, 20000, dev)
+    ca, cb = sfq.Counters(dev), sfq.Counters(dev)
+    h.profile(True)
+    for s in range(3):
+        h.step(a, seed=5, step=s, products=pa, counters=ca)
+    plan = h.plan(b, seed=5, step=0, products=pb, counters=cb, zero_product_counts=False)
+    for s in range(3):
+        plan.launch()
+    bulk_ms, emit_ms, n = h.profile_read()
+    assert n == 6 and bulk_ms > 0 and emit_ms > 0
+    assert h.profile_read() == (0.0, 0.0, 0)  # cleared by the read
+    h.profile(False)
+    h.step(a, seed=5, step=3, products=pa, counters=ca)
+    torch.cuda.synchronize()
+    assert h.profile_read()[2] == 0
+    plan.launch()
+    torch.cuda.synchronize()
+    assert same(state(a), state(b)) and same(product_set(pa), product_set(pb))
+    plan.close()
+    with pytest.raises(sfq.SFQError):
+        h.reserve(10, 0)
