@@ -134,7 +134,8 @@ sfq_status sfq_init_optical_depth(sfq_handle h, size_t n, const uint64_t* uid, u
  * elements unless stated. */
 typedef struct {
     int32_t species;           /* sfq_species                                                     */
-    int32_t reserved;          /* must be 0                                                       */
+    int32_t product_set;       /* with desc->nsets > 0: index of the sfq_product_set receiving
+                                  this tile's products; otherwise must be 0                       */
     uint64_t n;                /* number of particles                                             */
     double *px, *py, *pz;      /* momentum, updated in place by recoil.  With blcfa leptons this
                                   is the pushed momentum p_L^{(n+1/2)} of Sec. 5                  */
@@ -152,6 +153,9 @@ typedef struct {
     uint8_t* just_created;
     double* chi_out;           /* nullable: chi of every alive particle                          */
     double* rate_out;          /* nullable: rate W of every alive particle                       */
+    uint64_t step_offset;      /* this tile's draws use step index desc->step + step_offset
+                                  (mod 2^32): lets one launch advance tiles that are at different
+                                  steps of their own simulations                                  */
 } sfq_tile;
 
 /* Product buffers of one species (device SoA arrays of `capacity` elements). */
@@ -173,11 +177,22 @@ typedef struct {
     unsigned long long reserved;
 } sfq_counters;
 
+/* Product buffers and their append counters, one set per owner (e.g. per simulation when one
+ * step serves several): lets a single launch write every tile's products into its owner's own
+ * buffers. */
+typedef struct {
+    sfq_products photons, electrons, positrons;
+    unsigned long long* product_counts; /* device [3], as sfq_step_desc.product_counts          */
+} sfq_product_set;
+
 typedef struct {
     uint64_t seed;             /* Philox key                                                      */
-    uint64_t step;             /* step index: Philox counter word 2 (mod 2^32)                    */
+    uint64_t step;             /* step index: Philox counter word 2 (mod 2^32), plus each tile's
+                                  step_offset                                                     */
     int32_t ntiles;            /* 1 .. SFQ_MAX_TILES                                              */
-    int32_t reserved;
+    int32_t nsets;             /* 0: products go to the buffers below; 1 .. SFQ_MAX_TILES: each
+                                  tile's products go to product_sets[tile.product_set] and the
+                                  buffers and counts below are ignored                           */
     const sfq_tile* tiles;     /* HOST array of ntiles tile descriptors                           */
     sfq_products photons;      /* Compton photons                                                 */
     sfq_products electrons;    /* Breit-Wheeler electrons                                         */
@@ -186,6 +201,7 @@ typedef struct {
                                   the buffers; products are appended there and the counts grow
                                   (beyond capacity too: the final count is the size needed)      */
     sfq_counters* counters;    /* device, accumulated                                             */
+    const sfq_product_set* product_sets; /* HOST array of nsets sets (copied by the call)         */
 } sfq_step_desc;
 
 #define SFQ_MAX_TILES 4096

@@ -76,6 +76,8 @@ struct StepArgs {
     sfq_products prod[3];       // photons, electrons, positrons
     unsigned long long* prod_counts;
     sfq_counters* counters;
+    const sfq_product_set* sets; // nsets > 0: per-tile product destinations (device copy)
+    int nsets;
 };
 
 enum { CNT_PROCESSED, CNT_EMITTED, CNT_CONVERTED, CNT_REJECTED, CNT_OOD, CNT_CLAMPED, CNT_OVERFLOW,
@@ -226,6 +228,29 @@ __device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* c
     return base + (unsigned long long)__popcll(below);
 }
 
+// Slots in per-owner product buffers: the lanes of a wave that want a slot are grouped by their
+// set index (usually one or two distinct sets per wave) and each group takes its slots with one
+// atomic.  Every lane of the wave must call this (the loop is wave-uniform).
+__device__ __forceinline__ unsigned long long keyed_reserve(const sfq_product_set* sets,
+                                                            int species, int key, bool want)
+{
+    unsigned long long pending = __ballot(want);
+    const int lane = lane_id();
+    unsigned long long slot = 0;
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int lk = __shfl(key, leader);
+        const unsigned long long m = __ballot(want && key == lk);
+        unsigned long long base = 0;
+        if (lane == leader)
+            base = atomicAdd(&sets[lk].product_counts[species], (unsigned long long)__popcll(m));
+        base = __shfl(base, leader);
+        if ((m >> lane) & 1ull) slot = base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
+        pending &= ~m;
+    }
+    return slot;
+}
+
 // =============================================================================================
 // The step: a streaming kernel over all tiles and an emitter kernel over its compacted queue
 // =============================================================================================
@@ -287,11 +312,12 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepAr
     unsigned long long c_proc = 0, c_ood = 0;
     const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
     const double dt = A.ph.dt;
-    const uint32_t step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
+    const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
 
     for (int c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
         const int t = find_tile(A.chunk_off, A.ntiles, c);
         const sfq_tile T = A.tiles[t];
+        const uint32_t step = base_step + (uint32_t)T.step_offset;
         const uint64_t start = (uint64_t)(c - (int)A.chunk_off[t]) * (uint64_t)A.chunk;
         const uint64_t end = min(start + (uint64_t)A.chunk, T.n);
         const bool photon = (T.species == SFQ_PHOTON);
@@ -423,14 +449,15 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
     if (tid < CNT_N) s_cnt[tid] = 0;
     const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
     const unsigned nl = A.q_count[2 * blockIdx.x], np = A.q_count[2 * blockIdx.x + 1];
-    const uint32_t step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
+    const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
     // product slots of the whole block, reserved once: one photon per lepton emitter and one
     // electron-positron pair per converting photon (beyond-LCFA rejections leave no product, so
-    // that mode reserves per wave instead)
+    // that mode reserves per wave instead, and so do steps with per-tile product sets)
+    const bool multi = A.nsets > 0;
     if (tid == 0) {
-        s_base[0] = (!BLCFA && nl) ? atomicAdd(&A.prod_counts[0], (unsigned long long)nl) : 0;
-        s_base[1] = np ? atomicAdd(&A.prod_counts[1], (unsigned long long)np) : 0;
-        s_base[2] = np ? atomicAdd(&A.prod_counts[2], (unsigned long long)np) : 0;
+        s_base[0] = (!BLCFA && !multi && nl) ? atomicAdd(&A.prod_counts[0], (unsigned long long)nl) : 0;
+        s_base[1] = (!multi && np) ? atomicAdd(&A.prod_counts[1], (unsigned long long)np) : 0;
+        s_base[2] = (!multi && np) ? atomicAdd(&A.prod_counts[2], (unsigned long long)np) : 0;
     }
     __syncthreads();
     const unsigned total = nl + np;
@@ -446,7 +473,8 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
         const unsigned rank = pair ? e - nl : e;
         const uint64_t slot = pair ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
         uint64_t i = 0, uid = 0;
-        int t = 0;
+        uint32_t step = base_step;
+        int t = 0, pset = 0;
         double chi = 1.0, gamma = 1.0, r = 0.5, px = 0, py = 0, pz = 0;
         Draw d1{0, 0}, d2{0, 0};
         if (valid) {
@@ -458,6 +486,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
             py = A.q_py[slot];
             pz = A.q_pz[slot];
             uid = A.q_uid[slot];
+            step = base_step + (uint32_t)A.tiles[t].step_offset;
             d1 = philox_draw(A.seed, uid, step, SFQ_P_EMIT);
             d2 = philox_draw(A.seed, uid, step, SFQ_P_CHILD);
             r = uniform53(d1.a);
@@ -467,6 +496,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
         sample_coop<MIXED>(A.tb, valid, pair, chi, r, s, v, omv, ood);
         if (valid) {
             const sfq_tile& T = A.tiles[t];
+            if (multi) pset = T.product_set;
             parent = uid;
             const double pn = sqrt(fma(px, px, fma(py, py, pz * pz)));
             if (!pair) {
@@ -521,10 +551,11 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
             c_ood += ood ? 1 : 0;
         }
         {
-            const unsigned long long k =
-                BLCFA ? wave_reserve(&A.prod_counts[0], want_ph) : s_base[0] + rank;
+            unsigned long long k;
+            if (multi) k = keyed_reserve(A.sets, 0, pset, want_ph);
+            else k = BLCFA ? wave_reserve(&A.prod_counts[0], want_ph) : s_base[0] + rank;
             if (want_ph) {
-                const sfq_products& P = A.prod[0];
+                const sfq_products P = multi ? A.sets[pset].photons : A.prod[0];
                 if (k < P.capacity) {
                     P.px[k] = pgx; P.py[k] = pgy; P.pz[k] = pgz; P.tau[k] = tau_a;
                     P.uid[k] = uid_a; P.parent[k] = parent;
@@ -533,16 +564,20 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
                 }
             }
         }
+        unsigned long long ke = s_base[1] + rank, kp = s_base[2] + rank;
+        if (multi) {
+            ke = keyed_reserve(A.sets, 1, pset, want_pair);
+            kp = keyed_reserve(A.sets, 2, pset, want_pair);
+        }
         if (want_pair) {
-            const unsigned long long ke = s_base[1] + rank, kp = s_base[2] + rank;
-            const sfq_products& E = A.prod[1];
+            const sfq_products E = multi ? A.sets[pset].electrons : A.prod[1];
             if (ke < E.capacity) {
                 E.px[ke] = pgx; E.py[ke] = pgy; E.pz[ke] = pgz; E.tau[ke] = tau_a;
                 E.uid[ke] = uid_a; E.parent[ke] = parent;
             } else {
                 ++c_over;
             }
-            const sfq_products& P = A.prod[2];
+            const sfq_products P = multi ? A.sets[pset].positrons : A.prod[2];
             if (kp < P.capacity) {
                 P.px[kp] = pbx; P.py[kp] = pby; P.pz[kp] = pbz; P.tau[kp] = tau_b;
                 P.uid[kp] = uid_b; P.parent[kp] = parent;
@@ -561,6 +596,12 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
 __global__ void zero_counts_kernel(unsigned long long* counts)
 {
     if (threadIdx.x < 3) counts[threadIdx.x] = 0;
+}
+
+__global__ void zero_set_counts_kernel(const sfq_product_set* sets, int nsets)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < 3 * nsets) sets[k / 3].product_counts[k % 3] = 0;
 }
 
 __global__ void advance_step_kernel(unsigned long long* step)
@@ -693,7 +734,7 @@ struct Staging {
 };
 
 constexpr int N_STAGING = 8;
-constexpr size_t STAGING_BYTES = 1 << 20;
+constexpr size_t STAGING_BYTES = 2 << 20;
 
 }  // namespace
 
@@ -1069,15 +1110,23 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
     if (!desc || !desc->tiles) return fail(h, SFQ_E_ARG, "sfq_step: NULL descriptor");
     if (desc->ntiles <= 0 || desc->ntiles > SFQ_MAX_TILES)
         return fail(h, SFQ_E_ARG, "sfq_step: ntiles out of range");
-    if (!desc->counters || !desc->product_counts)
-        return fail(h, SFQ_E_ARG, "sfq_step: NULL counters");
+    if (!desc->counters) return fail(h, SFQ_E_ARG, "sfq_step: NULL counters");
+    if (desc->nsets < 0 || desc->nsets > SFQ_MAX_TILES)
+        return fail(h, SFQ_E_ARG, "sfq_step: nsets out of range");
+    if (desc->nsets == 0 && !desc->product_counts)
+        return fail(h, SFQ_E_ARG, "sfq_step: NULL product counts");
+    if (desc->nsets > 0 && !desc->product_sets)
+        return fail(h, SFQ_E_ARG, "sfq_step: NULL product sets");
     const int nt = desc->ntiles;
     off.assign(nt + 1, 0);
     for (int t = 0; t < nt; ++t) {
         const sfq_tile& T = desc->tiles[t];
         const std::string tn = " (tile " + std::to_string(t) + ")";
-        if (T.species < 0 || T.species > 2 || T.reserved != 0)
+        if (T.species < 0 || T.species > 2)
             return fail(h, SFQ_E_ARG, "sfq_step: bad tile species" + tn);
+        if (desc->nsets == 0 ? T.product_set != 0
+                             : (T.product_set < 0 || T.product_set >= desc->nsets))
+            return fail(h, SFQ_E_ARG, "sfq_step: product set index out of range" + tn);
         if (T.n >= (1ull << 32))
             return fail(h, SFQ_E_CAPACITY, "sfq_step: tile larger than 2^32 - 1 particles");
         const bool photon = T.species == SFQ_PHOTON;
@@ -1100,11 +1149,19 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
             return fail(h, SFQ_E_CAPACITY, "sfq_step: too many particles in one step");
         off[t + 1] = off[t] + (uint32_t)nch;
     }
-    const sfq_products* P[3] = {&desc->photons, &desc->electrons, &desc->positrons};
-    for (int k = 0; k < 3; ++k)
-        if (P[k]->capacity > 0 &&
-            (!P[k]->px || !P[k]->py || !P[k]->pz || !P[k]->tau || !P[k]->uid || !P[k]->parent))
+    auto bad = [](const sfq_products& P) {
+        return P.capacity > 0 && (!P.px || !P.py || !P.pz || !P.tau || !P.uid || !P.parent);
+    };
+    if (desc->nsets == 0) {
+        if (bad(desc->photons) || bad(desc->electrons) || bad(desc->positrons))
             return fail(h, SFQ_E_ARG, "sfq_step: NULL product array");
+    } else {
+        for (int k = 0; k < desc->nsets; ++k) {
+            const sfq_product_set& S = desc->product_sets[k];
+            if (!S.product_counts || bad(S.photons) || bad(S.electrons) || bad(S.positrons))
+                return fail(h, SFQ_E_ARG, "sfq_step: NULL array in product set " + std::to_string(k));
+        }
+    }
     return SFQ_OK;
 }
 
@@ -1161,6 +1218,8 @@ static void fill_args(const sfq_ctx* h, const sfq_step_desc* desc, StepArgs& A, 
     A.prod[2] = desc->positrons;
     A.prod_counts = desc->product_counts;
     A.counters = desc->counters;
+    A.sets = nullptr;
+    A.nsets = desc->nsets;
 }
 
 // A set of timing events for one step (caller holds h->mu); nullptr when timing is off or the
@@ -1228,7 +1287,13 @@ static void plan_release(sfq_plan_t* p)
 
 static void plan_enqueue(sfq_plan_t* p, hipStream_t st, const ProfEvents* pe = nullptr)
 {
-    if (p->zero_counts) hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, st, p->A.prod_counts);
+    if (p->zero_counts) {
+        if (p->A.nsets > 0)
+            hipLaunchKernelGGL(zero_set_counts_kernel, dim3((3 * p->A.nsets + 255) / 256), dim3(256),
+                               0, st, p->A.sets, p->A.nsets);
+        else
+            hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, st, p->A.prod_counts);
+    }
     launch_step_kernels(p->h, p->A, p->grid, st, pe);
     hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, p->d_step);
 }
@@ -1323,8 +1388,9 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     Staging& S = h->staging[h->next_staging];
     h->next_staging = (h->next_staging + 1) % N_STAGING;
     const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
-    if (off_pos + (nt + 1) * sizeof(uint32_t) > STAGING_BYTES)
-        return fail(h, SFQ_E_CAPACITY, "sfq_step: too many tiles");
+    const size_t set_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
+    const size_t used = set_pos + (size_t)desc->nsets * sizeof(sfq_product_set);
+    if (used > STAGING_BYTES) return fail(h, SFQ_E_CAPACITY, "sfq_step: too many tiles");
     if (!S.host) {
         HIP_TRY(h, hipHostMalloc(&S.host, STAGING_BYTES, hipHostMallocDefault));
         HIP_TRY(h, hipMalloc(&S.dev, STAGING_BYTES));
@@ -1336,8 +1402,9 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     char* hb = (char*)S.host;
     memcpy(hb, desc->tiles, nt * sizeof(sfq_tile));
     memcpy(hb + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
-    HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, off_pos + (nt + 1) * sizeof(uint32_t),
-                              hipMemcpyHostToDevice, (hipStream_t)stream));
+    if (desc->nsets > 0)
+        memcpy(hb + set_pos, desc->product_sets, desc->nsets * sizeof(sfq_product_set));
+    HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, used, hipMemcpyHostToDevice, (hipStream_t)stream));
     // the queue shape must describe the allocation actually bound
     QueueShape bound = qs;
     bound.entries = h->queue_entries;
@@ -1345,6 +1412,7 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     fill_args(h, desc, A, nchunks, chunk);
     A.tiles = (const sfq_tile*)S.dev;
     A.chunk_off = (const uint32_t*)((char*)S.dev + off_pos);
+    if (desc->nsets > 0) A.sets = (const sfq_product_set*)((char*)S.dev + set_pos);
     bind_queue(A, h->d_queue, bound);
     A.q_cap_per_block = qs.cap_per_block;
     launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, prof_events(h));
@@ -1370,7 +1438,9 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     HIP_TRY(h, hipSetDevice(h->device));
     const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk);
     const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
-    const size_t step_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 255) & ~(size_t)255;
+    const size_t set_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
+    const size_t step_pos =
+        (set_pos + (size_t)desc->nsets * sizeof(sfq_product_set) + 255) & ~(size_t)255;
     const size_t q_pos = step_pos + 256;
     sfq_plan_t* p = new sfq_plan_t();
     p->h = h;
@@ -1383,6 +1453,8 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     std::vector<char> hostbuf(step_pos + 8, 0);
     memcpy(hostbuf.data(), desc->tiles, nt * sizeof(sfq_tile));
     memcpy(hostbuf.data() + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
+    if (desc->nsets > 0)
+        memcpy(hostbuf.data() + set_pos, desc->product_sets, desc->nsets * sizeof(sfq_product_set));
     const unsigned long long step0 = desc->step;
     memcpy(hostbuf.data() + step_pos, &step0, 8);
     if (hipMemcpy(p->d_mem, hostbuf.data(), step_pos + 8, hipMemcpyHostToDevice) != hipSuccess ||
@@ -1396,6 +1468,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     p->A.tiles = (const sfq_tile*)p->d_mem;
     p->A.chunk_off = (const uint32_t*)((char*)p->d_mem + off_pos);
     p->A.step_ptr = p->d_step;
+    if (desc->nsets > 0) p->A.sets = (const sfq_product_set*)((char*)p->d_mem + set_pos);
     bind_queue(p->A, (char*)p->d_mem + q_pos, qs);
     *out = p;
     return SFQ_OK;

@@ -140,3 +140,61 @@ def tiles(ntiles: int = 64, seed: int = SEED_TILES, scale: float = 1.0):
         n = max(1, int(n * scale))
         out.append(plain_compton(n, seed=seed * 1000 + k, species=int(sp)))
     return out
+
+
+# ------------------------------------------------------------------------------------------------
+# The same counter-based draws on a torch device (for ensembles created on the GPU at run time,
+# e.g. by the serving harness).  uniforms_t reproduces uniforms() bit for bit; the workload
+# formulas below use torch's float64 functions, so they agree with the numpy versions to a few
+# ulp rather than exactly.
+# ------------------------------------------------------------------------------------------------
+def _s64(v: int) -> int:
+    """A uint64 constant as the int64 with the same bits."""
+    v &= 0xFFFFFFFFFFFFFFFF
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+_C1, _C2, _GOLD = _s64(0xBF58476D1CE4E5B9), _s64(0x94D049BB133111EB), _s64(0x9E3779B97F4A7C15)
+
+
+def _srl(z, k: int):
+    """Logical right shift of int64 bit patterns."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _mix_t(z):
+    z = (z ^ _srl(z, 30)) * _C1
+    z = (z ^ _srl(z, 27)) * _C2
+    return z ^ _srl(z, 31)
+
+
+def uniforms_t(seed: int, stream: int, idx):
+    """uniforms() for an int64 torch tensor of indices (on any device)."""
+    import torch
+
+    key = int(_mix(np.uint64((seed * 1000003 + stream * 7919) & 0xFFFFFFFFFFFFFFFF)))
+    z = _mix_t(idx * _GOLD + _s64(key))
+    return (_srl(z, 11).to(torch.float64) + 0.5) * 2.0 ** -53
+
+
+def ids_t(seed: int, idx):
+    return idx + (seed << 40)
+
+
+def plane_wave_t(n: int, device, seed: int = SEED_WAVE, species: int = ELECTRON,
+                 a_range=(10.0, 500.0), gamma_range=(1e2, 1e5)):
+    """plane_wave() generated on `device`: dict of (3, n) float64 tensors p, E, B, int64 uid, and
+    the field amplitude a and phase phi of each particle (E_y = B_z = a cos phi)."""
+    import torch
+
+    idx = torch.arange(n, dtype=torch.int64, device=device)
+    s0 = 10 * (species + 1)
+    lo, hi = math.log10(gamma_range[0]), math.log10(gamma_range[1])
+    gamma = torch.pow(10.0, lo + (hi - lo) * uniforms_t(seed, s0, idx))
+    pm = gamma if species == PHOTON else torch.sqrt((gamma - 1.0) * (gamma + 1.0))
+    a = a_range[0] + (a_range[1] - a_range[0]) * uniforms_t(seed, s0 + 1, idx)
+    phi = 2.0 * math.pi * uniforms_t(seed, s0 + 2, idx)
+    amp = a * torch.cos(phi)
+    z = torch.zeros_like(gamma)
+    return dict(species=species, p=torch.stack([-pm, z, z]), E=torch.stack([z, amp, z]),
+                B=torch.stack([z, z, amp]), uid=ids_t(seed + species, idx), a=a, phi=phi)

@@ -45,11 +45,12 @@ _P = C.c_void_p
 
 
 class Tile(C.Structure):
-    _fields_ = [("species", C.c_int32), ("reserved", C.c_int32), ("n", C.c_uint64),
+    _fields_ = [("species", C.c_int32), ("product_set", C.c_int32), ("n", C.c_uint64),
                 ("px", _P), ("py", _P), ("pz", _P), ("ex", _P), ("ey", _P), ("ez", _P),
                 ("bx", _P), ("by", _P), ("bz", _P), ("tau", _P), ("uid", _P), ("alive", _P),
                 ("px_prev", _P), ("py_prev", _P), ("pz_prev", _P), ("fperp", _P),
-                ("dfperp", _P), ("just_created", _P), ("chi_out", _P), ("rate_out", _P)]
+                ("dfperp", _P), ("just_created", _P), ("chi_out", _P), ("rate_out", _P),
+                ("step_offset", C.c_uint64)]
 
 
 class ProductsC(C.Structure):
@@ -57,11 +58,16 @@ class ProductsC(C.Structure):
                 ("capacity", C.c_uint64)]
 
 
+class ProductSetC(C.Structure):
+    _fields_ = [("photons", ProductsC), ("electrons", ProductsC), ("positrons", ProductsC),
+                ("product_counts", _P)]
+
+
 class StepDesc(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("step", C.c_uint64), ("ntiles", C.c_int32),
-                ("reserved", C.c_int32), ("tiles", C.POINTER(Tile)), ("photons", ProductsC),
+                ("nsets", C.c_int32), ("tiles", C.POINTER(Tile)), ("photons", ProductsC),
                 ("electrons", ProductsC), ("positrons", ProductsC), ("product_counts", _P),
-                ("counters", _P)]
+                ("counters", _P), ("product_sets", C.POINTER(ProductSetC))]
 
 
 COUNTER_NAMES = ("processed", "emitted", "converted", "blcfa_rejected", "out_of_domain",
@@ -269,29 +275,49 @@ class Handle:
         return out
 
     @staticmethod
-    def _desc(tiles, seed, step, products, counters):
+    def _desc(tiles, seed, step, products, counters, product_sets=None):
+        """Step descriptor.  With `product_sets` (a list of ProductBuffers), tile k's products go
+        to product_sets[tiles[k].product_set] and `products` may be None."""
         nt = len(tiles)
         if nt == 0 or nt > MAX_TILES:
             raise ValueError("1 <= len(tiles) <= MAX_TILES")
         arr = (Tile * nt)()
         for k, t in enumerate(tiles):
             arr[k] = t.to_c()
-        desc = StepDesc(seed=seed, step=step, ntiles=nt, reserved=0, tiles=arr,
-                        photons=products.photons.to_c(), electrons=products.electrons.to_c(),
-                        positrons=products.positrons.to_c(),
-                        product_counts=_ptr(products.counts), counters=_ptr(counters.t))
-        return desc, arr
+        if product_sets:
+            sets = (ProductSetC * len(product_sets))()
+            for k, pb in enumerate(product_sets):
+                sets[k] = ProductSetC(photons=pb.photons.to_c(), electrons=pb.electrons.to_c(),
+                                      positrons=pb.positrons.to_c(), product_counts=_ptr(pb.counts))
+            nsets = len(product_sets)
+        else:
+            if products is None:
+                raise ValueError("products or product_sets is required")
+            sets, nsets = None, 0
+            for t in tiles:
+                if t.product_set != 0:
+                    raise ValueError("product_set indices need product_sets")
+        none = ProductsC()
+        desc = StepDesc(seed=seed, step=step, ntiles=nt, nsets=nsets, tiles=arr,
+                        photons=products.photons.to_c() if products else none,
+                        electrons=products.electrons.to_c() if products else none,
+                        positrons=products.positrons.to_c() if products else none,
+                        product_counts=_ptr(products.counts) if products else None,
+                        counters=_ptr(counters.t), product_sets=sets)
+        return desc, (arr, sets)
 
     def step(self, tiles: Sequence["TileArrays"], *, seed: int, step: int,
-             products: "ProductBuffers", counters: "Counters", stream=None):
+             products: Optional["ProductBuffers"] = None, counters: "Counters",
+             product_sets: Optional[Sequence["ProductBuffers"]] = None, stream=None):
         """One Monte Carlo step over all tiles (one launch sequence on `stream`)."""
-        desc, _keep = self._desc(tiles, seed, step, products, counters)
+        desc, _keep = self._desc(tiles, seed, step, products, counters, product_sets)
         self._check(self._L.sfq_step(self._h, C.byref(desc), _stream(stream)))
 
-    def plan(self, tiles, *, seed: int, step: int, products: "ProductBuffers",
-             counters: "Counters", zero_product_counts: bool = True) -> "Plan":
+    def plan(self, tiles, *, seed: int, step: int, products: Optional["ProductBuffers"] = None,
+             counters: "Counters", zero_product_counts: bool = True,
+             product_sets: Optional[Sequence["ProductBuffers"]] = None) -> "Plan":
         return Plan(self, tiles, seed=seed, step=step, products=products, counters=counters,
-                    zero_product_counts=zero_product_counts)
+                    zero_product_counts=zero_product_counts, product_sets=product_sets)
 
 
 class Plan:
@@ -299,11 +325,12 @@ class Plan:
     index advancing on the device, optionally captured in a HIP graph."""
 
     def __init__(self, handle: Handle, tiles, *, seed, step, products, counters,
-                 zero_product_counts=True):
+                 zero_product_counts=True, product_sets=None):
         self._handle = handle
         self._L = handle._L
         self.tiles, self.products, self.counters = list(tiles), products, counters
-        desc, _keep = Handle._desc(self.tiles, seed, step, products, counters)
+        self.product_sets = list(product_sets) if product_sets else None
+        desc, _keep = Handle._desc(self.tiles, seed, step, products, counters, product_sets)
         p = C.c_void_p()
         handle._check(self._L.sfq_plan_create(handle._h, C.byref(desc), int(zero_product_counts),
                                               C.byref(p)))
@@ -357,6 +384,8 @@ class TileArrays:
     just_created: Optional[torch.Tensor] = None
     chi_out: Optional[torch.Tensor] = None
     rate_out: Optional[torch.Tensor] = None
+    product_set: int = 0
+    step_offset: int = 0
 
     def __post_init__(self):
         n = self.px.numel()
@@ -382,8 +411,9 @@ class TileArrays:
         return self.px.numel()
 
     def to_c(self) -> Tile:
-        t = Tile(species=self.species, reserved=0, n=self.n)
-        for nm, _ in Tile._fields_[3:]:
+        t = Tile(species=self.species, product_set=self.product_set, n=self.n,
+                 step_offset=self.step_offset)
+        for nm, _ in Tile._fields_[3:-1]:
             setattr(t, nm, _ptr(getattr(self, nm)))
         return t
 
