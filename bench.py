@@ -11,7 +11,9 @@ tiles (chi, rates, decisions, sampling, recoil, products).  Then, on the same GP
   * the MIXED form on the skewed-chi ensemble (chi log-uniform [1e-4, 1e3]);
   * the batched form: 64 uneven tiles of mixed species (sizes log-uniform 1e3..4e6, static-B
     geometry, chi log-uniform [1e-3, 1e2]), MIXED, launch shape from the autotuner, each step
-    one replay of a HIP graph captured from a plan.
+    one replay of a HIP graph captured from a plan;
+  * the served form: continuous batching of step requests from 8 clients' simulations with
+    beyond-LCFA electrons, admitted under an HBM budget (request latency p50/p99).
 
 Prints ONE JSON line: value = FP64 particle-updates/s over the timed steps; p50/p99 step
 latency; the roofline of the dominant (streaming) kernel from its own duration measured with HIP
@@ -160,6 +162,26 @@ def run_batched(steps, warmup, dev):
     return dict(wall=wall, step_ms=step_ms, counters=c, n_total=n_total, tuned=tuned)
 
 
+def run_served(dev, jobs_per_client=16, steps=40):
+    """Served form: 8 clients, Exp(2e6)-sized simulations (clamped to [1e4, 2e7]) arriving in a
+    burst, beyond-LCFA leptons, MIXED, admission under a 12 GiB budget, 2 lanes."""
+    import torch
+
+    from paper_2301_07684_amd import serve
+
+    warm = serve.Server(dev, hbm_budget=1 << 30, lanes=2)
+    warm.add_jobs(serve.workload(clients=2, jobs_per_client=1, steps=3, mean=1e5, hi=2e5))
+    warm.run()
+    warm.close()
+    srv = serve.Server(dev, hbm_budget=12 << 30, lanes=2)
+    srv.add_jobs(serve.workload(clients=8, jobs_per_client=jobs_per_client, steps=steps,
+                                think=0.002))
+    res = srv.run(time_limit=300)
+    srv.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(n_sample=24576):
     """The oracle as it stands on a bounded sample of the FP64 workload (all host cores)."""
     from oracle import oracle as O
@@ -224,6 +246,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -249,6 +272,9 @@ def main():
     if batched is not None:
         print(f"# batched form done: {batched['wall'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
+    served = None if args.no_served else run_served(dev)
+    if served is not None:
+        print(f"# served form done: {served['wall']:.2f} s", file=sys.stderr, flush=True)
 
     c = f64["counters"]
     K = args.steps
@@ -322,6 +348,22 @@ def main():
                                                 / HBM_PEAK,
                           "emitted_per_step": pb("emitted"),
                           "converted_per_step": pb("converted")}
+    if served is not None:
+        cs = served["counters"]
+        out["served"] = {"value": served["updates_per_s"], "unit": "particle-updates/s",
+                         "dtype": "f32 (f64 chi, optical depth, tails and beyond-LCFA state)",
+                         "workload": f"8 clients, {served['jobs']} simulations of Exp(2e6) "
+                                     "particles (clamped [1e4, 2e7], half electrons with "
+                                     "beyond-LCFA state, half photons), 40 steps each, burst "
+                                     "arrivals, 12 GiB HBM budget, 2 lanes",
+                         "p50_request_ms": served["p50_ms"], "p99_request_ms": served["p99_ms"],
+                         "requests": served["requests"], "batches": served["batches"],
+                         "mean_batch_requests": served["mean_batch"],
+                         "admission_wait_p50_ms": served["admission_wait_p50_ms"],
+                         "admission_wait_max_ms": served["admission_wait_max_ms"],
+                         "jobs_that_waited_for_memory": served["waited"],
+                         "wall_s": served["wall"], "emitted": cs["emitted"],
+                         "blcfa_rejected": cs["blcfa_rejected"], "converted": cs["converted"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -2,9 +2,12 @@
 
 Each step is checked on its own: the oracle receives exactly the GPU's inputs of that step
 (p^{(n-1/2)}, the pushed p_L^{(n+1/2)} and the stored F_perp / Delta F state), so the comparison
-does not depend on earlier steps.  Tolerances: chi, rates and the stored force state <= 1e-12
-relative; decisions identical outside a 1e-9 band; acceptance decisions identical; emitter
-energies after recoil <= 1e-9 relative to the pushed energy.
+does not depend on earlier steps.  Tolerances, FP64 form: chi, rates and the stored force state
+<= 1e-12 relative; decisions identical outside a 1e-9 band; acceptance decisions identical;
+emitter energies after recoil <= 1e-9 relative to the pushed energy.  MIXED form (the served
+configuration): chi and the force state as FP64 (they are FP64 in every form); rates <= 2e-5;
+decisions identical outside a 2e-5 band; at most two acceptance flips per step (the sampled
+energy, 2e-5 accurate, enters the acceptance test); recoil <= 2e-5 of the pushed energy.
 """
 import math
 
@@ -40,9 +43,16 @@ def kicks(n, step, scale):
     return np.stack([st * np.cos(ph), st * np.sin(ph), ct]) * mag
 
 
-def test_blcfa_steps_match_oracle(dev):
+TOLS = {sfq.FP64: dict(rate=1e-12, band=1e-9, recoil=1e-9, flips=0),
+        sfq.MIXED: dict(rate=2e-5, band=2e-5, recoil=2e-5, flips=2)}
+
+
+@pytest.mark.parametrize("precision", [sfq.FP64, sfq.MIXED])
+def test_blcfa_steps_match_oracle(dev, precision):
     n = 2048
-    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.LOCAL, blcfa=True)
+    tol = TOLS[precision]
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.LOCAL, blcfa=True,
+                   precision=precision)
     idx = np.arange(n)
     gamma = 10.0 ** (3 + 1.5 * inputs.uniforms(8, 0, idx))
     p = np.stack([gamma, np.zeros(n), np.zeros(n)])
@@ -74,7 +84,7 @@ def test_blcfa_steps_match_oracle(dev):
                            step=step)
         chi, rate = tile.chi_out.cpu().numpy(), tile.rate_out.cpu().numpy()
         assert np.allclose(chi, ref["chi"], rtol=1e-12, atol=0)
-        assert np.allclose(rate, ref["rate"], rtol=1e-12, atol=0)
+        assert np.allclose(rate, ref["rate"], rtol=tol["rate"], atol=0)
         # the component of F_perp along p_L cancels to ~0: compare against the force scale
         fscale = np.max(np.abs(ref["fperp"]))
         assert np.allclose(fperp.cpu().numpy(), ref["fperp"], rtol=1e-12, atol=1e-12 * fscale)
@@ -86,19 +96,20 @@ def test_blcfa_steps_match_oracle(dev):
             assert np.all(dfperp.cpu().numpy() == 0)
         # decisions outside the band
         r1 = np.array([O.uniform(O.draw(4, int(u), step, O.P_LOCAL)[0]) for u in uid.view(np.uint64)])
-        band = np.abs(ref["rate"] * h.dt - r1) <= 1e-9 * r1
+        band = np.abs(ref["rate"] * h.dt - r1) <= tol["band"] * r1
         k = prods.host_counts()[0]
         parents = prods.photons.parent[:k].cpu().numpy().view(np.uint64)
         emit_gpu = np.isin(uid.view(np.uint64), parents)
-        assert not np.any((emit_gpu != ref["emitted"].astype(bool)) & ~band)
-        assert abs(c["blcfa_rejected"] - int(ref["rejected"].sum())) <= int(band.sum())
+        flips = int(np.sum((emit_gpu != ref["emitted"].astype(bool)) & ~band))
+        assert flips <= tol["flips"], flips
+        assert abs(c["blcfa_rejected"] - int(ref["rejected"].sum())) <= int(band.sum()) + flips
         # recoil of the emitters and their photons
         pg = np.stack([t.cpu().numpy() for t in (tile.px, tile.py, tile.pz)])
         em = ref["emitted"].astype(bool) & emit_gpu
         g_push = np.sqrt(1 + np.sum(p_push ** 2, axis=0))
         g_gpu = np.sqrt(1 + np.sum(pg ** 2, axis=0))
         g_ref = np.sqrt(1 + np.sum(ref["p"] ** 2, axis=0))
-        assert np.all(np.abs(g_gpu[em] - g_ref[em]) <= 1e-9 * g_push[em])
+        assert np.all(np.abs(g_gpu[em] - g_ref[em]) <= tol["recoil"] * g_push[em])
         assert np.array_equal(pg[:, ~emit_gpu], p_push[:, ~emit_gpu])  # others untouched
         tot_emit += c["emitted"]
         tot_rej += c["blcfa_rejected"]
