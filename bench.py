@@ -41,19 +41,20 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_kernel_plane_wave_fp
 
 
 def stream_kernel_bytes(n_total, processed, emitted, converted):
-    """Algorithmic bytes of the streaming kernel for one step.  Every particle slot: its alive
-    flag (1 B).  Every live particle: p (24), E and B (48), uid (8), optical depth read (8).
-    Every live particle that does not emit: optical depth written back (8); emitters get a fresh
-    depth in the emitter kernel."""
-    return n_total + 88 * processed + 8 * (processed - emitted - converted)
+    """Algorithmic bytes of the streaming kernel for one step (optical-depth decisions).  Every
+    particle slot: its alive flag (1 B).  Every live particle: p (24), E and B (48) and the
+    optical depth (8) read.  Every live particle that does not emit: the optical depth written
+    back (8); emitters get a fresh depth in the emitter kernel.  The particle id is not needed
+    here: only emitters use it (emitter kernel)."""
+    return n_total + 80 * processed + 8 * (processed - emitted - converted)
 
 
 def emit_kernel_bytes(emitted, converted):
-    """Algorithmic bytes of the emitter kernel for one step.  A Compton emission writes the
-    emitter's momentum and optical depth (32) and one photon product (p 24, tau 8, uid 8,
-    parent 8 = 48).  A conversion writes the photon's alive flag (1) and two lepton products
-    (96)."""
-    return 80 * emitted + 97 * converted
+    """Algorithmic bytes of the emitter kernel for one step.  A Compton emission reads the
+    emitter's id (8) and writes its momentum and optical depth (32) and one photon product
+    (p 24, tau 8, uid 8, parent 8 = 48).  A conversion reads the photon's id (8) and writes its
+    alive flag (1) and two lepton products (96)."""
+    return 88 * emitted + 105 * converted
 
 
 def device_tiles(dev, sfq, h, workloads):

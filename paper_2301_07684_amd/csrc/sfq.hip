@@ -96,7 +96,7 @@ __device__ __forceinline__ double rate_lepton(const void* rad, const Physics& ph
         return (double)((float)ph.k_rate * (float)chi / (float)gamma * wt);
     }
     const double wt = wtilde_rad((const double*)rad, chi, ood);
-    return ph.k_rate * chi / gamma * wt;
+    return ph.k_rate * chi * rcp_nr(gamma) * wt;
 }
 
 template <bool MIXED>
@@ -109,7 +109,7 @@ __device__ __forceinline__ double rate_photon(const void* pair, const Physics& p
         return (double)((float)ph.k_rate / (float)gamma * wt);
     }
     const double wt = wtilde_pair((const double*)pair, chi, ood);
-    return ph.k_rate / gamma * wt;
+    return ph.k_rate * rcp_nr(gamma) * wt;
 }
 
 // Energy sampling for one lane; every lane of the wave must call it (cooperative table
@@ -195,22 +195,26 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 #ifndef SFQ_NT
 #define SFQ_NT 1
 #endif
+// (the pointers come from descriptors in memory, so they are cast to the global address space
+// to get global rather than flat memory instructions)
 template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p)
 {
+    const __attribute__((address_space(1))) T* g = (const __attribute__((address_space(1))) T*)p;
 #if SFQ_NT
-    return __builtin_nontemporal_load(p);
+    return __builtin_nontemporal_load(g);
 #else
-    return *p;
+    return *g;
 #endif
 }
 template <typename T>
 __device__ __forceinline__ void st_stream(T* p, T v)
 {
+    __attribute__((address_space(1))) T* g = (__attribute__((address_space(1))) T*)p;
 #if SFQ_NT
-    __builtin_nontemporal_store(v, p);
+    __builtin_nontemporal_store(v, g);
 #else
-    *p = v;
+    *g = v;
 #endif
 }
 
@@ -263,6 +267,48 @@ constexpr int STEP_BLOCK = 256;
 #define SFQ_EMIT_WAVES 3
 #endif
 
+// read as the alive flag of tiles that have no alive array
+__device__ const uint8_t k_alive_one[1] = {1};
+
+// A value that is the same in every lane, moved to scalar registers (the tile descriptor is
+// fetched with vector loads; keeping its pointers in vector registers would cost two per lane
+// each).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename P>
+__device__ __forceinline__ P* uniform_ptr(P* p)
+{
+    return (P*)uniform64((uint64_t)p);
+}
+
+__device__ __forceinline__ sfq_tile uniform_tile(const sfq_tile& src)
+{
+    sfq_tile T;
+    T.species = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)src.species);
+    T.product_set = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)src.product_set);
+    T.n = uniform64(src.n);
+    T.px = uniform_ptr(src.px); T.py = uniform_ptr(src.py); T.pz = uniform_ptr(src.pz);
+    T.ex = uniform_ptr(src.ex); T.ey = uniform_ptr(src.ey); T.ez = uniform_ptr(src.ez);
+    T.bx = uniform_ptr(src.bx); T.by = uniform_ptr(src.by); T.bz = uniform_ptr(src.bz);
+    T.tau = uniform_ptr(src.tau);
+    T.uid = uniform_ptr(src.uid);
+    T.alive = uniform_ptr(src.alive);
+    T.px_prev = uniform_ptr(src.px_prev); T.py_prev = uniform_ptr(src.py_prev);
+    T.pz_prev = uniform_ptr(src.pz_prev);
+    T.fperp = uniform_ptr(src.fperp);
+    T.dfperp = uniform_ptr(src.dfperp);
+    T.just_created = uniform_ptr(src.just_created);
+    T.chi_out = uniform_ptr(src.chi_out);
+    T.rate_out = uniform_ptr(src.rate_out);
+    T.step_offset = uniform64(src.step_offset);
+    return T;
+}
+
 __device__ __forceinline__ int find_tile(const uint32_t* off, int ntiles, int c)
 {
     int lo = 0, hi = ntiles - 1;
@@ -291,9 +337,15 @@ __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
 // Streaming pass: per alive particle gamma, chi (or the beyond-LCFA force update), the rate
 // from LDS-staged tables and the decision; emitters go to the block's queue slice through a
 // wave ballot + popcount prefix and one LDS atomic per wave.
-template <bool MIXED, bool BLCFA>
+//
+// Memory pattern: each iteration issues all loads of a particle as one group (the alive flag
+// was fetched one iteration earlier), so an iteration costs one memory round trip.  With
+// optical-depth decisions the particle id is not read here: only emitters need it, and the
+// emitter pass fetches it.
+template <bool MIXED, bool BLCFA, bool LOCAL>
 __global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepArgs A)
 {
+    static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
     using RT = typename std::conditional<MIXED, float, double>::type;
     __shared__ RT s_rad[RAD_SIZE];
     __shared__ RT s_pair[PAIR_SIZE];
@@ -315,91 +367,120 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepAr
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
 
     for (int c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
-        const int t = find_tile(A.chunk_off, A.ntiles, c);
-        const sfq_tile T = A.tiles[t];
+        const int t = __builtin_amdgcn_readfirstlane(find_tile(A.chunk_off, A.ntiles, c));
+        const sfq_tile T = uniform_tile(A.tiles[t]);
         const uint32_t step = base_step + (uint32_t)T.step_offset;
         const uint64_t start = (uint64_t)(c - (int)A.chunk_off[t]) * (uint64_t)A.chunk;
         const uint64_t end = min(start + (uint64_t)A.chunk, T.n);
         const bool photon = (T.species == SFQ_PHOTON);
         const bool blcfa = BLCFA && !photon;
+        // tiles without an alive array read a constant 1 instead (no branch)
+        const uint8_t* alive = T.alive ? T.alive : k_alive_one;
+        const uint64_t amask = T.alive ? ~0ull : 0ull;
+        // Every lane issues every load of an iteration in one group, the alive flag included
+        // (lanes past the end of the chunk read its last particle and drop the result): one
+        // memory round trip per iteration, with no load behind a data-dependent branch.  The
+        // price is reading the fields of dead particles.
         for (uint64_t base = start; base < end; base += STEP_BLOCK) {
             const uint64_t i = base + tid;
-            bool emit = false;
+            const uint64_t j = min(i, end - 1);
+            const uint8_t al = ld_stream(&alive[j & amask]);
+            bool live = false, emit = false;
             double chi = 0.0, gamma = 0.0, aux = 0.0, aux2 = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
             uint64_t quid = 0;
-            if (i < end && (T.alive == nullptr || ld_stream(&T.alive[i]) != 0)) {
-                ++c_proc;
-                bool ood = false;
-                double W;
-                if (!blcfa) {
-                    qx = ld_stream(&T.px[i]); qy = ld_stream(&T.py[i]); qz = ld_stream(&T.pz[i]);
-                    quid = ld_stream(&T.uid[i]);
-                    gamma_chi(photon, qx, qy, qz, ld_stream(&T.ex[i]), ld_stream(&T.ey[i]),
-                              ld_stream(&T.ez[i]), ld_stream(&T.bx[i]), ld_stream(&T.by[i]),
-                              ld_stream(&T.bz[i]), A.ph.lc_over_lr, gamma, chi);
-                    W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
-                               : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
-                    if (A.decision == SFQ_OPTICAL_DEPTH) {
-                        const double tau = ld_stream(&T.tau[i]) - W * dt;
-                        emit = tau < 0.0;
-                        if (!emit) st_stream(&T.tau[i], tau);  // emitters get a fresh depth later
-                    } else {
-                        const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
-                        emit = W * dt > uniform53(d.a);
-                    }
+            bool ood = false;
+            double W = 0.0;
+            if (!blcfa) {
+                qx = ld_stream(&T.px[j]); qy = ld_stream(&T.py[j]); qz = ld_stream(&T.pz[j]);
+                const double ex = ld_stream(&T.ex[j]), ey = ld_stream(&T.ey[j]),
+                             ez = ld_stream(&T.ez[j]);
+                const double bx = ld_stream(&T.bx[j]), by = ld_stream(&T.by[j]),
+                             bz = ld_stream(&T.bz[j]);
+                double tau0 = 0.0;
+                if (LOCAL) quid = ld_stream(&T.uid[j]);
+                else tau0 = ld_stream(&T.tau[j]);
+                // keep the whole load group ahead of the arithmetic: the first use of a loaded
+                // value waits for every outstanding memory operation (loads and stores share
+                // one counter here), so a use scheduled between the loads would split the group
+                __builtin_amdgcn_sched_barrier(0);
+                live = i < end && al != 0;
+                gamma_chi(photon, qx, qy, qz, ex, ey, ez, bx, by, bz, A.ph.lc_over_lr, gamma, chi);
+                W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
+                           : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+                if (!LOCAL) {
+                    const double tau = tau0 - W * dt;
+                    emit = live && tau < 0.0;
+                    if (live && !emit) st_stream(&T.tau[i], tau);  // emitters: fresh depth later
                 } else {
-                    // beyond-LCFA force update, Sec. 5 Eqs. (fl)-(condit)
-                    const uint64_t n = T.n;
-                    const double ux = T.px[i], uy = T.py[i], uz = T.pz[i];
-                    const double vx = T.px_prev[i], vy = T.py_prev[i], vz = T.pz_prev[i];
-                    qx = ux; qy = uy; qz = uz;
-                    quid = T.uid[i];
-                    const double flx = (ux - vx) / dt, fly = (uy - vy) / dt, flz = (uz - vz) / dt;
-                    const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
-                    const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
-                    gamma = sqrt(g2);
-                    const double fp = (flx * plx + fly * ply + flz * plz) / g2;
-                    const double Fx = flx - fp * plx, Fy = fly - fp * ply, Fz = flz - fp * plz;
-                    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-                    const double tc = A.ph.lc_over_lr;
-                    chi = tc * gamma * sqrt(F2);
-                    W = rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
-                    if (T.just_created[i]) {
-                        T.fperp[i] = Fx; T.fperp[n + i] = Fy; T.fperp[2 * n + i] = Fz;
-                        T.dfperp[i] = 0.0; T.dfperp[n + i] = 0.0; T.dfperp[2 * n + i] = 0.0;
-                        T.just_created[i] = 0;
-                    } else {
-                        const double ox = T.fperp[i], oy = T.fperp[n + i], oz = T.fperp[2 * n + i];
-                        const double qx = T.dfperp[i], qy = T.dfperp[n + i], qz = T.dfperp[2 * n + i];
-                        const double ax = Fx - ox, ay = Fy - oy, az = Fz - oz;
-                        const double d1x = ax / dt, d1y = ay / dt, d1z = az / dt;
-                        const double dt2 = dt * dt;
-                        const double d2x = (ax - qx) / dt2, d2y = (ay - qy) / dt2, d2z = (az - qz) / dt2;
-                        const double delta = tc * tc * ((d1x * d1x + d1y * d1y + d1z * d1z) +
-                                                        fabs(Fx * d2x + Fy * d2y + Fz * d2z));
-                        T.fperp[i] = Fx; T.fperp[n + i] = Fy; T.fperp[2 * n + i] = Fz;
-                        T.dfperp[i] = ax; T.dfperp[n + i] = ay; T.dfperp[2 * n + i] = az;
-                        const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
-                        const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
-                        emit = W * dt > uniform53(d.a);
-                        if (emit) {
-                            // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
-                            const double pu2 = ux * ux + uy * uy + uz * uz;
-                            aux2 = (pu2 - (g2 - 1.0)) / (sqrt(1.0 + pu2) + gamma);
-                            if (flag) {
-                                const double tau_ratio = 2.0 * PI * sqrt(F2 / delta);
-                                const double arg = chi / (8.0 * gamma) * tau_ratio;
-                                aux = 0.7 * gamma /
-                                      (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
-                                if (!(aux < 0.75 * gamma)) emit = false;  // Eq. (gammaLCFA) check
-                            } else if (chi > ZETA) {
-                                aux = 0.0;  // fields effectively constant: LCFA throughout
-                            } else {
-                                emit = false;
-                            }
+                    const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
+                    emit = live && W * dt > uniform53(d.a);
+                }
+            } else {
+                // beyond-LCFA force update, Sec. 5 Eqs. (fl)-(condit)
+                const uint64_t n = T.n;
+                const double ux = ld_stream(&T.px[j]), uy = ld_stream(&T.py[j]),
+                             uz = ld_stream(&T.pz[j]);
+                const double vx = ld_stream(&T.px_prev[j]), vy = ld_stream(&T.py_prev[j]),
+                             vz = ld_stream(&T.pz_prev[j]);
+                const double ox = ld_stream(&T.fperp[j]), oy = ld_stream(&T.fperp[n + j]),
+                             oz = ld_stream(&T.fperp[2 * n + j]);
+                const double rx = ld_stream(&T.dfperp[j]), ry = ld_stream(&T.dfperp[n + j]),
+                             rz = ld_stream(&T.dfperp[2 * n + j]);
+                const bool fresh = ld_stream(&T.just_created[j]) != 0;
+                quid = ld_stream(&T.uid[j]);
+                __builtin_amdgcn_sched_barrier(0);
+                live = i < end && al != 0;
+                qx = ux; qy = uy; qz = uz;
+                const double flx = (ux - vx) / dt, fly = (uy - vy) / dt, flz = (uz - vz) / dt;
+                const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
+                const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
+                gamma = sqrt(g2);
+                const double fp = (flx * plx + fly * ply + flz * plz) / g2;
+                const double Fx = flx - fp * plx, Fy = fly - fp * ply, Fz = flz - fp * plz;
+                const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+                const double tc = A.ph.lc_over_lr;
+                chi = tc * gamma * sqrt(F2);
+                W = rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+                if (live) {
+                    st_stream(&T.fperp[i], Fx); st_stream(&T.fperp[n + i], Fy);
+                    st_stream(&T.fperp[2 * n + i], Fz);
+                }
+                if (live && fresh) {
+                    st_stream(&T.dfperp[i], 0.0); st_stream(&T.dfperp[n + i], 0.0);
+                    st_stream(&T.dfperp[2 * n + i], 0.0);
+                    st_stream(&T.just_created[i], (uint8_t)0);
+                } else if (live) {
+                    const double ax = Fx - ox, ay = Fy - oy, az = Fz - oz;
+                    const double d1x = ax / dt, d1y = ay / dt, d1z = az / dt;
+                    const double dt2 = dt * dt;
+                    const double d2x = (ax - rx) / dt2, d2y = (ay - ry) / dt2, d2z = (az - rz) / dt2;
+                    const double delta = tc * tc * ((d1x * d1x + d1y * d1y + d1z * d1z) +
+                                                    fabs(Fx * d2x + Fy * d2y + Fz * d2z));
+                    st_stream(&T.dfperp[i], ax); st_stream(&T.dfperp[n + i], ay);
+                    st_stream(&T.dfperp[2 * n + i], az);
+                    const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
+                    const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
+                    emit = W * dt > uniform53(d.a);
+                    if (emit) {
+                        // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
+                        const double pu2 = ux * ux + uy * uy + uz * uz;
+                        aux2 = (pu2 - (g2 - 1.0)) / (sqrt(1.0 + pu2) + gamma);
+                        if (flag) {
+                            const double tau_ratio = 2.0 * PI * sqrt(F2 / delta);
+                            const double arg = chi / (8.0 * gamma) * tau_ratio;
+                            aux = 0.7 * gamma /
+                                  (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
+                            if (!(aux < 0.75 * gamma)) emit = false;  // Eq. (gammaLCFA) check
+                        } else if (chi > ZETA) {
+                            aux = 0.0;  // fields effectively constant: LCFA throughout
+                        } else {
+                            emit = false;
                         }
                     }
                 }
+            }
+            if (live) {
+                ++c_proc;
                 if (T.chi_out) T.chi_out[i] = chi;
                 if (T.rate_out) T.rate_out[i] = W;
                 c_ood += ood ? 1 : 0;
@@ -422,7 +503,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepAr
                     A.q_px[slot] = qx;
                     A.q_py[slot] = qy;
                     A.q_pz[slot] = qz;
-                    A.q_uid[slot] = quid;
+                    if (LOCAL) A.q_uid[slot] = quid;
                     if (blcfa) {
                         A.q_aux[slot] = aux;
                         A.q_aux2[slot] = aux2;
@@ -440,9 +521,10 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepAr
 // Emitter pass: block b samples the queue slice written by block b of the streaming pass, with
 // every lane busy: Philox draws, inverse-CDF tables, recoil and products (one global atomic per
 // wave and product buffer).
-template <bool MIXED, bool BLCFA>
+template <bool MIXED, bool BLCFA, bool LOCAL>
 __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepArgs A)
 {
+    static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
     __shared__ unsigned long long s_cnt[CNT_N];
     __shared__ unsigned long long s_base[3];
     const int tid = threadIdx.x;
@@ -485,7 +567,8 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
             px = A.q_px[slot];
             py = A.q_py[slot];
             pz = A.q_pz[slot];
-            uid = A.q_uid[slot];
+            // with optical-depth decisions the streaming pass did not read the id
+            uid = LOCAL ? A.q_uid[slot] : A.tiles[t].uid[i];
             step = base_step + (uint32_t)A.tiles[t].step_offset;
             d1 = philox_draw(A.seed, uid, step, SFQ_P_EMIT);
             d2 = philox_draw(A.seed, uid, step, SFQ_P_CHILD);
@@ -1243,21 +1326,23 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
 {
     const dim3 g(grid), b(STEP_BLOCK);
     if (pe) (void)hipEventRecord(pe->e[0], st);
-    if (h->precision == SFQ_MIXED) {
-        if (h->blcfa) hipLaunchKernelGGL((bulk_kernel<true, true>), g, b, 0, st, A);
-        else hipLaunchKernelGGL((bulk_kernel<true, false>), g, b, 0, st, A);
-    } else {
-        if (h->blcfa) hipLaunchKernelGGL((bulk_kernel<false, true>), g, b, 0, st, A);
-        else hipLaunchKernelGGL((bulk_kernel<false, false>), g, b, 0, st, A);
-    }
+    const bool mixed = h->precision == SFQ_MIXED, local = h->decision == SFQ_LOCAL;
+#define SFQ_LAUNCH_PAIR(K)                                                                     \
+    do {                                                                                       \
+        if (mixed) {                                                                           \
+            if (h->blcfa) hipLaunchKernelGGL((K<true, true, true>), g, b, 0, st, A);           \
+            else if (local) hipLaunchKernelGGL((K<true, false, true>), g, b, 0, st, A);        \
+            else hipLaunchKernelGGL((K<true, false, false>), g, b, 0, st, A);                  \
+        } else {                                                                               \
+            if (h->blcfa) hipLaunchKernelGGL((K<false, true, true>), g, b, 0, st, A);          \
+            else if (local) hipLaunchKernelGGL((K<false, false, true>), g, b, 0, st, A);       \
+            else hipLaunchKernelGGL((K<false, false, false>), g, b, 0, st, A);                 \
+        }                                                                                      \
+    } while (0)
+    SFQ_LAUNCH_PAIR(bulk_kernel);
     if (pe) (void)hipEventRecord(pe->e[1], st);
-    if (h->precision == SFQ_MIXED) {
-        if (h->blcfa) hipLaunchKernelGGL((emit_kernel<true, true>), g, b, 0, st, A);
-        else hipLaunchKernelGGL((emit_kernel<true, false>), g, b, 0, st, A);
-    } else {
-        if (h->blcfa) hipLaunchKernelGGL((emit_kernel<false, true>), g, b, 0, st, A);
-        else hipLaunchKernelGGL((emit_kernel<false, false>), g, b, 0, st, A);
-    }
+    SFQ_LAUNCH_PAIR(emit_kernel);
+#undef SFQ_LAUNCH_PAIR
     if (pe) (void)hipEventRecord(pe->e[2], st);
 }
 
