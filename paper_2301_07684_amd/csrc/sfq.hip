@@ -133,7 +133,7 @@ __device__ __forceinline__ void sample_coop(const Tables& tb, bool valid, bool p
     const int patch = q.patch + (pair ? N_INV_CHI * N_R_SEG : 0);  // pair patches follow
     bool need64 = true;
     if (MIXED) {
-        const float f = coop_patch_eval<float>(tb.phinv32, patch, (float)q.Xr, (float)q.Xc);
+        const float f = coop_patch_eval<float>(tb.phinv32, patch, (float)q.Xr, (float)q.Xc, valid);
         const float uf = (float)u;
         if (!pair) {
             const float xbar = q.upper ? expf(f) : (f * uf) * (f * uf) * (f * uf);
@@ -152,7 +152,8 @@ __device__ __forceinline__ void sample_coop(const Tables& tb, bool valid, bool p
         need64 = need64 && valid;
         if (__ballot(need64) == 0) return;
     }
-    const double f = coop_patch_eval<double>(tb.phinv, need64 ? patch : 0, q.Xr, q.Xc);
+    need64 = need64 && valid;
+    const double f = coop_patch_eval<double>(tb.phinv, patch, q.Xr, q.Xc, need64);
     if (!need64) return;
     if (!pair) {
         const double w = f * u;
@@ -259,9 +260,14 @@ __device__ __forceinline__ unsigned long long keyed_reserve(const sfq_product_se
 // The step: a streaming kernel over all tiles and an emitter kernel over its compacted queue
 // =============================================================================================
 constexpr int STEP_BLOCK = 256;
-// minimum waves per SIMD requested from the register allocator for the two step kernels
-#ifndef SFQ_BULK_WAVES
-#define SFQ_BULK_WAVES 4
+// minimum waves per SIMD requested from the register allocator for the two step kernels.  The
+// streaming kernel's register budget decides how many waves hide HBM latency: the beyond-LCFA
+// form needs 128 registers (4 waves), the FP64 LCFA form fits 96 (5 waves) and the mixed form
+// 80 (6 waves) without spills inside the particle loop.
+#ifdef SFQ_BULK_WAVES
+constexpr int bulk_waves(bool, bool) { return SFQ_BULK_WAVES; }
+#else
+constexpr int bulk_waves(bool mixed, bool blcfa) { return blcfa ? 4 : (mixed ? 6 : 5); }
 #endif
 #ifndef SFQ_EMIT_WAVES
 #define SFQ_EMIT_WAVES 3
@@ -343,7 +349,7 @@ __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
 // optical-depth decisions the particle id is not read here: only emitters need it, and the
 // emitter pass fetches it.
 template <bool MIXED, bool BLCFA, bool LOCAL>
-__global__ __launch_bounds__(STEP_BLOCK, SFQ_BULK_WAVES) void bulk_kernel(StepArgs A)
+__global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_kernel(StepArgs A)
 {
     static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
     using RT = typename std::conditional<MIXED, float, double>::type;

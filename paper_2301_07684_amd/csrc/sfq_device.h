@@ -155,6 +155,9 @@ __device__ __forceinline__ T clenshaw(const P* c, T X)
         const T bn = fma(X2, b1, T(c[k]) - b2);
         b2 = b1;
         b1 = bn;
+#ifdef SFQ_CLENSHAW_GROUP
+        if (k % SFQ_CLENSHAW_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
+#endif
     }
     return fma(X, b1, T(c[0]) - b2);
 }
@@ -218,6 +221,43 @@ __device__ __forceinline__ bool pair_segment(T chi, int& seg, T& X)
     return out;
 }
 
+// e^x for -708 < x <= 0: argument reduction x = n ln2 + r with |r| <= ln2/2 (Cody and Waite,
+// with ln2 split into two doubles) and the Taylor series of e^r to degree 13 by Horner's rule
+// (truncation below 1e-17); a few ulp.  Written out so that it needs few live registers.
+__device__ __forceinline__ double exp_nonpos(double x)
+{
+    constexpr double LOG2E = 1.4426950408889634;
+    constexpr double LN2_HI = 0.6931471805599453;
+    constexpr double LN2_LO = 2.3190468138462996e-17;
+    const double n = rint(x * LOG2E);
+    const double r = fma(-n, LN2_LO, fma(-n, LN2_HI, x));
+    double p = 1.0 / 6227020800.0;  // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
+__device__ __forceinline__ float exp_nonpos(float x) { return expf(x); }
+
+// chi^a in single precision, for the two-term asymptotic rates beyond the tables (chi > 2^16),
+// whose own truncation error there (~1e-6) is far above single-precision rounding
+template <typename T>
+__device__ __forceinline__ T pow_asym(T chi, float a)
+{
+    return T(exp2f(a * log2f((float)chi)));
+}
+
 // ---------------------------------------------------------------------------------------------
 // Rates.  `rad` and `pair` point to the (LDS-staged) coefficient tables.
 // ---------------------------------------------------------------------------------------------
@@ -229,7 +269,7 @@ __device__ __forceinline__ T wtilde_rad(const P* rad, T chi, bool* ood)
     T X;
     if (chi_segment(chi, seg, X)) {
         *ood = true;
-        return T(WRAD_ASYM_C1) * pow(chi, T(-1.0 / 3.0)) - T(WRAD_ASYM_C2) / chi;
+        return T(WRAD_ASYM_C1) * pow_asym(chi, -1.0f / 3.0f) - T(WRAD_ASYM_C2) / chi;
     }
     return clenshaw<RATE_DEG>(rad + seg * RATE_DEG, X);
 }
@@ -242,10 +282,10 @@ __device__ __forceinline__ T wtilde_pair(const P* pair, T chi, bool* ood)
     T X;
     if (pair_segment(chi, seg, X)) {
         *ood = true;
-        return T(WPAIR_ASYM_C) * pow(chi, T(2.0 / 3.0));
+        return T(WPAIR_ASYM_C) * pow_asym(chi, 2.0f / 3.0f);
     }
     const T P_ = clenshaw<RATE_DEG>(pair + seg * RATE_DEG, X);
-    return chi * P_ * exp(T(-8.0 / 3.0) / chi);
+    return chi * P_ * exp_nonpos(T(-8.0 / 3.0) / chi);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -353,32 +393,67 @@ __device__ __forceinline__ T cheb_T(int m, T x)
     return out;
 }
 
-// Cooperative evaluation of one patch per lane (all 64 lanes of the wave must call it).
-// In round b the 8 lanes of group g evaluate the patch of lane 8b + g: lane (g, m) loads
-// column m (8 coefficients, one per r index; the group reads 64 contiguous bytes per row),
-// runs Clenshaw's recurrence along r, weights by T_m(Xc) and the group sums over m.  Each
-// load instruction touches 8 rows of 8 different patches instead of 64 scattered lines.
+// Position of the k-th set bit (k from 0) of mask, by binary search on popcounts.
+__device__ __forceinline__ int kth_set_bit(unsigned long long mask, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const int c = __popcll(mask & ((1ull << w) - 1ull));
+        if (k >= c) {
+            k -= c;
+            mask >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
+// Cooperative evaluation of an 8 x 8 patch for every lane with `active` set.  In round b the
+// eight lane groups of eight take the next eight active lanes (in lane order): lane m of a
+// group loads column m of that lane's patch (eight lanes read a 64-byte row at once), runs
+// Clenshaw along the r variable and weights by T_m(Xc), and the group sums its columns with
+// xor shuffles.  A wave runs ceil(active lanes / 8) rounds (rounded up to even), so partly
+// filled waves and rare re-evaluations cost only what they use.  Every lane of the wave must
+// call it.
 template <typename T>
-__device__ __forceinline__ T coop_patch_eval(const T* table, int patch, T Xr, T Xc)
+__device__ __forceinline__ T coop_patch_eval(const T* table, int patch, T Xr, T Xc, bool active)
 {
     const int L = __lane_id();
     const int g = L >> 3, m = L & 7;
+    const unsigned long long mask = __ballot(active);
+    const int cnt = __popcll(mask);
+    const int rank = __popcll(mask & ((1ull << L) - 1ull));
+    const int first = cnt ? kth_set_bit(mask, 0) : 0;
     T result = T(0);
+    // two rounds per trip, so that two column loads are in flight together
 #pragma unroll 1
-    for (int b = 0; b < 8; ++b) {
-        const int src = (b << 3) | g;
-        const int pt = __shfl(patch, src);
-        const T xr = __shfl(Xr, src), xc = __shfl(Xc, src);
-        const T* c = table + (size_t)pt * INV_PATCH + m;
-        T col[INV_NR];
+    for (int b = 0; 8 * b < cnt; b += 2) {
+        const int k0 = 8 * b + g, k1 = k0 + 8;
+        const int s0 = k0 < cnt ? kth_set_bit(mask, k0) : first;  // spare groups redo a lane
+        const int s1 = k1 < cnt ? kth_set_bit(mask, k1) : first;
+        const int p0 = __shfl(patch, s0), p1 = __shfl(patch, s1);
+        const T xr0 = __shfl(Xr, s0), xc0 = __shfl(Xc, s0);
+        const T xr1 = __shfl(Xr, s1), xc1 = __shfl(Xc, s1);
+        const T* c0 = table + (size_t)p0 * INV_PATCH + m;
+        const T* c1 = table + (size_t)p1 * INV_PATCH + m;
+        T col0[INV_NR], col1[INV_NR];
 #pragma unroll
-        for (int i = 0; i < INV_NR; ++i) col[i] = c[i * INV_NC];
-        T v = clenshaw<INV_NR>(col, xr) * cheb_T(m, xc);
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        const T got = __shfl(v, (L & 7) << 3);
-        if ((L >> 3) == b) result = got;
+        for (int i = 0; i < INV_NR; ++i) {
+            col0[i] = c0[i * INV_NC];
+            col1[i] = c1[i * INV_NC];
+        }
+        T v0 = clenshaw<INV_NR>(col0, xr0) * cheb_T(m, xc0);
+        T v1 = clenshaw<INV_NR>(col1, xr1) * cheb_T(m, xc1);
+        v0 += __shfl_xor(v0, 1);
+        v1 += __shfl_xor(v1, 1);
+        v0 += __shfl_xor(v0, 2);
+        v1 += __shfl_xor(v1, 2);
+        v0 += __shfl_xor(v0, 4);
+        v1 += __shfl_xor(v1, 4);
+        const T got0 = __shfl(v0, (rank & 7) << 3), got1 = __shfl(v1, (rank & 7) << 3);
+        if (active && (rank >> 3) == b) result = got0;
+        if (active && (rank >> 3) == b + 1) result = got1;
     }
     return result;
 }
