@@ -72,7 +72,10 @@ struct StepArgs {
     double* q_aux;              // beyond-LCFA threshold gamma_{gamma,LCFA}
     double* q_aux2;             // beyond-LCFA: gamma of the pushed momentum minus gamma^{(n)}
     uint32_t* q_count;          // [2 grid]: lepton and photon emitters queued by each block
+    unsigned long long* q_proc; // [grid]: particles processed by each block of the streaming pass
+    unsigned long long* q_base; // [3 grid]: first product slot of each block (photons, e-, e+)
     uint64_t q_cap_per_block;
+    int grid;                   // blocks of the streaming and emitter kernels
     sfq_products prod[3];       // photons, electrons, positrons
     unsigned long long* prod_counts;
     sfq_counters* counters;
@@ -325,6 +328,22 @@ __device__ __forceinline__ int find_tile(const uint32_t* off, int ntiles, int c)
     return lo;
 }
 
+// Sum over the block (every thread gets it); s_tmp: at least one word of shared memory, which
+// the caller must not be using.
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long* s_tmp,
+                                                        unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    __syncthreads();
+    if (threadIdx.x == 0) s_tmp[0] = 0;
+    __syncthreads();
+    if (lane_id() == 0 && v) atomicAdd(&s_tmp[0], v);
+    __syncthreads();
+    const unsigned long long r = s_tmp[0];
+    __syncthreads();
+    return r;
+}
+
 __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
                                                    sfq_counters* global,
                                                    const unsigned long long (&vals)[CNT_N])
@@ -520,8 +539,68 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
     }
     __syncthreads();
     if (tid < 2) A.q_count[2 * blockIdx.x + tid] = s_qn[tid];
-    const unsigned long long vals[CNT_N] = {c_proc, 0, 0, 0, c_ood, 0, 0};
+    // the block's processed count goes to the queue for the scan kernel (no global atomic:
+    // thousands of blocks adding to one word serialise); the rare out-of-domain count is added
+    __shared__ unsigned long long s_tmp[1];
+    const unsigned long long proc = block_sum(s_tmp, c_proc);
+    if (tid == 0) A.q_proc[blockIdx.x] = proc;
+    const unsigned long long vals[CNT_N] = {0, 0, 0, 0, c_ood, 0, 0};
     block_add_counters(s_cnt, A.counters, vals);
+}
+
+// Between the two passes, one block: each streaming block's first product slot (exclusive
+// prefix sums of the queued emitters over blocks, from the current product counts), the new
+// product counts, and the step's processed / emitted / converted counters, each written once.
+// Every queued lepton emits and every queued photon converts, except that beyond-LCFA
+// rejections are only known in the emitter pass, which then reserves photon slots itself.
+constexpr int SCAN_BLOCK = 1024;
+
+__global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
+{
+    __shared__ unsigned long long s_l[SCAN_BLOCK], s_p[SCAN_BLOCK], s_n[SCAN_BLOCK];
+    const int tid = threadIdx.x, G = A.grid;
+    const int per = (G + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    const int lo = min(tid * per, G), hi = min(lo + per, G);
+    unsigned long long nl = 0, np = 0, proc = 0;
+    for (int b = lo; b < hi; ++b) {
+        nl += A.q_count[2 * b];
+        np += A.q_count[2 * b + 1];
+        proc += A.q_proc[b];
+    }
+    s_l[tid] = nl; s_p[tid] = np; s_n[tid] = proc;
+    __syncthreads();
+    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {  // inclusive scan (Hillis-Steele)
+        const unsigned long long a = tid >= off ? s_l[tid - off] : 0ull;
+        const unsigned long long b = tid >= off ? s_p[tid - off] : 0ull;
+        const unsigned long long c = tid >= off ? s_n[tid - off] : 0ull;
+        __syncthreads();
+        s_l[tid] += a; s_p[tid] += b; s_n[tid] += c;
+        __syncthreads();
+    }
+    const bool multi = A.nsets > 0;
+    const unsigned long long b0 = multi ? 0ull : A.prod_counts[0];
+    const unsigned long long b1 = multi ? 0ull : A.prod_counts[1];
+    const unsigned long long b2 = multi ? 0ull : A.prod_counts[2];
+    unsigned long long run_l = s_l[tid] - nl, run_p = s_p[tid] - np;
+    for (int b = lo; b < hi; ++b) {
+        A.q_base[3 * b] = b0 + run_l;
+        A.q_base[3 * b + 1] = b1 + run_p;
+        A.q_base[3 * b + 2] = b2 + run_p;
+        run_l += A.q_count[2 * b];
+        run_p += A.q_count[2 * b + 1];
+    }
+    __syncthreads();  // every read of the product counts happens before they are advanced
+    if (tid == 0) {
+        const unsigned long long tl = s_l[SCAN_BLOCK - 1], tp = s_p[SCAN_BLOCK - 1];
+        if (!multi) {
+            if (!A.blcfa) A.prod_counts[0] = b0 + tl;
+            A.prod_counts[1] = b1 + tp;
+            A.prod_counts[2] = b2 + tp;
+        }
+        atomicAdd(&A.counters->processed, s_n[SCAN_BLOCK - 1]);
+        if (!A.blcfa) atomicAdd(&A.counters->emitted, tl);
+        atomicAdd(&A.counters->converted, tp);
+    }
 }
 
 // Emitter pass: block b samples the queue slice written by block b of the streaming pass, with
@@ -538,15 +617,12 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
     const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
     const unsigned nl = A.q_count[2 * blockIdx.x], np = A.q_count[2 * blockIdx.x + 1];
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
-    // product slots of the whole block, reserved once: one photon per lepton emitter and one
-    // electron-positron pair per converting photon (beyond-LCFA rejections leave no product, so
-    // that mode reserves per wave instead, and so do steps with per-tile product sets)
+    // product slots of the whole block, from the scan kernel: one photon per lepton emitter and
+    // one electron-positron pair per converting photon (beyond-LCFA rejections leave no
+    // product, so that mode reserves photon slots per wave instead, and steps with per-tile
+    // product sets reserve per wave and set)
     const bool multi = A.nsets > 0;
-    if (tid == 0) {
-        s_base[0] = (!BLCFA && !multi && nl) ? atomicAdd(&A.prod_counts[0], (unsigned long long)nl) : 0;
-        s_base[1] = (!multi && np) ? atomicAdd(&A.prod_counts[1], (unsigned long long)np) : 0;
-        s_base[2] = (!multi && np) ? atomicAdd(&A.prod_counts[2], (unsigned long long)np) : 0;
-    }
+    if (tid < 3) s_base[tid] = multi ? 0ull : A.q_base[3 * blockIdx.x + tid];
     __syncthreads();
     const unsigned total = nl + np;
     unsigned long long c_emit = 0, c_conv = 0, c_rej = 0, c_clamp = 0, c_over = 0, c_ood = 0;
@@ -676,7 +752,9 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
         }
     }
     __syncthreads();
-    const unsigned long long vals[CNT_N] = {0, c_emit, c_conv, c_rej, c_ood, c_clamp, c_over};
+    // emissions and conversions were counted by the scan kernel, except beyond-LCFA emissions
+    (void)c_conv;
+    const unsigned long long vals[CNT_N] = {0, BLCFA ? c_emit : 0ull, 0, c_rej, c_ood, c_clamp, c_over};
     block_add_counters(s_cnt, A.counters, vals);
 }
 
@@ -1269,7 +1347,9 @@ static QueueShape queue_shape(const sfq_ctx* h, int nchunks, int blocks_per_cu, 
     return q;
 }
 
-static size_t queue_bytes(const QueueShape& q) { return q.entries * (4 + 4 + 8 * 9) + 8 * (size_t)q.grid + 256; }
+// per entry: 8 doubles + 2 uint32 (72 bytes, 80 reserved); per block: 2 uint32 counts, the
+// processed count and 3 product bases
+static size_t queue_bytes(const QueueShape& q) { return q.entries * 80 + 40 * (size_t)q.grid + 256; }
 
 static void bind_queue(StepArgs& A, void* mem, const QueueShape& qs)
 {
@@ -1286,7 +1366,10 @@ static void bind_queue(StepArgs& A, void* mem, const QueueShape& qs)
     A.q_idx = (uint32_t*)(q + 64 * E);
     A.q_tile = (uint32_t*)(q + 68 * E);
     A.q_count = (uint32_t*)(q + 72 * E);
+    A.q_proc = (unsigned long long*)(q + 72 * E + 8 * (size_t)qs.grid);
+    A.q_base = (unsigned long long*)(q + 72 * E + 16 * (size_t)qs.grid);
     A.q_cap_per_block = qs.cap_per_block;
+    A.grid = qs.grid;
 }
 
 static void fill_args(const sfq_ctx* h, const sfq_step_desc* desc, StepArgs& A, int nchunks,
@@ -1347,6 +1430,7 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
     } while (0)
     SFQ_LAUNCH_PAIR(bulk_kernel);
     if (pe) (void)hipEventRecord(pe->e[1], st);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, A);
     SFQ_LAUNCH_PAIR(emit_kernel);
 #undef SFQ_LAUNCH_PAIR
     if (pe) (void)hipEventRecord(pe->e[2], st);
