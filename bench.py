@@ -73,10 +73,10 @@ def device_tiles(dev, sfq, h, workloads):
     return tiles
 
 
-def run_form(precision, workload, n, steps, warmup, dev):
+def run_form(precision, workload, n, steps, warmup, dev, launch=None):
     import torch
 
-    from paper_2301_07684_amd import inputs, sfq
+    from paper_2301_07684_amd import autotune, inputs, sfq
 
     h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=precision)
     tiles = []
@@ -89,6 +89,11 @@ def run_form(precision, workload, n, steps, warmup, dev):
         del w
     prods = sfq.ProductBuffers.empty(n // 4, n // 16, dev)
     cnt = sfq.Counters(dev)
+    if launch is None:
+        tuned = autotune.tune(h, tiles, prods, cnt, seed=0, step=1, repeats=3, cache_path=None)
+    else:
+        h.set_launch(*launch)
+        tuned = {"shape": list(launch)}
     h.reserve(2 * n, 2)
     stream = torch.cuda.current_stream()
     for s in range(warmup):
@@ -118,7 +123,7 @@ def run_form(precision, workload, n, steps, warmup, dev):
     del tiles, prods
     torch.cuda.empty_cache()
     return dict(wall=wall, step_ms=step_ms, counters=c, n_total=2 * n,
-                bulk_ms=bulk_ms / nprof, emit_ms=emit_ms / nprof)
+                bulk_ms=bulk_ms / nprof, emit_ms=emit_ms / nprof, shape=tuned["shape"])
 
 
 def run_batched(steps, warmup, dev):
@@ -249,6 +254,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--launch", default=None,
+                    help="fixed launch shape BLOCKS_PER_CUxCHUNK for the FP64 and MIXED forms "
+                         "instead of the autotuner (e.g. for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the QED step is independent per particle and this "
@@ -261,11 +269,12 @@ def main():
     if args.copy_calibration:
         copy_calibration(dev)
         return
-    f64 = run_form(0, "plane_wave", args.n, args.steps, args.warmup, dev)
+    launch = tuple(int(v) for v in args.launch.split("x")) if args.launch else None
+    f64 = run_form(0, "plane_wave", args.n, args.steps, args.warmup, dev, launch)
     print(f"# fp64 form done: {f64['wall'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
     mixed = None if args.no_mixed else run_form(1, "plane_wave_skewed", args.n, args.steps,
-                                                args.warmup, dev)
+                                                args.warmup, dev, launch)
     if mixed is not None:
         print(f"# mixed form done: {mixed['wall'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
@@ -308,11 +317,12 @@ def main():
         "converted_per_step": per("converted"),
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": measured_traffic(),
-                     "kernel": "bulk_kernel<false, false> (streaming pass)",
+                     "kernel": "bulk_kernel<false, false, false> (streaming pass)",
                      "kernel_ms": f64["bulk_ms"], "algorithmic_bytes_per_launch": bulk_bytes},
-        "emit_kernel": {"kernel": "emit_kernel<false, false>", "kernel_ms": f64["emit_ms"],
-                        "algorithmic_bytes_per_launch": emit_bytes,
-                        "achieved_GB_per_s": emit_bytes / emit_s / 1e9},
+        "emitter_pass": {"kernels": "scan_kernel + emit_kernel<false, false, false>",
+                         "ms": f64["emit_ms"], "algorithmic_bytes_per_launch": emit_bytes,
+                         "achieved_GB_per_s": emit_bytes / emit_s / 1e9},
+        "launch_shape": f64["shape"],
         "step_roofline_frac": (bulk_bytes + emit_bytes) / (float(np.mean(f64["step_ms"])) * 1e-3)
                               / HBM_PEAK,
     }
@@ -326,7 +336,8 @@ def main():
                         "ms_per_step": mixed["wall"] / K * 1e3,
                         "p50_step_ms": float(np.percentile(mixed["step_ms"], 50)),
                         "p99_step_ms": float(np.percentile(mixed["step_ms"], 99)),
-                        "bulk_kernel_ms": mixed["bulk_ms"], "emit_kernel_ms": mixed["emit_ms"],
+                        "bulk_kernel_ms": mixed["bulk_ms"], "emitter_pass_ms": mixed["emit_ms"],
+                        "launch_shape": mixed["shape"],
                         "bulk_roofline_frac": bb / (mixed["bulk_ms"] * 1e-3) / HBM_PEAK,
                         "emitted_per_step": pm("emitted"),
                         "converted_per_step": pm("converted")}
