@@ -553,12 +553,25 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
 // product counts, and the step's processed / emitted / converted counters, each written once.
 // Every queued lepton emits and every queued photon converts, except that beyond-LCFA
 // rejections are only known in the emitter pass, which then reserves photon slots itself.
-constexpr int SCAN_BLOCK = 1024;
+constexpr int SCAN_BLOCK = 256;
+
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ unsigned long long wave_inclusive_scan(unsigned long long v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long u = __shfl_up(v, o);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
 
 __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
 {
-    __shared__ unsigned long long s_l[SCAN_BLOCK], s_p[SCAN_BLOCK], s_n[SCAN_BLOCK];
-    const int tid = threadIdx.x, G = A.grid;
+    constexpr int NW = SCAN_BLOCK / 64;
+    __shared__ unsigned long long s_w[3][NW];
+    const int tid = threadIdx.x, w = tid >> 6, G = A.grid;
     const int per = (G + SCAN_BLOCK - 1) / SCAN_BLOCK;
     const int lo = min(tid * per, G), hi = min(lo + per, G);
     unsigned long long nl = 0, np = 0, proc = 0;
@@ -567,21 +580,22 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
         np += A.q_count[2 * b + 1];
         proc += A.q_proc[b];
     }
-    s_l[tid] = nl; s_p[tid] = np; s_n[tid] = proc;
+    // block-wide inclusive scans: within each wave, then over the wave totals
+    unsigned long long il = wave_inclusive_scan(nl), ip = wave_inclusive_scan(np);
+    const unsigned long long in = wave_inclusive_scan(proc);
+    if ((tid & 63) == 63) { s_w[0][w] = il; s_w[1][w] = ip; s_w[2][w] = in; }
     __syncthreads();
-    for (int off = 1; off < SCAN_BLOCK; off <<= 1) {  // inclusive scan (Hillis-Steele)
-        const unsigned long long a = tid >= off ? s_l[tid - off] : 0ull;
-        const unsigned long long b = tid >= off ? s_p[tid - off] : 0ull;
-        const unsigned long long c = tid >= off ? s_n[tid - off] : 0ull;
-        __syncthreads();
-        s_l[tid] += a; s_p[tid] += b; s_n[tid] += c;
-        __syncthreads();
+    unsigned long long tl = 0, tp = 0, tn = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        if (k < w) { il += s_w[0][k]; ip += s_w[1][k]; }
+        tl += s_w[0][k]; tp += s_w[1][k]; tn += s_w[2][k];
     }
     const bool multi = A.nsets > 0;
     const unsigned long long b0 = multi ? 0ull : A.prod_counts[0];
     const unsigned long long b1 = multi ? 0ull : A.prod_counts[1];
     const unsigned long long b2 = multi ? 0ull : A.prod_counts[2];
-    unsigned long long run_l = s_l[tid] - nl, run_p = s_p[tid] - np;
+    unsigned long long run_l = il - nl, run_p = ip - np;
     for (int b = lo; b < hi; ++b) {
         A.q_base[3 * b] = b0 + run_l;
         A.q_base[3 * b + 1] = b1 + run_p;
@@ -591,13 +605,12 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
     }
     __syncthreads();  // every read of the product counts happens before they are advanced
     if (tid == 0) {
-        const unsigned long long tl = s_l[SCAN_BLOCK - 1], tp = s_p[SCAN_BLOCK - 1];
         if (!multi) {
             if (!A.blcfa) A.prod_counts[0] = b0 + tl;
             A.prod_counts[1] = b1 + tp;
             A.prod_counts[2] = b2 + tp;
         }
-        atomicAdd(&A.counters->processed, s_n[SCAN_BLOCK - 1]);
+        atomicAdd(&A.counters->processed, tn);
         if (!A.blcfa) atomicAdd(&A.counters->emitted, tl);
         atomicAdd(&A.counters->converted, tp);
     }

@@ -140,6 +140,7 @@ class Simulation:
         self.in_flight = False
         self.ready_event = None
         self.last_batch = 0           # requests in the batch of the last step
+        self._tiles = None
         with torch.cuda.stream(stream):
             e = inputs.plane_wave_t(spec.n_leptons, dev, seed=spec.seed, species=sfq.ELECTRON)
             self.p = e["p"].contiguous()
@@ -159,32 +160,35 @@ class Simulation:
     def push(self, dt: float):
         """Client work before a step: electrons get the Lorentz-force kick of the plane wave
         E = a cos(phi + 2 t) y, B = a cos(phi + 2 t) z (charge -1), with p_prev the momentum
-        before the kick."""
+        before the kick.  Written as few fused tensor operations (each is a kernel launch)."""
         import torch
 
         with torch.cuda.stream(self.stream):
             self.p_prev.copy_(self.p)
-            amp = self.a * torch.cos(self.phi + 2.0 * dt * self.step)
-            px, py, pz = self.p[0], self.p[1], self.p[2]
-            ginv = torch.rsqrt(1.0 + px * px + py * py + pz * pz)
-            # q (E + v x B) with q = -1: v x B = (vy Bz, -vx Bz, 0)
-            fx = -(py * ginv) * amp
-            fy = -(1.0 - px * ginv) * amp
-            self.p[0].add_(fx, alpha=dt)
-            self.p[1].add_(fy, alpha=dt)
+            amp = torch.cos(self.phi + 2.0 * dt * self.step).mul_(self.a)
+            ginv = (self.p * self.p).sum(0).add_(1.0).rsqrt_()
+            v = self.p_prev[:2] * ginv  # (vx, vy)
+            # q (E + v x B) dt with q = -1: (-vy a, -(1 - vx) a) dt
+            self.p[0].addcmul_(v[1], amp, value=-dt)
+            self.p[1].addcmul_(v[0].sub_(1.0), amp, value=dt)
             self.ready_event = torch.cuda.Event()
             self.ready_event.record(self.stream)
 
     def tiles(self, product_set: int) -> List[sfq.TileArrays]:
-        lep = sfq.TileArrays(sfq.ELECTRON, self.p[0], self.p[1], self.p[2], uid=self.e_uid,
-                             px_prev=self.p_prev[0], py_prev=self.p_prev[1],
-                             pz_prev=self.p_prev[2], fperp=self.fperp, dfperp=self.dfperp,
-                             just_created=self.just_created, product_set=product_set,
-                             step_offset=self.step)
-        pho = sfq.TileArrays(sfq.PHOTON, self.k[0], self.k[1], self.k[2], *self.kE, *self.kB,
-                             uid=self.g_uid, alive=self.alive, product_set=product_set,
-                             step_offset=self.step)
-        return [t for t in (lep, pho) if t.n > 0]
+        """The simulation's tiles for a batched step (built once; the product set and the
+        Philox step offset change per step)."""
+        if self._tiles is None:
+            lep = sfq.TileArrays(sfq.ELECTRON, self.p[0], self.p[1], self.p[2], uid=self.e_uid,
+                                 px_prev=self.p_prev[0], py_prev=self.p_prev[1],
+                                 pz_prev=self.p_prev[2], fperp=self.fperp, dfperp=self.dfperp,
+                                 just_created=self.just_created)
+            pho = sfq.TileArrays(sfq.PHOTON, self.k[0], self.k[1], self.k[2], *self.kE,
+                                 *self.kB, uid=self.g_uid, alive=self.alive)
+            self._tiles = [t for t in (lep, pho) if t.n > 0]
+        for t in self._tiles:
+            t.product_set = product_set
+            t.step_offset = self.step
+        return self._tiles
 
     @property
     def particles(self) -> int:

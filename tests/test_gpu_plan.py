@@ -164,3 +164,25 @@ def test_reserve_and_kernel_timing(dev):
     plan.close()
     with pytest.raises(sfq.SFQError):
         h.reserve(10, 0)
+
+
+@pytest.mark.parametrize("precision", [sfq.FP64, sfq.MIXED])
+def test_extreme_launch_shapes_give_identical_results(dev, precision):
+    """16384 blocks of 256-particle chunks (every scan thread sums 64 blocks) and 1 block per CU
+    with 2^22-particle chunks against the default shape: same state, same products."""
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=precision)
+    base = make_tiles(dev, h, sizes=(1 << 21, 3, (1 << 21) + 77, 4096))
+    results = []
+    for shape in ((8, 2048), (64, 256), (1, 1 << 22)):
+        h.set_launch(*shape)
+        tiles = clone_tiles(base)
+        pb = sfq.ProductBuffers.empty(1 << 22, 1 << 20, dev)
+        cnt = sfq.Counters(dev)
+        for s in range(2):
+            h.step(tiles, seed=21, step=s, products=pb, counters=cnt)
+        torch.cuda.synchronize()
+        results.append((state(tiles), product_set(pb), cnt.as_dict()))
+    c0 = results[0][2]
+    assert c0["emitted"] > 1000 and c0["overflow"] == 0
+    for st, ps, c in results[1:]:
+        assert same(st, results[0][0]) and same(ps, results[0][1]) and c == c0
