@@ -20,7 +20,7 @@ namespace sfq {
 // ---------------------------------------------------------------------------------------------
 // Table geometry (identical to the generator's; checked when the table file is loaded).
 // ---------------------------------------------------------------------------------------------
-constexpr int RATE_DEG = 20;
+constexpr int RATE_DEG = 16;
 constexpr int CHI_OCT_LO = -6, CHI_OCT_HI = 16;
 constexpr int N_CHI_SEG = 1 + (CHI_OCT_HI - CHI_OCT_LO);
 constexpr int PAIR_OCT_LO = -7;
@@ -112,13 +112,28 @@ __device__ __forceinline__ double rcp_nr(double x)
     return fma(r, e, r);
 }
 
+// sqrt(x) for x >= 0: the hardware reciprocal-square-root estimate refined by a Goldschmidt
+// step and a residual correction (about 1 ulp); arguments below 2^-1000 (where the estimate
+// would lose range) give 0.  No scaling path for subnormal input, which the step never needs.
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double s = x * y, h = 0.5 * y;
+    const double r = fma(-s, h, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    const double d = fma(-s, s, x);
+    s = fma(d, h, s);
+    return x > 0x1p-1000 ? s : 0.0;
+}
+
 __device__ __forceinline__ void gamma_chi(bool photon, double px, double py, double pz, double ex,
                                           double ey, double ez, double bx, double by, double bz,
                                           double lc_over_lr, double& gamma, double& chi)
 {
     const double p2 = fma(px, px, fma(py, py, pz * pz));
-    const double pn = sqrt(p2);
-    gamma = photon ? pn : sqrt(1.0 + p2);
+    const double pn = sqrt_nr(p2);
+    gamma = photon ? pn : sqrt_nr(1.0 + p2);
     // A particle at rest (|p|^2 below 1e-300) takes the p -> 0 limit of the expressions below
     // (E_perp = E, u = 0): chi = lc |E| for a lepton, 0 for a photon.  No branch, so the loads
     // feeding this function are issued together.
@@ -139,7 +154,7 @@ __device__ __forceinline__ void gamma_chi(bool photon, double px, double py, dou
     const double vx = fma(d, eqx, ux), vy = fma(d, eqy, uy), vz = fma(d, eqz, uz);
     double rad = fma(vx, vx, fma(vy, vy, vz * vz));
     if (!photon) rad = fma(q, pe, rad);
-    chi = lc_over_lr * sqrt(rad);
+    chi = lc_over_lr * sqrt_nr(rad);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -39,7 +39,7 @@ from scipy import special as sp
 # ------------------------------------------------------------------------------------------------
 # Table geometry.  Must match the constants compiled into the HIP library (sfq_tables.h).
 # ------------------------------------------------------------------------------------------------
-RATE_DEG = 20          # Chebyshev terms per rate segment
+RATE_DEG = 16          # Chebyshev terms per rate segment
 CHI_OCT_LO = -6        # first chi octave [2^-6, 2^-5); chi < 2^-6 is the linear segment 0
 CHI_OCT_HI = 16        # last octave ends at 2^16
 N_CHI_SEG = 1 + (CHI_OCT_HI - CHI_OCT_LO)   # 23 segments
