@@ -265,8 +265,8 @@ __device__ __forceinline__ unsigned long long keyed_reserve(const sfq_product_se
 constexpr int STEP_BLOCK = 256;
 // minimum waves per SIMD requested from the register allocator for the two step kernels.  The
 // streaming kernel's register budget decides how many waves hide HBM latency: the beyond-LCFA
-// form needs 128 registers (4 waves), the FP64 LCFA form fits 96 (5 waves) and the mixed form
-// 80 (6 waves) without spills inside the particle loop.
+// form needs 128 registers (4 waves), the FP64 LCFA form fits 91 (5 waves) and the mixed form
+// 67 (6 waves) without spills inside the particle loop.
 #ifdef SFQ_BULK_WAVES
 constexpr int bulk_waves(bool, bool) { return SFQ_BULK_WAVES; }
 #else
