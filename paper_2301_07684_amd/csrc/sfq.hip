@@ -75,7 +75,8 @@ struct StepArgs {
     unsigned long long* q_proc; // [grid]: particles processed by each block of the streaming pass
     unsigned long long* q_base; // [3 grid]: first product slot of each block (photons, e-, e+)
     uint64_t q_cap_per_block;
-    int grid;                   // blocks of the streaming and emitter kernels
+    int grid;                   // blocks of the streaming kernel (= queue slices)
+    int emit_split;             // emitter blocks per queue slice
     sfq_products prod[3];       // photons, electrons, positrons
     unsigned long long* prod_counts;
     sfq_counters* counters;
@@ -627,21 +628,26 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
     __shared__ unsigned long long s_base[3];
     const int tid = threadIdx.x;
     if (tid < CNT_N) s_cnt[tid] = 0;
-    const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
-    const unsigned nl = A.q_count[2 * blockIdx.x], np = A.q_count[2 * blockIdx.x + 1];
+    // emitter block -> (queue slice, part of it): a slice is shared by emit_split blocks, each
+    // taking a contiguous range of its entries
+    const int qb = blockIdx.x / A.emit_split, part = blockIdx.x % A.emit_split;
+    const uint64_t qbase = (uint64_t)qb * A.q_cap_per_block;
+    const unsigned nl = A.q_count[2 * qb], np = A.q_count[2 * qb + 1];
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
     // product slots of the whole block, from the scan kernel: one photon per lepton emitter and
     // one electron-positron pair per converting photon (beyond-LCFA rejections leave no
     // product, so that mode reserves photon slots per wave instead, and steps with per-tile
     // product sets reserve per wave and set)
     const bool multi = A.nsets > 0;
-    if (tid < 3) s_base[tid] = multi ? 0ull : A.q_base[3 * blockIdx.x + tid];
+    if (tid < 3) s_base[tid] = multi ? 0ull : A.q_base[3 * qb + tid];
     __syncthreads();
     const unsigned total = nl + np;
     unsigned long long c_emit = 0, c_conv = 0, c_rej = 0, c_clamp = 0, c_over = 0, c_ood = 0;
-    for (unsigned b0 = 0; b0 < total; b0 += STEP_BLOCK) {
+    const unsigned per = (total + A.emit_split - 1) / A.emit_split;
+    const unsigned e_lo = min(total, per * (unsigned)part), e_hi = min(total, e_lo + per);
+    for (unsigned b0 = e_lo; b0 < e_hi; b0 += STEP_BLOCK) {
         const unsigned e = b0 + tid;
-        const bool valid = e < total;
+        const bool valid = e < e_hi;
         bool want_ph = false, want_pair = false;
         double pgx = 0, pgy = 0, pgz = 0, tau_a = 0, pbx = 0, pby = 0, pbz = 0, tau_b = 0;
         uint64_t uid_a = 0, uid_b = 0, parent = 0;
@@ -1364,6 +1370,16 @@ static QueueShape queue_shape(const sfq_ctx* h, int nchunks, int blocks_per_cu, 
 // processed count and 3 product bases
 static size_t queue_bytes(const QueueShape& q) { return q.entries * 80 + 40 * (size_t)q.grid + 256; }
 
+// Emitter blocks per queue slice: enough emitter blocks to keep every compute unit busy with
+// the latency-bound emitter pass even when the streaming pass runs few, large blocks.
+#ifndef SFQ_EMIT_BPC
+#define SFQ_EMIT_BPC 6
+#endif
+static int emit_split_for(const sfq_ctx* h, int grid)
+{
+    return std::max(1, std::min(16, (h->num_cus * SFQ_EMIT_BPC) / std::max(1, grid)));
+}
+
 static void bind_queue(StepArgs& A, void* mem, const QueueShape& qs)
 {
     char* q = (char*)mem;
@@ -1429,22 +1445,22 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
     const dim3 g(grid), b(STEP_BLOCK);
     if (pe) (void)hipEventRecord(pe->e[0], st);
     const bool mixed = h->precision == SFQ_MIXED, local = h->decision == SFQ_LOCAL;
-#define SFQ_LAUNCH_PAIR(K)                                                                     \
+#define SFQ_LAUNCH_PAIR(K, G)                                                                  \
     do {                                                                                       \
         if (mixed) {                                                                           \
-            if (h->blcfa) hipLaunchKernelGGL((K<true, true, true>), g, b, 0, st, A);           \
-            else if (local) hipLaunchKernelGGL((K<true, false, true>), g, b, 0, st, A);        \
-            else hipLaunchKernelGGL((K<true, false, false>), g, b, 0, st, A);                  \
+            if (h->blcfa) hipLaunchKernelGGL((K<true, true, true>), G, b, 0, st, A);           \
+            else if (local) hipLaunchKernelGGL((K<true, false, true>), G, b, 0, st, A);        \
+            else hipLaunchKernelGGL((K<true, false, false>), G, b, 0, st, A);                  \
         } else {                                                                               \
-            if (h->blcfa) hipLaunchKernelGGL((K<false, true, true>), g, b, 0, st, A);          \
-            else if (local) hipLaunchKernelGGL((K<false, false, true>), g, b, 0, st, A);       \
-            else hipLaunchKernelGGL((K<false, false, false>), g, b, 0, st, A);                 \
+            if (h->blcfa) hipLaunchKernelGGL((K<false, true, true>), G, b, 0, st, A);          \
+            else if (local) hipLaunchKernelGGL((K<false, false, true>), G, b, 0, st, A);       \
+            else hipLaunchKernelGGL((K<false, false, false>), G, b, 0, st, A);                 \
         }                                                                                      \
     } while (0)
-    SFQ_LAUNCH_PAIR(bulk_kernel);
+    SFQ_LAUNCH_PAIR(bulk_kernel, g);
     if (pe) (void)hipEventRecord(pe->e[1], st);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, A);
-    SFQ_LAUNCH_PAIR(emit_kernel);
+    SFQ_LAUNCH_PAIR(emit_kernel, dim3(grid * A.emit_split));
 #undef SFQ_LAUNCH_PAIR
     if (pe) (void)hipEventRecord(pe->e[2], st);
 }
@@ -1603,6 +1619,7 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     if (desc->nsets > 0) A.sets = (const sfq_product_set*)((char*)S.dev + set_pos);
     bind_queue(A, h->d_queue, bound);
     A.q_cap_per_block = qs.cap_per_block;
+    A.emit_split = emit_split_for(h, qs.grid);
     launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, prof_events(h));
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
@@ -1658,6 +1675,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     p->A.step_ptr = p->d_step;
     if (desc->nsets > 0) p->A.sets = (const sfq_product_set*)((char*)p->d_mem + set_pos);
     bind_queue(p->A, (char*)p->d_mem + q_pos, qs);
+    p->A.emit_split = emit_split_for(h, qs.grid);
     *out = p;
     return SFQ_OK;
 }
