@@ -2,7 +2,8 @@
 
     python -m paper_2301_07684_amd.build
 
-compiles csrc/sfq.hip into libsfq.so next to this file (hipcc, --offload-arch=gfx950) and
+compiles csrc/sfq.hip into libsfq.so next to this file (hipcc, --offload-arch=gfx950), the
+serving harness's client push (csrc/harness.hip) into libsfq_harness.so, and
 (re)generates data/sfq_tables.bin when the table generator's source changed.
 """
 from __future__ import annotations
@@ -16,6 +17,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libsfq.so")
 SOURCES = [os.path.join(HERE, "csrc", "sfq.hip")]
+# client-side push kernel of the serving harness (not part of the QED library)
+HARNESS_LIB = os.path.join(HERE, "libsfq_harness.so")
+HARNESS_SOURCES = [os.path.join(HERE, "csrc", "harness.hip")]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -37,17 +41,25 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
-def build_library(verbose: bool = True) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-o", tmp, *SOURCES]
+def _hipcc_shared(out: str, sources, verbose: bool) -> str:
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIP_FLAGS, "-o", tmp, *sources]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build_library(verbose: bool = True) -> str:
+    return _hipcc_shared(LIB, SOURCES, verbose)
+
+
+def build_harness(verbose: bool = True) -> str:
+    return _hipcc_shared(HARNESS_LIB, HARNESS_SOURCES, verbose)
 
 
 def build_tables(verbose: bool = True) -> str:
@@ -60,6 +72,7 @@ def build_tables(verbose: bool = True) -> str:
 def build(verbose: bool = True):
     build_tables(verbose)
     build_library(verbose)
+    build_harness(verbose)
 
 
 if __name__ == "__main__":

@@ -19,18 +19,43 @@ step per tick of their own time loop.  The server
 The client side is a test harness, not part of the library.  Each simulation holds electrons
 with beyond-LCFA state (paper Sec. 5: the step needs p before and after the push) and photons,
 all in a linearly polarised plane wave.  Before every step the client pushes its electrons with
-a Lorentz-force kick (explicit, on its own stream), which supplies p^{(n-1/2)} and
-p_L^{(n+1/2)}.
+a Lorentz-force kick (explicit, one kernel of the harness library libsfq_harness.so on the
+client's stream), which supplies p^{(n-1/2)} and p_L^{(n+1/2)}.
 """
 from __future__ import annotations
 
 import collections
+import ctypes as C
 import math
+import os
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Deque, Dict, List, Optional, Sequence
 
 from . import inputs, sfq
+
+_HARNESS = None
+
+
+def _harness():
+    """The harness's push kernel library (built next to the QED library; raises if missing)."""
+    global _HARNESS
+    if _HARNESS is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfq_harness.so")
+        if not os.path.exists(path):
+            raise RuntimeError(f"serving harness library not built: {path} is missing "
+                               "(run `python -m paper_2301_07684_amd.build`)")
+        L = C.CDLL(path)
+        L.harness_push_plane_wave.restype = C.c_int
+        L.harness_push_plane_wave.argtypes = [C.c_size_t] + [C.c_void_p] * 8 + \
+            [C.c_double, C.c_double, C.c_void_p]
+        _HARNESS = L
+    return _HARNESS
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr())
+
 
 # Device bytes per particle of a simulation (the footprint admission charges)
 LEPTON_BYTES = 8 * 3 * 4 + 8 + 1 + 8 + 8  # p, p_prev, F_perp, dF; uid; just_created; a; phi
@@ -160,19 +185,18 @@ class Simulation:
     def push(self, dt: float):
         """Client work before a step: electrons get the Lorentz-force kick of the plane wave
         E = a cos(phi + 2 t) y, B = a cos(phi + 2 t) z (charge -1), with p_prev the momentum
-        before the kick.  Written as few fused tensor operations (each is a kernel launch)."""
+        before the kick (one harness kernel on the client's stream)."""
         import torch
 
-        with torch.cuda.stream(self.stream):
-            self.p_prev.copy_(self.p)
-            amp = torch.cos(self.phi + 2.0 * dt * self.step).mul_(self.a)
-            ginv = (self.p * self.p).sum(0).add_(1.0).rsqrt_()
-            v = self.p_prev[:2] * ginv  # (vx, vy)
-            # q (E + v x B) dt with q = -1: (-vy a, -(1 - vx) a) dt
-            self.p[0].addcmul_(v[1], amp, value=-dt)
-            self.p[1].addcmul_(v[0].sub_(1.0), amp, value=dt)
-            self.ready_event = torch.cuda.Event()
-            self.ready_event.record(self.stream)
+        n = self.spec.n_leptons
+        st = _harness().harness_push_plane_wave(
+            n, _p(self.p[0]), _p(self.p[1]), _p(self.p[2]), _p(self.p_prev[0]),
+            _p(self.p_prev[1]), _p(self.p_prev[2]), _p(self.a), _p(self.phi),
+            2.0 * dt * self.step, dt, C.c_void_p(self.stream.cuda_stream))
+        if st != 0:
+            raise RuntimeError(f"harness push failed with HIP error {st}")
+        self.ready_event = torch.cuda.Event()
+        self.ready_event.record(self.stream)
 
     def tiles(self, product_set: int) -> List[sfq.TileArrays]:
         """The simulation's tiles for a batched step (built once; the product set and the

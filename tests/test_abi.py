@@ -30,6 +30,13 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, nm), nm
 
 
+def test_serving_harness_library_exports_its_push():
+    from paper_2301_07684_amd import build
+
+    lib = C.CDLL(build.HARNESS_LIB)
+    assert hasattr(lib, "harness_push_plane_wave")
+
+
 def test_struct_layouts_match_the_header(tmp_path):
     from paper_2301_07684_amd import sfq
 
