@@ -390,6 +390,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
     unsigned long long c_proc = 0, c_ood = 0;
     const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
     const double dt = A.ph.dt;
+    const double idt = 1.0 / dt, idt2 = idt * idt;  // beyond-LCFA finite differences
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
 
     for (int c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
@@ -416,7 +417,87 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
             uint64_t quid = 0;
             bool ood = false;
             double W = 0.0;
-            if (!blcfa) {
+            if (BLCFA) {
+                // One load group for both species of a beyond-LCFA step: six slots hold E and B
+                // on photon chunks and p^{(n-1/2)}, F_perp on lepton chunks; the lepton-only
+                // Delta F and flag slots re-read the momentum and alive flag on photon chunks.
+                const uint64_t n = T.n;
+                const double* q0 = blcfa ? T.px_prev : T.ex;
+                const double* q1 = blcfa ? T.py_prev : T.ey;
+                const double* q2 = blcfa ? T.pz_prev : T.ez;
+                const double* q3 = blcfa ? T.fperp : T.bx;
+                const double* q4 = blcfa ? T.fperp + n : T.by;
+                const double* q5 = blcfa ? T.fperp + 2 * n : T.bz;
+                const double* q6 = blcfa ? T.dfperp : T.px;
+                const double* q7 = blcfa ? T.dfperp + n : T.py;
+                const double* q8 = blcfa ? T.dfperp + 2 * n : T.pz;
+                const uint8_t* q9 = blcfa ? T.just_created + j : alive + (j & amask);
+                const double ux = ld_stream(&T.px[j]), uy = ld_stream(&T.py[j]),
+                             uz = ld_stream(&T.pz[j]);
+                const double a0 = ld_stream(&q0[j]), a1 = ld_stream(&q1[j]), a2 = ld_stream(&q2[j]);
+                const double a3 = ld_stream(&q3[j]), a4 = ld_stream(&q4[j]), a5 = ld_stream(&q5[j]);
+                const double rx = ld_stream(&q6[j]), ry = ld_stream(&q7[j]), rz = ld_stream(&q8[j]);
+                const bool fresh = ld_stream(q9) != 0;
+                quid = ld_stream(&T.uid[j]);
+                __builtin_amdgcn_sched_barrier(0);
+                live = i < end && al != 0;
+                qx = ux; qy = uy; qz = uz;
+                if (!blcfa) {
+                    gamma_chi(true, ux, uy, uz, a0, a1, a2, a3, a4, a5, A.ph.lc_over_lr, gamma, chi);
+                    W = rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood);
+                    const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
+                    emit = live && W * dt > uniform53(d.a);
+                } else {
+                    // beyond-LCFA force update, Sec. 5 Eqs. (fl)-(condit)
+                    const double vx = a0, vy = a1, vz = a2, ox = a3, oy = a4, oz = a5;
+                    const double flx = (ux - vx) * idt, fly = (uy - vy) * idt, flz = (uz - vz) * idt;
+                    const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
+                    const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
+                    gamma = sqrt_nr(g2);
+                    const double fp = (flx * plx + fly * ply + flz * plz) * rcp_nr(g2);
+                    const double Fx = flx - fp * plx, Fy = fly - fp * ply, Fz = flz - fp * plz;
+                    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+                    const double tc = A.ph.lc_over_lr;
+                    chi = tc * gamma * sqrt(F2);
+                    W = rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+                    if (live) {
+                        st_stream(&T.fperp[i], Fx); st_stream(&T.fperp[n + i], Fy);
+                        st_stream(&T.fperp[2 * n + i], Fz);
+                    }
+                    if (live && fresh) {
+                        st_stream(&T.dfperp[i], 0.0); st_stream(&T.dfperp[n + i], 0.0);
+                        st_stream(&T.dfperp[2 * n + i], 0.0);
+                        st_stream(&T.just_created[i], (uint8_t)0);
+                    } else if (live) {
+                        const double ax = Fx - ox, ay = Fy - oy, az = Fz - oz;
+                        const double d1x = ax * idt, d1y = ay * idt, d1z = az * idt;
+                        const double d2x = (ax - rx) * idt2, d2y = (ay - ry) * idt2, d2z = (az - rz) * idt2;
+                        const double delta = tc * tc * ((d1x * d1x + d1y * d1y + d1z * d1z) +
+                                                        fabs(Fx * d2x + Fy * d2y + Fz * d2z));
+                        st_stream(&T.dfperp[i], ax); st_stream(&T.dfperp[n + i], ay);
+                        st_stream(&T.dfperp[2 * n + i], az);
+                        const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
+                        const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
+                        emit = W * dt > uniform53(d.a);
+                        if (emit) {
+                            // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
+                            const double pu2 = ux * ux + uy * uy + uz * uz;
+                            aux2 = (pu2 - (g2 - 1.0)) / (sqrt(1.0 + pu2) + gamma);
+                            if (flag) {
+                                const double tau_ratio = 2.0 * PI * sqrt(F2 / delta);
+                                const double arg = chi / (8.0 * gamma) * tau_ratio;
+                                aux = 0.7 * gamma /
+                                      (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
+                                if (!(aux < 0.75 * gamma)) emit = false;  // Eq. (gammaLCFA) check
+                            } else if (chi > ZETA) {
+                                aux = 0.0;  // fields effectively constant: LCFA throughout
+                            } else {
+                                emit = false;
+                            }
+                        }
+                    }
+                }
+            } else {
                 qx = ld_stream(&T.px[j]); qy = ld_stream(&T.py[j]); qz = ld_stream(&T.pz[j]);
                 const double ex = ld_stream(&T.ex[j]), ey = ld_stream(&T.ey[j]),
                              ez = ld_stream(&T.ez[j]);
@@ -440,69 +521,6 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
                 } else {
                     const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
                     emit = live && W * dt > uniform53(d.a);
-                }
-            } else {
-                // beyond-LCFA force update, Sec. 5 Eqs. (fl)-(condit)
-                const uint64_t n = T.n;
-                const double ux = ld_stream(&T.px[j]), uy = ld_stream(&T.py[j]),
-                             uz = ld_stream(&T.pz[j]);
-                const double vx = ld_stream(&T.px_prev[j]), vy = ld_stream(&T.py_prev[j]),
-                             vz = ld_stream(&T.pz_prev[j]);
-                const double ox = ld_stream(&T.fperp[j]), oy = ld_stream(&T.fperp[n + j]),
-                             oz = ld_stream(&T.fperp[2 * n + j]);
-                const double rx = ld_stream(&T.dfperp[j]), ry = ld_stream(&T.dfperp[n + j]),
-                             rz = ld_stream(&T.dfperp[2 * n + j]);
-                const bool fresh = ld_stream(&T.just_created[j]) != 0;
-                quid = ld_stream(&T.uid[j]);
-                __builtin_amdgcn_sched_barrier(0);
-                live = i < end && al != 0;
-                qx = ux; qy = uy; qz = uz;
-                const double flx = (ux - vx) / dt, fly = (uy - vy) / dt, flz = (uz - vz) / dt;
-                const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
-                const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
-                gamma = sqrt(g2);
-                const double fp = (flx * plx + fly * ply + flz * plz) / g2;
-                const double Fx = flx - fp * plx, Fy = fly - fp * ply, Fz = flz - fp * plz;
-                const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-                const double tc = A.ph.lc_over_lr;
-                chi = tc * gamma * sqrt(F2);
-                W = rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
-                if (live) {
-                    st_stream(&T.fperp[i], Fx); st_stream(&T.fperp[n + i], Fy);
-                    st_stream(&T.fperp[2 * n + i], Fz);
-                }
-                if (live && fresh) {
-                    st_stream(&T.dfperp[i], 0.0); st_stream(&T.dfperp[n + i], 0.0);
-                    st_stream(&T.dfperp[2 * n + i], 0.0);
-                    st_stream(&T.just_created[i], (uint8_t)0);
-                } else if (live) {
-                    const double ax = Fx - ox, ay = Fy - oy, az = Fz - oz;
-                    const double d1x = ax / dt, d1y = ay / dt, d1z = az / dt;
-                    const double dt2 = dt * dt;
-                    const double d2x = (ax - rx) / dt2, d2y = (ay - ry) / dt2, d2z = (az - rz) / dt2;
-                    const double delta = tc * tc * ((d1x * d1x + d1y * d1y + d1z * d1z) +
-                                                    fabs(Fx * d2x + Fy * d2y + Fz * d2z));
-                    st_stream(&T.dfperp[i], ax); st_stream(&T.dfperp[n + i], ay);
-                    st_stream(&T.dfperp[2 * n + i], az);
-                    const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
-                    const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
-                    emit = W * dt > uniform53(d.a);
-                    if (emit) {
-                        // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
-                        const double pu2 = ux * ux + uy * uy + uz * uz;
-                        aux2 = (pu2 - (g2 - 1.0)) / (sqrt(1.0 + pu2) + gamma);
-                        if (flag) {
-                            const double tau_ratio = 2.0 * PI * sqrt(F2 / delta);
-                            const double arg = chi / (8.0 * gamma) * tau_ratio;
-                            aux = 0.7 * gamma /
-                                  (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
-                            if (!(aux < 0.75 * gamma)) emit = false;  // Eq. (gammaLCFA) check
-                        } else if (chi > ZETA) {
-                            aux = 0.0;  // fields effectively constant: LCFA throughout
-                        } else {
-                            emit = false;
-                        }
-                    }
                 }
             }
             if (live) {
