@@ -104,6 +104,8 @@ def lib():
                                         C.POINTER(C.c_int32)]),
             "orc_step_blcfa_batch": (None, [C.POINTER(StepCfg), l] + [_dp] * 8 +
                                      [C.POINTER(C.c_uint8), C.POINTER(u64), C.POINTER(Result)]),
+            "orc_boris_push": (None, [d, _dp, _dp, _dp, d, _dp]),
+            "orc_boris_push_batch": (None, [d, l] + [_dp] * 9 + [d, _dp, _dp, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -254,6 +256,24 @@ def chi(species, p, E, B, lc_over_lr):
 
 
 # ---- random numbers -----------------------------------------------------------------------------
+def boris_push(species, p, E, B, dt):
+    """Boris push of n particles ((3, n) arrays) over dt: charge -1 for electrons, +1 for
+    positrons; photons are returned unchanged (they feel no force)."""
+    p = _f64(p)
+    if species == PHOTON:
+        return p.copy()
+    q = -1.0 if species == ELECTRON else 1.0
+    E, B = _f64(E), _f64(B)
+    n = p.shape[1]
+    out = np.empty_like(p)
+    cols = [np.ascontiguousarray(a[k]) for a in (p, E, B) for k in range(3)]
+    outs = [np.empty(n) for _ in range(3)]
+    lib().orc_boris_push_batch(q, n, *[_ptr(c) for c in cols], float(dt), *[_ptr(o) for o in outs])
+    for k in range(3):
+        out[k] = outs[k]
+    return out
+
+
 def philox(ctr, key):
     c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
     k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])

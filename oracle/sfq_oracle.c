@@ -531,6 +531,48 @@ double orc_chi(int is_photon, const double p[3], const double E[3], const double
     return (double)(g * (long double)lc_over_lr * sqrtl(rad));
 }
 
+/* ------------------------------------------------------------------------------------------ */
+/* Boris push (J. P. Boris, Proc. 4th Conf. Num. Sim. Plasmas, 1970), the leapfrog momentum     */
+/* update of the PIC cycle (paper Fig. 7): for charge q (units of |e|, mass m_e) in normalised  */
+/* units dp/dt = q (E + p x B / gamma): half an electric kick, a rotation about B by the        */
+/* half-angle vector t = q dt B / (2 gamma^-), and the other half electric kick.               */
+/* ------------------------------------------------------------------------------------------ */
+void orc_boris_push(double q, const double p[3], const double E[3], const double B[3], double dt,
+                    double out[3])
+{
+    const long double h = 0.5L * (long double)q * (long double)dt;
+    long double um[3], t[3], s[3], up[3], uq[3];
+    for (int k = 0; k < 3; ++k) um[k] = (long double)p[k] + h * (long double)E[k];
+    const long double g = sqrtl(1.0L + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    for (int k = 0; k < 3; ++k) t[k] = h * (long double)B[k] / g;
+    const long double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    for (int k = 0; k < 3; ++k) s[k] = 2.0L * t[k] / (1.0L + t2);
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    uq[0] = um[0] + (up[1] * s[2] - up[2] * s[1]);
+    uq[1] = um[1] + (up[2] * s[0] - up[0] * s[2]);
+    uq[2] = um[2] + (up[0] * s[1] - up[1] * s[0]);
+    for (int k = 0; k < 3; ++k) out[k] = (double)(uq[k] + h * (long double)E[k]);
+}
+
+void orc_boris_push_batch(double q, long n, const double* px, const double* py, const double* pz,
+                          const double* ex, const double* ey, const double* ez, const double* bx,
+                          const double* by, const double* bz, double dt, double* ox, double* oy,
+                          double* oz)
+{
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        const double p[3] = {px[i], py[i], pz[i]}, E[3] = {ex[i], ey[i], ez[i]},
+                     B[3] = {bx[i], by[i], bz[i]};
+        double o[3];
+        orc_boris_push(q, p, E, B, dt, o);
+        ox[i] = o[0];
+        oy[i] = o[1];
+        oz[i] = o[2];
+    }
+}
+
 double orc_gamma(int is_photon, const double p[3])
 {
     long double p2 = (long double)p[0] * p[0] + (long double)p[1] * p[1] + (long double)p[2] * p[2];

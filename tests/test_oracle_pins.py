@@ -563,3 +563,56 @@ def test_blcfa_acceptance_rule():
     assert 0 < ratio < 1  # the LCFA spectrum falls with energy
     assert O.blcfa_accept(gbar, limit, g, chi, ratio * 0.999)
     assert not O.blcfa_accept(gbar, limit, g, chi, ratio * 1.001)
+
+
+# ------------------------------------------------------------------------------------------------
+# Boris push (the leapfrog momentum update of the PIC cycle, paper Fig. 7), pinned by properties
+# of the scheme rather than by its formula: an exact rotation in a pure magnetic field, an exact
+# kick in a pure electric field, and time reversibility.
+# ------------------------------------------------------------------------------------------------
+def _random_fields(n, seed):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(size=(3, n)) * 10.0 ** rng.uniform(0, 4, n)
+    E = rng.normal(size=(3, n)) * 10.0 ** rng.uniform(0, 3, n)
+    B = rng.normal(size=(3, n)) * 10.0 ** rng.uniform(0, 3, n)
+    return p, E, B
+
+
+@pytest.mark.parametrize("species", [O.ELECTRON, O.POSITRON])
+def test_boris_pure_magnetic_field_is_an_exact_rotation(species):
+    p, _, B = _random_fields(500, 31)
+    dt = 0.02
+    out = O.boris_push(species, p, np.zeros_like(p), B, dt)
+    q = -1.0 if species == O.ELECTRON else 1.0
+    gamma = np.sqrt(1.0 + np.sum(p * p, axis=0))
+    bh = B / np.linalg.norm(B, axis=0)
+    # |p| (hence gamma) is conserved and the component along B is unchanged
+    assert np.allclose(np.linalg.norm(out, axis=0), np.linalg.norm(p, axis=0), rtol=1e-14)
+    assert np.allclose(np.sum(out * bh, 0), np.sum(p * bh, 0), rtol=1e-10,
+                       atol=1e-12 * np.linalg.norm(p, axis=0))
+    # the perpendicular part turns by 2 atan(|q| dt |B| / (2 gamma)), clockwise about B for q > 0
+    pp = p - np.sum(p * bh, 0) * bh
+    op = out - np.sum(out * bh, 0) * bh
+    cosang = np.sum(pp * op, 0) / (np.linalg.norm(pp, axis=0) * np.linalg.norm(op, axis=0))
+    sinang = np.sum(np.cross(pp.T, op.T).T * bh, 0) / (np.linalg.norm(pp, axis=0) *
+                                                          np.linalg.norm(op, axis=0))
+    ang = np.arctan2(sinang, cosang)
+    expect = -q * 2.0 * np.arctan(dt * np.linalg.norm(B, axis=0) / (2.0 * gamma))
+    assert np.allclose(ang, expect, rtol=1e-9, atol=1e-13)
+
+
+def test_boris_pure_electric_field_is_an_exact_kick():
+    p, E, _ = _random_fields(500, 32)
+    dt = 0.03
+    for species, q in ((O.ELECTRON, -1.0), (O.POSITRON, 1.0)):
+        out = O.boris_push(species, p, E, np.zeros_like(p), dt)
+        assert np.allclose(out, p + q * E * dt, rtol=1e-14, atol=1e-14 * np.abs(p).max())
+
+
+def test_boris_is_time_reversible_and_photons_do_not_move():
+    p, E, B = _random_fields(500, 33)
+    dt = 0.01
+    fwd = O.boris_push(O.ELECTRON, p, E, B, dt)
+    back = O.boris_push(O.ELECTRON, fwd, E, B, -dt)
+    assert np.allclose(back, p, rtol=1e-10, atol=1e-10 * np.abs(p).max())
+    assert np.array_equal(O.boris_push(O.PHOTON, p, E, B, dt), p)
