@@ -13,7 +13,9 @@ tiles (chi, rates, decisions, sampling, recoil, products).  Then, on the same GP
     geometry, chi log-uniform [1e-3, 1e2]), MIXED, launch shape from the autotuner, each step
     one replay of a HIP graph captured from a plan;
   * the served form: continuous batching of step requests from 8 clients' simulations with
-    beyond-LCFA electrons, admitted under an HBM budget (request latency p50/p99).
+    beyond-LCFA electrons, admitted under an HBM budget (request latency p50/p99);
+  * the fused form: the headline workload with every electron's momentum pushed through its
+    fields (Boris) inside the streaming kernel before the QED step.
 
 Prints ONE JSON line: value = FP64 particle-updates/s over the timed steps; p50/p99 step
 latency; the roofline of the dominant (streaming) kernel from its own duration measured with HIP
@@ -49,6 +51,13 @@ def stream_kernel_bytes(n_total, processed, emitted, converted):
     return n_total + 80 * processed + 8 * (processed - emitted - converted)
 
 
+def pushed_stream_kernel_bytes(n_total, processed, emitted, converted, leptons):
+    """The streaming kernel with the fused momentum push: as above, plus the pushed momentum
+    (24 B) written back for every live lepton that does not emit (emitters' momenta are written
+    after the recoil by the emitter kernel, as without the push)."""
+    return stream_kernel_bytes(n_total, processed, emitted, converted) + 24 * (leptons - emitted)
+
+
 def emit_kernel_bytes(emitted, converted):
     """Algorithmic bytes of the emitter kernel for one step.  A Compton emission reads the
     emitter's id (8) and writes its momentum and optical depth (32) and one photon product
@@ -73,7 +82,7 @@ def device_tiles(dev, sfq, h, workloads):
     return tiles
 
 
-def run_form(precision, workload, n, steps, warmup, dev, launch=None):
+def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False):
     import torch
 
     from paper_2301_07684_amd import autotune, inputs, sfq
@@ -98,7 +107,7 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None):
     stream = torch.cuda.current_stream()
     for s in range(warmup):
         prods.reset()
-        h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt)
+        h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt, push=push)
     torch.cuda.synchronize()
     cnt.reset()
     h.profile(True)
@@ -110,7 +119,7 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None):
     for s in range(steps):
         prods.reset()
         ev[s][0].record(stream)
-        h.step(tiles, seed=0, step=warmup + s + 1, products=prods, counters=cnt)
+        h.step(tiles, seed=0, step=warmup + s + 1, products=prods, counters=cnt, push=push)
         ev[s][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -253,6 +262,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-push", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--launch", default=None,
                     help="fixed launch shape BLOCKS_PER_CUxCHUNK for the FP64 and MIXED forms "
@@ -285,6 +295,11 @@ def main():
     served = None if args.no_served else run_served(dev)
     if served is not None:
         print(f"# served form done: {served['wall']:.2f} s", file=sys.stderr, flush=True)
+    fused = None if args.no_push else run_form(0, "plane_wave", args.n, args.steps, args.warmup,
+                                               dev, tuple(f64["shape"]), push=True)
+    if fused is not None:
+        print(f"# fused push form done: {fused['wall'] / args.steps * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
 
     c = f64["counters"]
     K = args.steps
@@ -376,6 +391,24 @@ def main():
                          "jobs_that_waited_for_memory": served["waited"],
                          "wall_s": served["wall"], "emitted": cs["emitted"],
                          "blcfa_rejected": cs["blcfa_rejected"], "converted": cs["converted"]}
+    if fused is not None:
+        cf = fused["counters"]
+        pf = lambda k: cf[k] / K
+        fb = pushed_stream_kernel_bytes(fused["n_total"], pf("processed"), pf("emitted"),
+                                        pf("converted"), fused["n_total"] // 2)
+        out["fused_push"] = {"value": cf["processed"] / fused["wall"],
+                             "unit": "particle-updates/s", "dtype": "f64",
+                             "workload": "the headline workload, electrons pushed (Boris) "
+                                         "through their fields inside the streaming kernel",
+                             "ms_per_step": fused["wall"] / K * 1e3,
+                             "p50_step_ms": float(np.percentile(fused["step_ms"], 50)),
+                             "p99_step_ms": float(np.percentile(fused["step_ms"], 99)),
+                             "bulk_kernel_ms": fused["bulk_ms"],
+                             "emitter_pass_ms": fused["emit_ms"],
+                             "bulk_algorithmic_bytes": fb,
+                             "bulk_roofline_frac": fb / (fused["bulk_ms"] * 1e-3) / HBM_PEAK,
+                             "emitted_per_step": pf("emitted"),
+                             "converted_per_step": pf("converted")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

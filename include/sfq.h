@@ -202,6 +202,17 @@ typedef struct {
                                   (beyond capacity too: the final count is the size needed)      */
     sfq_counters* counters;    /* device, accumulated                                             */
     const sfq_product_set* product_sets; /* HOST array of nsets sets (copied by the call)         */
+    int32_t push;              /* 1: before the QED step, every alive lepton's momentum gets the
+                                  Boris push through its tile's E and B over one time step dt
+                                  (charge -1 for electrons, +1 for positrons; time in 1/omega_r,
+                                  fields in m c omega_r / e, the units of the QED step), and the
+                                  step then works on the pushed momentum, which is what the tile
+                                  holds afterwards.  Photons are not pushed.  This is the particle
+                                  update of the PIC cycle fused with the QED step (paper Fig. 7),
+                                  for callers whose fields are already at the particles.  Not
+                                  with beyond-LCFA handles (SFQ_E_ARG): there the caller's push
+                                  is an input of the force update.  0: momenta are taken as given */
+    int32_t reserved2;         /* 0                                                               */
 } sfq_step_desc;
 
 #define SFQ_MAX_TILES 4096

@@ -82,6 +82,7 @@ struct StepArgs {
     sfq_counters* counters;
     const sfq_product_set* sets; // nsets > 0: per-tile product destinations (device copy)
     int nsets;
+    int push;                    // leptons get the Boris push before the step
 };
 
 enum { CNT_PROCESSED, CNT_EMITTED, CNT_CONVERTED, CNT_REJECTED, CNT_OOD, CNT_CLAMPED, CNT_OVERFLOW,
@@ -368,10 +369,11 @@ __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
 // was fetched one iteration earlier), so an iteration costs one memory round trip.  With
 // optical-depth decisions the particle id is not read here: only emitters need it, and the
 // emitter pass fetches it.
-template <bool MIXED, bool BLCFA, bool LOCAL>
+template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH>
 __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_kernel(StepArgs A)
 {
     static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
+    static_assert(!(PUSH && BLCFA), "beyond-LCFA steps take the caller's pushed momentum");
     using RT = typename std::conditional<MIXED, float, double>::type;
     __shared__ RT s_rad[RAD_SIZE];
     __shared__ RT s_pair[PAIR_SIZE];
@@ -511,6 +513,11 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
                 // one counter here), so a use scheduled between the loads would split the group
                 __builtin_amdgcn_sched_barrier(0);
                 live = i < end && al != 0;
+                const bool pushed = PUSH && !photon;
+                if (pushed) {
+                    const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
+                    boris_push(hq, ex, ey, ez, bx, by, bz, qx, qy, qz);
+                }
                 gamma_chi(photon, qx, qy, qz, ex, ey, ez, bx, by, bz, A.ph.lc_over_lr, gamma, chi);
                 W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
                            : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
@@ -521,6 +528,11 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
                 } else {
                     const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
                     emit = live && W * dt > uniform53(d.a);
+                }
+                // the pushed momentum of the particles that do not emit (emitters recoil from
+                // the queued, pushed momentum in the emitter pass)
+                if (pushed && live && !emit) {
+                    st_stream(&T.px[i], qx); st_stream(&T.py[i], qy); st_stream(&T.pz[i], qz);
                 }
             }
             if (live) {
@@ -1321,6 +1333,10 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
         return fail(h, SFQ_E_ARG, "sfq_step: NULL product counts");
     if (desc->nsets > 0 && !desc->product_sets)
         return fail(h, SFQ_E_ARG, "sfq_step: NULL product sets");
+    if (desc->push != 0 && desc->push != 1)
+        return fail(h, SFQ_E_ARG, "sfq_step: push must be 0 or 1");
+    if (desc->push && h->blcfa)
+        return fail(h, SFQ_E_ARG, "sfq_step: push is not available with beyond-LCFA handles");
     const int nt = desc->ntiles;
     off.assign(nt + 1, 0);
     for (int t = 0; t < nt; ++t) {
@@ -1439,6 +1455,7 @@ static void fill_args(const sfq_ctx* h, const sfq_step_desc* desc, StepArgs& A, 
     A.counters = desc->counters;
     A.sets = nullptr;
     A.nsets = desc->nsets;
+    A.push = desc->push;
 }
 
 // A set of timing events for one step (caller holds h->mu); nullptr when timing is off or the
@@ -1475,7 +1492,24 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
             else hipLaunchKernelGGL((K<false, false, false>), G, b, 0, st, A);                 \
         }                                                                                      \
     } while (0)
-    SFQ_LAUNCH_PAIR(bulk_kernel, g);
+    if (h->blcfa) {
+        if (mixed) hipLaunchKernelGGL((bulk_kernel<true, true, true, false>), g, b, 0, st, A);
+        else hipLaunchKernelGGL((bulk_kernel<false, true, true, false>), g, b, 0, st, A);
+    } else {
+#define SFQ_LAUNCH_BULK(M, L)                                                                  \
+    do {                                                                                       \
+        if (A.push) hipLaunchKernelGGL((bulk_kernel<M, false, L, true>), g, b, 0, st, A);      \
+        else hipLaunchKernelGGL((bulk_kernel<M, false, L, false>), g, b, 0, st, A);            \
+    } while (0)
+        if (mixed) {
+            if (local) SFQ_LAUNCH_BULK(true, true);
+            else SFQ_LAUNCH_BULK(true, false);
+        } else {
+            if (local) SFQ_LAUNCH_BULK(false, true);
+            else SFQ_LAUNCH_BULK(false, false);
+        }
+#undef SFQ_LAUNCH_BULK
+    }
     if (pe) (void)hipEventRecord(pe->e[1], st);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, A);
     SFQ_LAUNCH_PAIR(emit_kernel, dim3(grid * A.emit_split));

@@ -158,6 +158,32 @@ __device__ __forceinline__ void gamma_chi(bool photon, double px, double py, dou
 }
 
 // ---------------------------------------------------------------------------------------------
+// Boris push (the leapfrog momentum update of the PIC cycle the step sits in, paper Fig. 7):
+// half an electric kick, a rotation about B by the angle 2 atan(|hq B| / gamma^-) evaluated at
+// the half-kicked momentum, and the second half kick; hq = q dt / 2 in the step's units (p in
+// m c, t in 1/omega_r, E and B in m c omega_r / e).  p is updated in place.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void boris_push(double hq, double ex, double ey, double ez, double bx,
+                                           double by, double bz, double& px, double& py,
+                                           double& pz)
+{
+    const double mx = fma(hq, ex, px), my = fma(hq, ey, py), mz = fma(hq, ez, pz);
+    const double gm = sqrt_nr(1.0 + fma(mx, mx, fma(my, my, mz * mz)));
+    const double f = hq * rcp_nr(gm);
+    const double tx = f * bx, ty = f * by, tz = f * bz;
+    const double sf = 2.0 * rcp_nr(1.0 + fma(tx, tx, fma(ty, ty, tz * tz)));
+    const double sx = sf * tx, sy = sf * ty, sz = sf * tz;
+    // u' = u- + u- x t, then u+ = u- + u' x s
+    const double rx = mx + (my * tz - mz * ty), ry = my + (mz * tx - mx * tz),
+                 rz = mz + (mx * ty - my * tx);
+    const double ux = mx + (ry * sz - rz * sy), uy = my + (rz * sx - rx * sz),
+                 uz = mz + (rx * sy - ry * sx);
+    px = fma(hq, ex, ux);
+    py = fma(hq, ey, uy);
+    pz = fma(hq, ez, uz);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Clenshaw's recurrence (App. B): f = sum_{k<N} c_k T_k(X), c_0 full weight.
 // ---------------------------------------------------------------------------------------------
 template <int N, typename T, typename P>

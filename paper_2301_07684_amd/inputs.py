@@ -124,6 +124,24 @@ def plane_wave(n: int, idx=None, seed: int = SEED_WAVE, species: int = ELECTRON,
                 gamma=gamma)
 
 
+SEED_GENERAL = 106
+
+
+def general_fields(n: int, idx=None, seed: int = SEED_GENERAL, species: int = ELECTRON,
+                   field_range=(1.0, 1e3), gamma_range=(1e2, 1e5)):
+    """Isotropic particles in fields of arbitrary geometry: E and B in independent isotropic
+    directions with log-uniform magnitudes (units of m c omega_r / e), for steps that push the
+    momentum through the fields before the QED step."""
+    idx = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64)
+    s0 = 50 + 10 * species
+    gamma = _loguniform(uniforms(seed, s0, idx), *gamma_range)
+    pm = gamma if species == PHOTON else np.sqrt((gamma - 1.0) * (gamma + 1.0))
+    p = _isotropic(seed, s0 + 1, idx) * pm
+    E = _isotropic(seed, s0 + 3, idx) * _loguniform(uniforms(seed, s0 + 5, idx), *field_range)
+    B = _isotropic(seed, s0 + 6, idx) * _loguniform(uniforms(seed, s0 + 8, idx), *field_range)
+    return dict(species=species, p=p, E=E, B=B, uid=ids(seed + species, idx), gamma=gamma)
+
+
 def tile_sizes(ntiles: int = 64, seed: int = SEED_TILES, lo: float = 1e3, hi: float = 4e6):
     u = uniforms(seed, 90, np.arange(ntiles))
     sizes = np.floor(_loguniform(u, lo, hi)).astype(np.int64)

@@ -67,7 +67,8 @@ class StepDesc(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("step", C.c_uint64), ("ntiles", C.c_int32),
                 ("nsets", C.c_int32), ("tiles", C.POINTER(Tile)), ("photons", ProductsC),
                 ("electrons", ProductsC), ("positrons", ProductsC), ("product_counts", _P),
-                ("counters", _P), ("product_sets", C.POINTER(ProductSetC))]
+                ("counters", _P), ("product_sets", C.POINTER(ProductSetC)),
+                ("push", C.c_int32), ("reserved2", C.c_int32)]
 
 
 COUNTER_NAMES = ("processed", "emitted", "converted", "blcfa_rejected", "out_of_domain",
@@ -275,9 +276,10 @@ class Handle:
         return out
 
     @staticmethod
-    def _desc(tiles, seed, step, products, counters, product_sets=None):
+    def _desc(tiles, seed, step, products, counters, product_sets=None, push=False):
         """Step descriptor.  With `product_sets` (a list of ProductBuffers), tile k's products go
-        to product_sets[tiles[k].product_set] and `products` may be None."""
+        to product_sets[tiles[k].product_set] and `products` may be None.  push=True gives every
+        alive lepton the Boris push through its tile's fields before the step."""
         nt = len(tiles)
         if nt == 0 or nt > MAX_TILES:
             raise ValueError("1 <= len(tiles) <= MAX_TILES")
@@ -303,21 +305,25 @@ class Handle:
                         electrons=products.electrons.to_c() if products else none,
                         positrons=products.positrons.to_c() if products else none,
                         product_counts=_ptr(products.counts) if products else None,
-                        counters=_ptr(counters.t), product_sets=sets)
+                        counters=_ptr(counters.t), product_sets=sets, push=int(bool(push)))
         return desc, (arr, sets)
 
     def step(self, tiles: Sequence["TileArrays"], *, seed: int, step: int,
              products: Optional["ProductBuffers"] = None, counters: "Counters",
-             product_sets: Optional[Sequence["ProductBuffers"]] = None, stream=None):
-        """One Monte Carlo step over all tiles (one launch sequence on `stream`)."""
-        desc, _keep = self._desc(tiles, seed, step, products, counters, product_sets)
+             product_sets: Optional[Sequence["ProductBuffers"]] = None, push: bool = False,
+             stream=None):
+        """One Monte Carlo step over all tiles (one launch sequence on `stream`); with
+        push=True the leptons' momenta are first pushed through their fields (fused)."""
+        desc, _keep = self._desc(tiles, seed, step, products, counters, product_sets, push)
         self._check(self._L.sfq_step(self._h, C.byref(desc), _stream(stream)))
 
     def plan(self, tiles, *, seed: int, step: int, products: Optional["ProductBuffers"] = None,
              counters: "Counters", zero_product_counts: bool = True,
-             product_sets: Optional[Sequence["ProductBuffers"]] = None) -> "Plan":
+             product_sets: Optional[Sequence["ProductBuffers"]] = None,
+             push: bool = False) -> "Plan":
         return Plan(self, tiles, seed=seed, step=step, products=products, counters=counters,
-                    zero_product_counts=zero_product_counts, product_sets=product_sets)
+                    zero_product_counts=zero_product_counts, product_sets=product_sets,
+                    push=push)
 
 
 class Plan:
@@ -325,12 +331,13 @@ class Plan:
     index advancing on the device, optionally captured in a HIP graph."""
 
     def __init__(self, handle: Handle, tiles, *, seed, step, products, counters,
-                 zero_product_counts=True, product_sets=None):
+                 zero_product_counts=True, product_sets=None, push=False):
         self._handle = handle
         self._L = handle._L
         self.tiles, self.products, self.counters = list(tiles), products, counters
         self.product_sets = list(product_sets) if product_sets else None
-        desc, _keep = Handle._desc(self.tiles, seed, step, products, counters, product_sets)
+        desc, _keep = Handle._desc(self.tiles, seed, step, products, counters, product_sets,
+                                   push)
         p = C.c_void_p()
         handle._check(self._L.sfq_plan_create(handle._h, C.byref(desc), int(zero_product_counts),
                                               C.byref(p)))

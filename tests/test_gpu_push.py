@@ -1,0 +1,216 @@
+"""The fused momentum push + QED step (sfq_step_desc.push) against the oracle's Boris push
+followed by the oracle's step (paper Fig. 7: the particle push of the PIC cycle, then the QED
+module on the updated momentum).
+
+Bars: the pushed momentum of every alive lepton that does not emit within 1e-14 of the oracle's
+(relative to |p|, FP64 arithmetic in both forms); chi within 1e-12 relative (the pushed momentum's
+rounding, amplified by chi's conditioning, on top of the step's 1e-13); rates and samples to the
+step's own tolerances (FP64 1e-12 / 1e-9, MIXED 2e-5); decisions identical outside the band
+around the threshold; photons and dead particles untouched, bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2301_07684_amd import inputs, sfq
+
+pytestmark = pytest.mark.gpu
+
+TOL_PUSH = 1e-14
+TOL_CHI = 1e-12
+TOL = {sfq.FP64: dict(rate=2e-12, sample=1e-9, band=1e-9),
+       sfq.MIXED: dict(rate=2e-5, sample=2e-5, band=2e-5)}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.abs(a - b) / np.abs(b)
+    r[a == b] = 0.0
+    return r
+
+
+def make_tile(w, dev, tau, alive):
+    n = w["p"].shape[1]
+    return sfq.TileArrays(w["species"], *[T(w["p"][i], dev) for i in range(3)],
+                          *[T(w["E"][i], dev) for i in range(3)],
+                          *[T(w["B"][i], dev) for i in range(3)],
+                          tau=T(tau, dev), uid=T(w["uid"], dev), alive=T(alive, dev),
+                          chi_out=torch.zeros(n, dtype=torch.float64, device=dev),
+                          rate_out=torch.zeros(n, dtype=torch.float64, device=dev))
+
+
+def products_by_parent(pb, k, name):
+    ps = getattr(pb, name)
+    n = min(pb.host_counts()[k], ps.capacity)
+    par = ps.parent[:n].cpu().numpy().view(np.uint64)
+    p = np.stack([ps.px[:n].cpu().numpy(), ps.py[:n].cpu().numpy(), ps.pz[:n].cpu().numpy()])
+    return {int(par[j]): p[:, j] for j in range(n)}
+
+
+def workloads(n):
+    """Leptons and photons in arbitrary fields and in the counter-propagating plane wave."""
+    out = []
+    for sp in (sfq.ELECTRON, sfq.POSITRON, sfq.PHOTON):
+        out.append(inputs.general_fields(n, species=sp))
+    for sp in (sfq.ELECTRON, sfq.POSITRON):
+        out.append(inputs.plane_wave(1 << 24, idx=np.arange(n) * 4099 + 7, species=sp))
+    return out
+
+
+def check(w, tile, tau0, alive0, prods, h, tol, *, seed, step, n_sample=120):
+    sp = w["species"]
+    photon = sp == sfq.PHOTON
+    uids = w["uid"].view(np.uint64)
+    live = alive0 != 0
+    p_or = w["p"] if photon else O.boris_push(sp, w["p"], w["E"], w["B"], h.dt)
+    og, oc = O.chi(sp, p_or, w["E"], w["B"], h.lc_over_lr)
+    W = O.rates(sp, og, oc, h.lr_over_lc)
+    chi = tile.chi_out.cpu().numpy()
+    rate = tile.rate_out.cpu().numpy()
+    assert np.max(rel(chi[live], oc[live])) < TOL_CHI
+    tiny = np.finfo(np.float32).tiny * h.lr_over_lc if tol is TOL[sfq.MIXED] else 0.0
+    ok = (np.abs(rate - W) <= tol["rate"] * np.abs(W)) | (np.abs(rate - W) <= tiny)
+    assert np.all(ok[live])
+    thr = W * h.dt
+    emit_or = live & (tau0 - thr < 0)
+    in_band = np.abs(tau0 - thr) <= tol["band"] * np.maximum(tau0, thr)
+    pmap = products_by_parent(prods, 1 if photon else 0, "electrons" if photon else "photons")
+    emit_gpu = np.array([int(u) in pmap for u in uids])
+    assert not ((emit_gpu != emit_or) & ~in_band).any()
+    assert not (emit_gpu & ~live).any()
+    p_gpu = np.stack([tile.px.cpu().numpy(), tile.py.cpu().numpy(), tile.pz.cpu().numpy()])
+    if photon:
+        # photons are never pushed
+        assert np.array_equal(p_gpu, w["p"])
+        return emit_or
+    # dead leptons untouched; the pushed momentum of every alive non-emitter
+    assert np.array_equal(p_gpu[:, ~live], w["p"][:, ~live])
+    ne = live & ~emit_gpu
+    err = np.linalg.norm(p_gpu[:, ne] - p_or[:, ne], axis=0) / np.linalg.norm(p_or[:, ne], axis=0)
+    assert np.max(err) < TOL_PUSH, np.max(err)
+    # emitters: the oracle's step on the oracle-pushed momentum, on a sample
+    em_idx = np.flatnonzero(emit_or & emit_gpu & ~in_band)
+    rng = np.random.default_rng(step)
+    pick = rng.choice(em_idx, min(n_sample, em_idx.size), replace=False)
+    ref = O.step(sp, p_or[:, pick], w["E"][:, pick], w["B"][:, pick], tau0[pick], uids[pick],
+                 dt=h.dt, lc_over_lr=h.lc_over_lr, seed=seed, step=step)
+    assert ref["emitted"].all()
+    pm_ref = np.linalg.norm(ref["p"], axis=0)
+    pm_gpu = np.linalg.norm(p_gpu[:, pick], axis=0)
+    assert np.max(rel(pm_gpu, pm_ref)) < tol["sample"]
+    # the recoil keeps the pushed direction
+    cosang = np.sum(p_gpu[:, pick] * p_or[:, pick], 0) / (pm_gpu * np.linalg.norm(p_or[:, pick], axis=0))
+    assert np.all(cosang > 1 - 1e-13)
+    for q in ref["products"]:
+        got = pmap[q["parent"]]
+        mref = np.sqrt(q["px"] ** 2 + q["py"] ** 2 + q["pz"] ** 2)
+        assert abs(np.linalg.norm(got) / mref - 1) < tol["sample"]
+    return emit_or
+
+
+@pytest.mark.parametrize("precision", [sfq.FP64, sfq.MIXED])
+def test_fused_push_and_step_matches_oracle_push_then_step(dev, precision):
+    n = 6000
+    seed, step = 21, 5
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=precision)
+    ws = workloads(n)
+    tiles, taus, alives = [], [], []
+    for k, w in enumerate(ws):
+        tau0 = h.init_optical_depth(T(w["uid"], dev), seed=seed).cpu().numpy() * 2e-2
+        alive = np.ones(n, dtype=np.uint8)
+        alive[k::7] = 0
+        taus.append(tau0)
+        alives.append(alive)
+        tiles.append(make_tile(w, dev, tau0, alive))
+    prods = sfq.ProductBuffers.empty(5 * n, 2 * n, dev)
+    cnt = sfq.Counters(dev)
+    h.step(tiles, seed=seed, step=step, products=prods, counters=cnt, push=True)
+    torch.cuda.synchronize()
+    c = cnt.as_dict()
+    assert c["overflow"] == 0
+    assert c["processed"] == sum(int(a.sum()) for a in alives)
+    for w, tile, tau0, alive in zip(ws, tiles, taus, alives):
+        check(w, tile, tau0, alive, prods, h, TOL[precision], seed=seed, step=step)
+    assert c["emitted"] > 1000 and c["converted"] > 50
+
+
+def test_local_decisions_with_push(dev):
+    n = 4000
+    seed, step = 4, 12
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.LOCAL)
+    w = inputs.general_fields(n, species=sfq.POSITRON, field_range=(30.0, 2e3))
+    alive = np.ones(n, dtype=np.uint8)
+    tile = make_tile(w, dev, np.zeros(n), alive)
+    prods = sfq.ProductBuffers.empty(n, 1, dev)
+    cnt = sfq.Counters(dev)
+    h.step([tile], seed=seed, step=step, products=prods, counters=cnt, push=True)
+    torch.cuda.synchronize()
+    p_or = O.boris_push(sfq.POSITRON, w["p"], w["E"], w["B"], h.dt)
+    ref = O.step(sfq.POSITRON, p_or, w["E"], w["B"], np.zeros(n), w["uid"].view(np.uint64),
+                 dt=h.dt, lc_over_lr=h.lc_over_lr, seed=seed, step=step, decision=O.LOCAL)
+    u = np.array([O.uniform(O.draw(seed, int(x), step, O.P_LOCAL)[0])
+                  for x in w["uid"].view(np.uint64)])
+    thr = ref["rate"] * h.dt
+    band = np.abs(thr - u) <= 1e-9 * np.maximum(thr, u)
+    pmap = products_by_parent(prods, 0, "photons")
+    emit_gpu = np.array([int(x) in pmap for x in w["uid"].view(np.uint64)])
+    assert not ((emit_gpu != ref["emitted"].astype(bool)) & ~band).any()
+    assert 50 < emit_gpu.sum() < n - 50
+    p_gpu = np.stack([tile.px.cpu().numpy(), tile.py.cpu().numpy(), tile.pz.cpu().numpy()])
+    keep = ~emit_gpu & ~band
+    err = np.linalg.norm(p_gpu[:, keep] - p_or[:, keep], axis=0) / np.linalg.norm(p_or[:, keep], axis=0)
+    assert np.max(err) < TOL_PUSH
+    ok = emit_gpu & ~band
+    assert np.max(rel(np.linalg.norm(p_gpu[:, ok], axis=0),
+                      np.linalg.norm(ref["p"][:, ok], axis=0))) < 1e-9
+
+
+def test_plan_with_push_matches_eager_steps(dev):
+    n = 20000
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    mk = lambda: [make_tile(w, dev, h.init_optical_depth(T(w["uid"], dev), seed=1).cpu().numpy(),
+                            np.ones(n, dtype=np.uint8))
+                  for w in (inputs.general_fields(n, species=sfq.ELECTRON),
+                            inputs.general_fields(n, species=sfq.PHOTON))]
+    eager, planned = mk(), mk()
+    pe, pp = sfq.ProductBuffers.empty(n, n, dev), sfq.ProductBuffers.empty(n, n, dev)
+    ce, cp = sfq.Counters(dev), sfq.Counters(dev)
+    plan = h.plan(planned, seed=9, step=30, products=pp, counters=cp, push=True)
+    plan.capture(2)
+    for r in range(2):
+        for s in range(2):
+            pe.reset()
+            h.step(eager, seed=9, step=30 + 2 * r + s, products=pe, counters=ce, push=True)
+        plan.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(eager, planned):
+            for f in ("px", "py", "pz", "tau", "alive"):
+                assert torch.equal(getattr(a, f), getattr(b, f)), (r, f)
+        assert torch.equal(pe.counts, pp.counts)
+    assert ce.as_dict() == cp.as_dict()
+    plan.close()
+    # the momenta really moved: every electron was pushed four times
+    w = inputs.general_fields(n, species=sfq.ELECTRON)
+    assert not np.allclose(eager[0].px.cpu().numpy(), w["p"][0])
+
+
+def test_push_is_rejected_with_beyond_lcfa_handles(dev):
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.LOCAL, blcfa=True)
+    w = inputs.general_fields(100, species=sfq.PHOTON)
+    tile = make_tile(w, dev, np.zeros(100), np.ones(100, dtype=np.uint8))
+    with pytest.raises(sfq.SFQError):
+        h.step([tile], seed=0, step=0, products=sfq.ProductBuffers.empty(10, 10, dev),
+               counters=sfq.Counters(dev), push=True)
