@@ -138,15 +138,17 @@ typedef struct {
                                   this tile's products; otherwise must be 0                       */
     uint64_t n;                /* number of particles                                             */
     double *px, *py, *pz;      /* momentum, updated in place by recoil.  With blcfa leptons this
-                                  is the pushed momentum p_L^{(n+1/2)} of Sec. 5                  */
-    const double *ex, *ey, *ez;/* electric field at the particle (unused by blcfa leptons)        */
-    const double *bx, *by, *bz;/* magnetic field at the particle (unused by blcfa leptons)        */
+                                  is the pushed momentum p_L^{(n+1/2)} of Sec. 5, or, with
+                                  desc->push, p^{(n-1/2)} (the step pushes it)                    */
+    const double *ex, *ey, *ez;/* electric field at the particle (blcfa leptons: only with push)  */
+    const double *bx, *by, *bz;/* magnetic field at the particle (blcfa leptons: only with push)  */
     double* tau;               /* remaining optical depth tau_d (OPTICAL_DEPTH; else nullable)    */
     const uint64_t* uid;       /* particle identifiers: the Philox counter of every draw          */
     uint8_t* alive;            /* nullable (all alive).  Converted photons are set to 0           */
     /* beyond-LCFA state (blcfa handles, lepton tiles; else NULL): the momentum before the push
-     * p^{(n-1/2)}, the stored transverse Lorentz force F_perp^{(n-1)} and its last difference
-     * (3n doubles each, component-major: x[0..n), y[0..n), z[0..n)), and the just-created flag */
+     * p^{(n-1/2)} (not read, and may be NULL, with desc->push), the stored transverse Lorentz
+     * force F_perp^{(n-1)} and its last difference (3n doubles each, component-major:
+     * x[0..n), y[0..n), z[0..n)), and the just-created flag                                    */
     const double *px_prev, *py_prev, *pz_prev;
     double* fperp;
     double* dfperp;
@@ -209,9 +211,11 @@ typedef struct {
                                   step then works on the pushed momentum, which is what the tile
                                   holds afterwards.  Photons are not pushed.  This is the particle
                                   update of the PIC cycle fused with the QED step (paper Fig. 7),
-                                  for callers whose fields are already at the particles.  Not
-                                  with beyond-LCFA handles (SFQ_E_ARG): there the caller's push
-                                  is an input of the force update.  0: momenta are taken as given */
+                                  for callers whose fields are already at the particles.  With
+                                  beyond-LCFA handles the tile's momentum is p^{(n-1/2)} and the
+                                  push supplies p^{(n+1/2)} to the force update of Sec. 5, so
+                                  px_prev.. are not needed; lepton tiles then need E and B.
+                                  0: momenta are taken as given                                   */
     int32_t reserved2;         /* 0                                                               */
 } sfq_step_desc;
 

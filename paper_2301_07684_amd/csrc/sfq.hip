@@ -266,13 +266,17 @@ __device__ __forceinline__ unsigned long long keyed_reserve(const sfq_product_se
 // =============================================================================================
 constexpr int STEP_BLOCK = 256;
 // minimum waves per SIMD requested from the register allocator for the two step kernels.  The
-// streaming kernel's register budget decides how many waves hide HBM latency: the beyond-LCFA
-// form needs 128 registers (4 waves), the FP64 LCFA form fits 91 (5 waves) and the mixed form
-// 67 (6 waves) without spills inside the particle loop.
+// streaming kernel's register budget decides how many waves hide HBM latency: the FP64 LCFA
+// form fits 93 registers (5 waves) and the mixed form 67 (6 waves); the mixed beyond-LCFA form
+// fits 128 (4 waves), while the FP64 beyond-LCFA form and the beyond-LCFA forms with the fused
+// push would spill to scratch at 128 and get 168 (3 waves).
 #ifdef SFQ_BULK_WAVES
-constexpr int bulk_waves(bool, bool) { return SFQ_BULK_WAVES; }
+constexpr int bulk_waves(bool, bool, bool) { return SFQ_BULK_WAVES; }
 #else
-constexpr int bulk_waves(bool mixed, bool blcfa) { return blcfa ? 4 : (mixed ? 6 : 5); }
+constexpr int bulk_waves(bool mixed, bool blcfa, bool push)
+{
+    return blcfa ? ((mixed && !push) ? 4 : 3) : (mixed ? 6 : 5);
+}
 #endif
 #ifndef SFQ_EMIT_WAVES
 #define SFQ_EMIT_WAVES 3
@@ -370,10 +374,9 @@ __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
 // optical-depth decisions the particle id is not read here: only emitters need it, and the
 // emitter pass fetches it.
 template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH>
-__global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_kernel(StepArgs A)
+__global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bulk_kernel(StepArgs A)
 {
     static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
-    static_assert(!(PUSH && BLCFA), "beyond-LCFA steps take the caller's pushed momentum");
     using RT = typename std::conditional<MIXED, float, double>::type;
     __shared__ RT s_rad[RAD_SIZE];
     __shared__ RT s_pair[PAIR_SIZE];
@@ -420,29 +423,53 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
             bool ood = false;
             double W = 0.0;
             if (BLCFA) {
-                // One load group for both species of a beyond-LCFA step: six slots hold E and B
-                // on photon chunks and p^{(n-1/2)}, F_perp on lepton chunks; the lepton-only
-                // Delta F and flag slots re-read the momentum and alive flag on photon chunks.
+                // One load group for both species of a beyond-LCFA step.  Without the push, six
+                // slots hold E and B on photon chunks and p^{(n-1/2)}, F_perp on lepton chunks;
+                // the lepton-only Delta F and flag slots re-read the momentum and alive flag on
+                // photon chunks.  With the push every chunk reads E and B, the tile's momentum
+                // is p^{(n-1/2)}, and lepton chunks read F_perp and Delta F in six more slots.
                 const uint64_t n = T.n;
-                const double* q0 = blcfa ? T.px_prev : T.ex;
-                const double* q1 = blcfa ? T.py_prev : T.ey;
-                const double* q2 = blcfa ? T.pz_prev : T.ez;
-                const double* q3 = blcfa ? T.fperp : T.bx;
-                const double* q4 = blcfa ? T.fperp + n : T.by;
-                const double* q5 = blcfa ? T.fperp + 2 * n : T.bz;
+                const double* q0 = (blcfa && !PUSH) ? T.px_prev : T.ex;
+                const double* q1 = (blcfa && !PUSH) ? T.py_prev : T.ey;
+                const double* q2 = (blcfa && !PUSH) ? T.pz_prev : T.ez;
+                const double* q3 = (blcfa && !PUSH) ? T.fperp : T.bx;
+                const double* q4 = (blcfa && !PUSH) ? T.fperp + n : T.by;
+                const double* q5 = (blcfa && !PUSH) ? T.fperp + 2 * n : T.bz;
                 const double* q6 = blcfa ? T.dfperp : T.px;
                 const double* q7 = blcfa ? T.dfperp + n : T.py;
                 const double* q8 = blcfa ? T.dfperp + 2 * n : T.pz;
                 const uint8_t* q9 = blcfa ? T.just_created + j : alive + (j & amask);
-                const double ux = ld_stream(&T.px[j]), uy = ld_stream(&T.py[j]),
-                             uz = ld_stream(&T.pz[j]);
+                const double* q10 = blcfa ? T.fperp : T.px;
+                const double* q11 = blcfa ? T.fperp + n : T.py;
+                const double* q12 = blcfa ? T.fperp + 2 * n : T.pz;
+                double ux = ld_stream(&T.px[j]), uy = ld_stream(&T.py[j]), uz = ld_stream(&T.pz[j]);
                 const double a0 = ld_stream(&q0[j]), a1 = ld_stream(&q1[j]), a2 = ld_stream(&q2[j]);
                 const double a3 = ld_stream(&q3[j]), a4 = ld_stream(&q4[j]), a5 = ld_stream(&q5[j]);
                 const double rx = ld_stream(&q6[j]), ry = ld_stream(&q7[j]), rz = ld_stream(&q8[j]);
+                double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+                if (PUSH) {
+                    o0 = ld_stream(&q10[j]);
+                    o1 = ld_stream(&q11[j]);
+                    o2 = ld_stream(&q12[j]);
+                }
                 const bool fresh = ld_stream(q9) != 0;
                 quid = ld_stream(&T.uid[j]);
                 __builtin_amdgcn_sched_barrier(0);
                 live = i < end && al != 0;
+                // p^{(n-1/2)} and F_perp^{(n-1)}: loaded, or (with the push) the tile's momentum
+                // before the push and the six extra slots
+                double vx, vy, vz, ox, oy, oz;
+                if (PUSH) {
+                    vx = ux; vy = uy; vz = uz;
+                    ox = o0; oy = o1; oz = o2;
+                    if (blcfa) {
+                        const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
+                        boris_push(hq, a0, a1, a2, a3, a4, a5, ux, uy, uz);
+                    }
+                } else {
+                    vx = a0; vy = a1; vz = a2;
+                    ox = a3; oy = a4; oz = a5;
+                }
                 qx = ux; qy = uy; qz = uz;
                 if (!blcfa) {
                     gamma_chi(true, ux, uy, uz, a0, a1, a2, a3, a4, a5, A.ph.lc_over_lr, gamma, chi);
@@ -451,7 +478,6 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
                     emit = live && W * dt > uniform53(d.a);
                 } else {
                     // beyond-LCFA force update, Sec. 5 Eqs. (fl)-(condit)
-                    const double vx = a0, vy = a1, vz = a2, ox = a3, oy = a4, oz = a5;
                     const double flx = (ux - vx) * idt, fly = (uy - vy) * idt, flz = (uz - vz) * idt;
                     const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
                     const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
@@ -497,6 +523,11 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA)) void bulk_ker
                                 emit = false;
                             }
                         }
+                    }
+                    // the pushed momentum of the leptons that do not emit (emitters: from the
+                    // queue in the emitter pass, after the recoil or the rejection)
+                    if (PUSH && live && !emit) {
+                        st_stream(&T.px[i], ux); st_stream(&T.py[i], uy); st_stream(&T.pz[i], uz);
                     }
                 }
             } else {
@@ -742,6 +773,9 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
                     want_ph = true;
                     ++c_emit;
                 } else {
+                    // rejected: the lepton keeps the pushed momentum, which with the fused push
+                    // the tile does not hold yet
+                    if (A.push) { T.px[i] = px; T.py[i] = py; T.pz[i] = pz; }
                     ++c_rej;
                 }
             } else {
@@ -1335,8 +1369,6 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
         return fail(h, SFQ_E_ARG, "sfq_step: NULL product sets");
     if (desc->push != 0 && desc->push != 1)
         return fail(h, SFQ_E_ARG, "sfq_step: push must be 0 or 1");
-    if (desc->push && h->blcfa)
-        return fail(h, SFQ_E_ARG, "sfq_step: push is not available with beyond-LCFA handles");
     const int nt = desc->ntiles;
     off.assign(nt + 1, 0);
     for (int t = 0; t < nt; ++t) {
@@ -1354,14 +1386,14 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
         if (T.n > 0) {
             if (!T.px || !T.py || !T.pz || !T.uid)
                 return fail(h, SFQ_E_ARG, "sfq_step: NULL momentum/uid" + tn);
-            if (!bl && (!T.ex || !T.ey || !T.ez || !T.bx || !T.by || !T.bz))
+            if ((!bl || desc->push) && (!T.ex || !T.ey || !T.ez || !T.bx || !T.by || !T.bz))
                 return fail(h, SFQ_E_ARG, "sfq_step: NULL field array" + tn);
             if (!bl && h->decision == SFQ_OPTICAL_DEPTH && !T.tau)
                 return fail(h, SFQ_E_ARG, "sfq_step: NULL tau" + tn);
             if (photon && !T.alive)
                 return fail(h, SFQ_E_ARG, "sfq_step: photon tiles need an alive array" + tn);
-            if (bl && (!T.px_prev || !T.py_prev || !T.pz_prev || !T.fperp || !T.dfperp ||
-                       !T.just_created))
+            if (bl && ((!desc->push && (!T.px_prev || !T.py_prev || !T.pz_prev)) || !T.fperp ||
+                       !T.dfperp || !T.just_created))
                 return fail(h, SFQ_E_ARG, "sfq_step: beyond-LCFA state missing" + tn);
         }
         const uint64_t nch = (T.n + chunk - 1) / chunk;
@@ -1492,24 +1524,24 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
             else hipLaunchKernelGGL((K<false, false, false>), G, b, 0, st, A);                 \
         }                                                                                      \
     } while (0)
-    if (h->blcfa) {
-        if (mixed) hipLaunchKernelGGL((bulk_kernel<true, true, true, false>), g, b, 0, st, A);
-        else hipLaunchKernelGGL((bulk_kernel<false, true, true, false>), g, b, 0, st, A);
-    } else {
-#define SFQ_LAUNCH_BULK(M, L)                                                                  \
+#define SFQ_LAUNCH_BULK(M, BL, L)                                                              \
     do {                                                                                       \
-        if (A.push) hipLaunchKernelGGL((bulk_kernel<M, false, L, true>), g, b, 0, st, A);      \
-        else hipLaunchKernelGGL((bulk_kernel<M, false, L, false>), g, b, 0, st, A);            \
+        if (A.push) hipLaunchKernelGGL((bulk_kernel<M, BL, L, true>), g, b, 0, st, A);         \
+        else hipLaunchKernelGGL((bulk_kernel<M, BL, L, false>), g, b, 0, st, A);               \
     } while (0)
+    if (h->blcfa) {
+        if (mixed) SFQ_LAUNCH_BULK(true, true, true);
+        else SFQ_LAUNCH_BULK(false, true, true);
+    } else {
         if (mixed) {
-            if (local) SFQ_LAUNCH_BULK(true, true);
-            else SFQ_LAUNCH_BULK(true, false);
+            if (local) SFQ_LAUNCH_BULK(true, false, true);
+            else SFQ_LAUNCH_BULK(true, false, false);
         } else {
-            if (local) SFQ_LAUNCH_BULK(false, true);
-            else SFQ_LAUNCH_BULK(false, false);
+            if (local) SFQ_LAUNCH_BULK(false, false, true);
+            else SFQ_LAUNCH_BULK(false, false, false);
         }
-#undef SFQ_LAUNCH_BULK
     }
+#undef SFQ_LAUNCH_BULK
     if (pe) (void)hipEventRecord(pe->e[1], st);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, A);
     SFQ_LAUNCH_PAIR(emit_kernel, dim3(grid * A.emit_split));

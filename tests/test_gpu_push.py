@@ -207,10 +207,135 @@ def test_plan_with_push_matches_eager_steps(dev):
     assert not np.allclose(eager[0].px.cpu().numpy(), w["p"][0])
 
 
-def test_push_is_rejected_with_beyond_lcfa_handles(dev):
+def _varying_fields(n, step, gamma, lc_over_lr):
+    """E and B in new random directions every step, of the strength that gives chi ~ 1..30: a
+    rapidly varying transverse force, so that the beyond-LCFA threshold matters."""
+    idx = np.arange(n)
+    out = []
+    for k in range(2):
+        u = [inputs.uniforms(17, 200 + 6 * step + 3 * k + j, idx) for j in range(3)]
+        ct = 2 * u[0] - 1
+        ph = 2 * np.pi * u[1]
+        st = np.sqrt(1 - ct * ct)
+        mag = 10.0 / (lc_over_lr * gamma) * (0.2 + u[2])
+        out.append(np.stack([st * np.cos(ph), st * np.sin(ph), ct]) * mag)
+    return out
+
+
+@pytest.mark.parametrize("precision", [sfq.FP64, sfq.MIXED])
+def test_blcfa_with_push_matches_oracle_push_then_blcfa_step(dev, precision):
+    """Beyond-LCFA steps with the fused push: the tile holds p^{(n-1/2)} and the fields; the
+    step pushes and feeds (p^{(n-1/2)}, p^{(n+1/2)}) to the force update of Sec. 5.  The oracle
+    gets the same pair from its own push.  Every step is checked on its own inputs."""
+    n = 2048
+    rate_tol, band_tol, recoil_tol, max_flips = ((1e-12, 1e-9, 1e-9, 0) if precision == sfq.FP64
+                                                 else (2e-5, 2e-5, 2e-5, 2))
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.LOCAL, blcfa=True,
+                   precision=precision)
+    idx = np.arange(n)
+    gamma = 10.0 ** (3 + 1.5 * inputs.uniforms(18, 0, idx))
+    species = [sfq.ELECTRON, sfq.POSITRON]
+    ps = {sp: np.stack([gamma, np.zeros(n), np.zeros(n)]) * (1 if sp == sfq.ELECTRON else -1)
+          for sp in species}
+    uids = {sp: inputs.ids(18 + sp, idx) for sp in species}
+    state = {sp: (torch.zeros(3 * n, dtype=torch.float64, device=dev),
+                  torch.zeros(3 * n, dtype=torch.float64, device=dev),
+                  torch.ones(n, dtype=torch.uint8, device=dev)) for sp in species}
+    wg = inputs.plane_wave(1 << 20, idx=idx * 97, species=sfq.PHOTON)
+    tot_emit = tot_rej = 0
+    for step in range(1, 6):
+        E, B = _varying_fields(n, step, gamma, h.lc_over_lr)
+        before = {sp: [x.cpu().numpy().copy() for x in state[sp]] for sp in species}
+        tiles = []
+        for sp in species:
+            f, d, jc = state[sp]
+            tiles.append(sfq.TileArrays(sp, *[T(ps[sp][k], dev) for k in range(3)],
+                                        *[T(E[k], dev) for k in range(3)],
+                                        *[T(B[k], dev) for k in range(3)],
+                                        uid=T(uids[sp], dev), fperp=f, dfperp=d, just_created=jc,
+                                        chi_out=torch.zeros(n, dtype=torch.float64, device=dev),
+                                        rate_out=torch.zeros(n, dtype=torch.float64, device=dev)))
+        ph = make_tile(wg, dev, np.zeros(n), np.ones(n, dtype=np.uint8))
+        prods = sfq.ProductBuffers.empty(2 * n, n, dev)
+        cnt = sfq.Counters(dev)
+        h.step(tiles + [ph], seed=8, step=step, products=prods, counters=cnt, push=True)
+        torch.cuda.synchronize()
+        c = cnt.as_dict()
+        pmap = products_by_parent(prods, 0, "photons")
+        rej_ref = 0
+        for sp, tile in zip(species, tiles):
+            p_prev = ps[sp]
+            p_push = O.boris_push(sp, p_prev, E, B, h.dt)
+            ref = O.step_blcfa(p_prev, p_push, *before[sp], uids[sp].view(np.uint64), dt=h.dt,
+                               lc_over_lr=h.lc_over_lr, seed=8, step=step)
+            # the force is a difference of momenta: the two pushes' last-bit differences grow by
+            # |p| / |p^{(n+1/2)} - p^{(n-1/2)}| in chi (a few ulp of |p| over the kick)
+            cond = np.linalg.norm(p_push, axis=0) / np.linalg.norm(p_push - p_prev, axis=0)
+            chi_tol = 1e-12 + 32 * np.finfo(float).eps * cond
+            assert np.all(rel(tile.chi_out.cpu().numpy(), ref["chi"]) < chi_tol)
+            rate = tile.rate_out.cpu().numpy()
+            pos = ref["rate"] > 0
+            assert np.all(rel(rate[pos], ref["rate"][pos]) < rate_tol + 4 * chi_tol[pos])
+            f, d, jc = state[sp]
+            fscale = np.max(np.abs(ref["fperp"]))
+            assert np.allclose(f.cpu().numpy(), ref["fperp"], rtol=1e-10, atol=1e-11 * fscale)
+            assert np.allclose(d.cpu().numpy(), ref["dfperp"], rtol=1e-8, atol=1e-11 * fscale)
+            assert np.array_equal(jc.cpu().numpy(), ref["just_created"])
+            r1 = np.array([O.uniform(O.draw(8, int(u), step, O.P_LOCAL)[0])
+                           for u in uids[sp].view(np.uint64)])
+            band = np.abs(ref["rate"] * h.dt - r1) <= np.maximum(band_tol, 4 * chi_tol) * r1
+            emit_gpu = np.array([int(u) in pmap for u in uids[sp].view(np.uint64)])
+            flips = int(np.sum((emit_gpu != ref["emitted"].astype(bool)) & ~band))
+            assert flips <= max_flips, flips
+            pg = np.stack([t.cpu().numpy() for t in (tile.px, tile.py, tile.pz)])
+            # leptons that kept their momentum (no emission, or a rejected one): the pushed one
+            keep = ~emit_gpu
+            err = np.linalg.norm(pg[:, keep] - p_push[:, keep], axis=0) / \
+                np.linalg.norm(p_push[:, keep], axis=0)
+            assert np.max(err) < TOL_PUSH
+            em = ref["emitted"].astype(bool) & emit_gpu
+            g_push = np.sqrt(1 + np.sum(p_push ** 2, axis=0))
+            g_gpu = np.sqrt(1 + np.sum(pg ** 2, axis=0))
+            g_ref = np.sqrt(1 + np.sum(ref["p"] ** 2, axis=0))
+            assert np.all(np.abs(g_gpu[em] - g_ref[em]) <= recoil_tol * g_push[em])
+            rej_ref += int(ref["rejected"].sum())
+            ps[sp] = pg
+        if step == 1:  # newly created leptons store their force and never emit
+            assert c["emitted"] == 0 and c["blcfa_rejected"] == 0
+        assert abs(c["blcfa_rejected"] - rej_ref) <= 2 * max_flips + 2
+        # photons: never pushed; conversions against the oracle's local decisions
+        assert np.array_equal(ph.px.cpu().numpy(), wg["p"][0])
+        refg = O.step(O.PHOTON, wg["p"], wg["E"], wg["B"], np.zeros(n), wg["uid"].view(np.uint64),
+                      dt=h.dt, lc_over_lr=h.lc_over_lr, seed=8, step=step, decision=O.LOCAL)
+        conv = products_by_parent(prods, 1, "electrons")
+        conv_gpu = np.array([int(u) in conv for u in wg["uid"].view(np.uint64)])
+        rg = np.array([O.uniform(O.draw(8, int(u), step, O.P_LOCAL)[0])
+                       for u in wg["uid"].view(np.uint64)])
+        bandg = np.abs(refg["rate"] * h.dt - rg) <= band_tol * rg
+        assert not ((conv_gpu != refg["emitted"].astype(bool)) & ~bandg).any()
+        tot_emit += c["emitted"]
+        tot_rej += c["blcfa_rejected"]
+    assert tot_emit > 100 and tot_rej > 10  # the acceptance test was exercised
+
+
+def test_push_argument_validation(dev):
     h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, decision=sfq.LOCAL, blcfa=True)
-    w = inputs.general_fields(100, species=sfq.PHOTON)
-    tile = make_tile(w, dev, np.zeros(100), np.ones(100, dtype=np.uint8))
+    n = 100
+    z = lambda: torch.zeros(n, dtype=torch.float64, device=dev)
+    st = dict(uid=torch.arange(n, device=dev), fperp=torch.zeros(3 * n, dtype=torch.float64, device=dev),
+              dfperp=torch.zeros(3 * n, dtype=torch.float64, device=dev),
+              just_created=torch.ones(n, dtype=torch.uint8, device=dev))
+    pb, cnt = sfq.ProductBuffers.empty(10, 10, dev), sfq.Counters(dev)
+    # beyond-LCFA leptons: with the push the fields are required ...
     with pytest.raises(sfq.SFQError):
-        h.step([tile], seed=0, step=0, products=sfq.ProductBuffers.empty(10, 10, dev),
-               counters=sfq.Counters(dev), push=True)
+        h.step([sfq.TileArrays(sfq.ELECTRON, z(), z(), z(), **st)], seed=0, step=0, products=pb,
+               counters=cnt, push=True)
+    # ... without it the momentum before the push
+    with pytest.raises(sfq.SFQError):
+        h.step([sfq.TileArrays(sfq.ELECTRON, z(), z(), z(), *[z() for _ in range(6)], **st)],
+               seed=0, step=0, products=pb, counters=cnt)
+    # with the push and the fields, no p^{(n-1/2)} arrays are needed
+    h.step([sfq.TileArrays(sfq.ELECTRON, z() + 100.0, z(), z(), *[z() for _ in range(6)], **st)],
+           seed=0, step=0, products=pb, counters=cnt, push=True)
+    torch.cuda.synchronize()
+    assert cnt.as_dict()["processed"] == n
