@@ -197,6 +197,69 @@ def run_served(dev, jobs_per_client=16, steps=40):
     return res
 
 
+def constant_field_kernel_bytes(processed, emitted):
+    """Streaming-kernel bytes of a uniform-field electron tile with the fused push (no alive
+    array, optical depth): p and the optical depth read (32 B) for every particle; the pushed p
+    and the new depth written (32 B) for every particle that does not emit."""
+    return 32 * processed + 32 * (processed - emitted)
+
+
+def run_constant_field(dev, n, warmup=2):
+    """The paper's constant-field set-up at scale: n electrons of 10 GeV at chi = 1 in a uniform
+    magnetic field (one field value for the tile), 1.3 fs in 130 steps of 0.01 fs with the
+    fused push and recoil.  Returns timings, counters and the photon count against N T R."""
+    import torch
+
+    from paper_2301_07684_amd import inputs, sfq
+
+    seed = inputs.SEED_SYNC
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    K = int(round(inputs.T_SIM_FS / (inputs.DT_SECONDS * 1e15)))
+    s = inputs.synchrotron_t(n, dev, seed=seed)
+    g0 = inputs.GAMMA_10GEV
+    W = float(h.rates(sfq.ELECTRON, torch.tensor([g0], dtype=torch.float64, device=dev),
+                      torch.tensor([1.0], dtype=torch.float64, device=dev))[0])
+    tau = h.init_optical_depth(s["uid"], seed=seed)
+    tile = sfq.TileArrays(sfq.ELECTRON, s["p"][0], s["p"][1], s["p"][2], *s["E"], *s["B"],
+                          tau=tau, uid=s["uid"], uniform_fields=True)
+    pb = sfq.ProductBuffers.empty(int(n * W * h.dt * 1.5) + 10000, 1, dev)
+    cnt = sfq.Counters(dev)
+    h.reserve(n, 1)
+    for k in range(warmup):
+        pb.reset()
+        h.step([tile], seed=seed, step=k, products=pb, counters=cnt, push=True)
+    # back to the initial state for the measured run
+    torch.cuda.synchronize()
+    s["p"][0].fill_(s["pm"])
+    s["p"][1:].zero_()
+    h.init_optical_depth(s["uid"], seed=seed, out=tau)
+    cnt.reset()
+    h.profile(True)
+    h.profile_read()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        pb.reset()
+        ev[k][0].record(stream)
+        h.step([tile], seed=seed, step=k, products=pb, counters=cnt, push=True)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bulk_ms, emit_ms, nprof = h.profile_read()
+    c = cnt.as_dict()
+    if c["overflow"]:
+        raise RuntimeError("product buffers overflowed during the constant-field run")
+    h.close()
+    del tile, s, tau, pb
+    torch.cuda.empty_cache()
+    return dict(wall=wall, K=K, n=n, counters=c, W=W, dt=inputs.DT,
+                step_ms=np.array([a.elapsed_time(b) for a, b in ev]),
+                bulk_ms=bulk_ms / nprof, emit_ms=emit_ms / nprof)
+
+
 def cpu_baseline(n_sample=24576):
     """The oracle as it stands on a bounded sample of the FP64 workload (all host cores)."""
     from oracle import oracle as O
@@ -263,6 +326,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-push", action="store_true")
+    ap.add_argument("--no-constant-field", action="store_true")
+    ap.add_argument("--constant-field-n", type=int, default=1 << 30,
+                    help="electrons of the constant-field run")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--launch", default=None,
                     help="fixed launch shape BLOCKS_PER_CUxCHUNK for the FP64 and MIXED forms "
@@ -299,6 +365,10 @@ def main():
                                                dev, tuple(f64["shape"]), push=True)
     if fused is not None:
         print(f"# fused push form done: {fused['wall'] / args.steps * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
+    const = None if args.no_constant_field else run_constant_field(dev, args.constant_field_n)
+    if const is not None:
+        print(f"# constant-field run done: {const['wall'] / const['K'] * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
 
     c = f64["counters"]
@@ -409,6 +479,22 @@ def main():
                              "bulk_roofline_frac": fb / (fused["bulk_ms"] * 1e-3) / HBM_PEAK,
                              "emitted_per_step": pf("emitted"),
                              "converted_per_step": pf("converted")}
+    if const is not None:
+        cc = const["counters"]
+        kb = constant_field_kernel_bytes(cc["processed"] / const["K"], cc["emitted"] / const["K"])
+        n_a = const["n"] * const["K"] * const["W"] * const["dt"]
+        out["constant_field"] = {
+            "value": cc["processed"] / const["wall"], "unit": "particle-updates/s",
+            "dtype": "f64",
+            "workload": f"{const['n']} electrons of 10 GeV at chi = 1 in a uniform magnetic field "
+                        "(one value per tile), 1.3 fs = 130 steps, fused push, recoil",
+            "ms_per_step": const["wall"] / const["K"] * 1e3,
+            "p50_step_ms": float(np.percentile(const["step_ms"], 50)),
+            "p99_step_ms": float(np.percentile(const["step_ms"], 99)),
+            "bulk_kernel_ms": const["bulk_ms"], "emitter_pass_ms": const["emit_ms"],
+            "bulk_algorithmic_bytes": kb,
+            "bulk_roofline_frac": kb / (const["bulk_ms"] * 1e-3) / HBM_PEAK,
+            "photons": cc["emitted"], "N_T_R": n_a, "photons_over_N_T_R": cc["emitted"] / n_a}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

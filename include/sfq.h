@@ -158,6 +158,11 @@ typedef struct {
     uint64_t step_offset;      /* this tile's draws use step index desc->step + step_offset
                                   (mod 2^32): lets one launch advance tiles that are at different
                                   steps of their own simulations                                  */
+    int32_t uniform_fields;    /* 1: ex..bz each point to ONE double, the field of every particle
+                                  of the tile (a constant, uniform external field such as the
+                                  paper's Sec. 4.3 validation set-up: no per-particle field
+                                  traffic); 0: arrays of n                                        */
+    int32_t reserved3;         /* 0                                                               */
 } sfq_tile;
 
 /* Product buffers of one species (device SoA arrays of `capacity` elements). */

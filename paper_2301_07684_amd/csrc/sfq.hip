@@ -321,6 +321,7 @@ __device__ __forceinline__ sfq_tile uniform_tile(const sfq_tile& src)
     T.chi_out = uniform_ptr(src.chi_out);
     T.rate_out = uniform_ptr(src.rate_out);
     T.step_offset = uniform64(src.step_offset);
+    T.uniform_fields = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)src.uniform_fields);
     return T;
 }
 
@@ -409,6 +410,8 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
         // tiles without an alive array read a constant 1 instead (no branch)
         const uint8_t* alive = T.alive ? T.alive : k_alive_one;
         const uint64_t amask = T.alive ? ~0ull : 0ull;
+        // uniform fields: every lane reads element 0 (one cache line for the wave)
+        const uint64_t fmask = T.uniform_fields ? 0ull : ~0ull;
         // Every lane issues every load of an iteration in one group, the alive flag included
         // (lanes past the end of the chunk read its last particle and drop the result): one
         // memory round trip per iteration, with no load behind a data-dependent branch.  The
@@ -429,6 +432,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
                 // photon chunks.  With the push every chunk reads E and B, the tile's momentum
                 // is p^{(n-1/2)}, and lepton chunks read F_perp and Delta F in six more slots.
                 const uint64_t n = T.n;
+                const uint64_t jf = j & ((blcfa && !PUSH) ? ~0ull : fmask);  // slots 0..5
                 const double* q0 = (blcfa && !PUSH) ? T.px_prev : T.ex;
                 const double* q1 = (blcfa && !PUSH) ? T.py_prev : T.ey;
                 const double* q2 = (blcfa && !PUSH) ? T.pz_prev : T.ez;
@@ -443,8 +447,8 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
                 const double* q11 = blcfa ? T.fperp + n : T.py;
                 const double* q12 = blcfa ? T.fperp + 2 * n : T.pz;
                 double ux = ld_stream(&T.px[j]), uy = ld_stream(&T.py[j]), uz = ld_stream(&T.pz[j]);
-                const double a0 = ld_stream(&q0[j]), a1 = ld_stream(&q1[j]), a2 = ld_stream(&q2[j]);
-                const double a3 = ld_stream(&q3[j]), a4 = ld_stream(&q4[j]), a5 = ld_stream(&q5[j]);
+                const double a0 = ld_stream(&q0[jf]), a1 = ld_stream(&q1[jf]), a2 = ld_stream(&q2[jf]);
+                const double a3 = ld_stream(&q3[jf]), a4 = ld_stream(&q4[jf]), a5 = ld_stream(&q5[jf]);
                 const double rx = ld_stream(&q6[j]), ry = ld_stream(&q7[j]), rz = ld_stream(&q8[j]);
                 double o0 = 0.0, o1 = 0.0, o2 = 0.0;
                 if (PUSH) {
@@ -532,10 +536,11 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
                 }
             } else {
                 qx = ld_stream(&T.px[j]); qy = ld_stream(&T.py[j]); qz = ld_stream(&T.pz[j]);
-                const double ex = ld_stream(&T.ex[j]), ey = ld_stream(&T.ey[j]),
-                             ez = ld_stream(&T.ez[j]);
-                const double bx = ld_stream(&T.bx[j]), by = ld_stream(&T.by[j]),
-                             bz = ld_stream(&T.bz[j]);
+                const uint64_t jf = j & fmask;
+                const double ex = ld_stream(&T.ex[jf]), ey = ld_stream(&T.ey[jf]),
+                             ez = ld_stream(&T.ez[jf]);
+                const double bx = ld_stream(&T.bx[jf]), by = ld_stream(&T.by[jf]),
+                             bz = ld_stream(&T.bz[jf]);
                 double tau0 = 0.0;
                 if (LOCAL) quid = ld_stream(&T.uid[j]);
                 else tau0 = ld_stream(&T.tau[j]);
@@ -1376,6 +1381,8 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
         const std::string tn = " (tile " + std::to_string(t) + ")";
         if (T.species < 0 || T.species > 2)
             return fail(h, SFQ_E_ARG, "sfq_step: bad tile species" + tn);
+        if (T.uniform_fields != 0 && T.uniform_fields != 1)
+            return fail(h, SFQ_E_ARG, "sfq_step: uniform_fields must be 0 or 1" + tn);
         if (desc->nsets == 0 ? T.product_set != 0
                              : (T.product_set < 0 || T.product_set >= desc->nsets))
             return fail(h, SFQ_E_ARG, "sfq_step: product set index out of range" + tn);

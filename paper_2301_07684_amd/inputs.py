@@ -216,3 +216,28 @@ def plane_wave_t(n: int, device, seed: int = SEED_WAVE, species: int = ELECTRON,
     z = torch.zeros_like(gamma)
     return dict(species=species, p=torch.stack([-pm, z, z]), E=torch.stack([z, amp, z]),
                 B=torch.stack([z, z, amp]), uid=ids_t(seed + species, idx), a=a, phi=phi)
+
+
+# ---- constant-field validation set-up (paper Sec. 4.3: 10 GeV electrons at chi = 1 in a constant,
+# uniform magnetic field, 1.3 fs) ------------------------------------------------------------------
+ELECTRON_REST_MEV = 0.51099895000
+GAMMA_10GEV = 1.0e4 / ELECTRON_REST_MEV
+T_SIM_FS = 1.3
+SEED_SYNC = 107
+
+
+def synchrotron_t(n: int, device, seed: int = SEED_SYNC, gamma: float = GAMMA_10GEV,
+                  chi: float = 1.0):
+    """n electrons of energy gamma moving along +x in the uniform field B = b z with b set so
+    that chi = lambda_C |p| b / lambda_r.  Returns torch tensors: p (3, n) float64 and uid (n,)
+    int64 on `device`, and the one-element field arrays E (3 x zeros) and B (0, 0, b) for
+    tiles with uniform fields."""
+    import torch
+
+    pm = math.sqrt((gamma - 1.0) * (gamma + 1.0))
+    b = chi / (pm * LC_OVER_LR)
+    f = lambda v: torch.full((1,), v, dtype=torch.float64, device=device)
+    p = torch.zeros((3, n), dtype=torch.float64, device=device)
+    p[0].fill_(pm)
+    uid = ids_t(seed, torch.arange(n, dtype=torch.int64, device=device))
+    return dict(p=p, uid=uid, E=[f(0.0), f(0.0), f(0.0)], B=[f(0.0), f(0.0), f(b)], b=b, pm=pm)

@@ -50,7 +50,8 @@ class Tile(C.Structure):
                 ("bx", _P), ("by", _P), ("bz", _P), ("tau", _P), ("uid", _P), ("alive", _P),
                 ("px_prev", _P), ("py_prev", _P), ("pz_prev", _P), ("fperp", _P),
                 ("dfperp", _P), ("just_created", _P), ("chi_out", _P), ("rate_out", _P),
-                ("step_offset", C.c_uint64)]
+                ("step_offset", C.c_uint64), ("uniform_fields", C.c_int32),
+                ("reserved3", C.c_int32)]
 
 
 class ProductsC(C.Structure):
@@ -393,15 +394,17 @@ class TileArrays:
     rate_out: Optional[torch.Tensor] = None
     product_set: int = 0
     step_offset: int = 0
+    uniform_fields: bool = False  # ex..bz hold one value each, the field of every particle
 
     def __post_init__(self):
         n = self.px.numel()
         f64 = ("px", "py", "pz", "ex", "ey", "ez", "bx", "by", "bz", "tau", "px_prev", "py_prev",
                "pz_prev", "chi_out", "rate_out")
+        fields = ("ex", "ey", "ez", "bx", "by", "bz")
         for nm in f64:
             a = getattr(self, nm)
             if a is not None:
-                _dev(a, torch.float64, n, nm)
+                _dev(a, torch.float64, 1 if (self.uniform_fields and nm in fields) else n, nm)
         for nm in ("fperp", "dfperp"):
             a = getattr(self, nm)
             if a is not None:
@@ -419,8 +422,8 @@ class TileArrays:
 
     def to_c(self) -> Tile:
         t = Tile(species=self.species, product_set=self.product_set, n=self.n,
-                 step_offset=self.step_offset)
-        for nm, _ in Tile._fields_[3:-1]:
+                 step_offset=self.step_offset, uniform_fields=int(bool(self.uniform_fields)))
+        for nm, _ in Tile._fields_[3:-3]:
             setattr(t, nm, _ptr(getattr(self, nm)))
         return t
 
