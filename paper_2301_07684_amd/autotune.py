@@ -104,3 +104,64 @@ def tune(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], products: sfq.Prod
         cache[key] = entry
         save_cache(cache, cache_path)
     return dict(entry, cached=False, key=key)
+
+
+# ------------------------------------------------------------------------------------------------
+# Accuracy/speed dial
+# ------------------------------------------------------------------------------------------------
+# Relative error bound of each arithmetic form, per quantity: the bars its parity tests hold it
+# to (rates against the quadrature of Eqs. (wtilde), (wtilde_pair); sampled energy fractions
+# against the exact inversion of Eqs. (again), (again_pp)).
+FORM_ERRORS = {
+    sfq.FP64: {"rate": 1e-12, "sample": 1e-9},
+    sfq.MIXED: {"rate": 2e-5, "sample": 2e-5},
+}
+# bw_fast (App. A function 7) is not a relative error: pair creation is dropped below chi = 0.3,
+# where the pair rate is below 9.1e-6 alpha lambda_r / (lambda_C gamma) (Sec. 4.2).
+BW_FAST_BOUND = "pair creation dropped for chi < 0.3, where W_pair < 9.1e-6 alpha lambda_r/(lambda_C gamma)"
+
+
+def select_form(handle_kwargs: Dict, tiles: Sequence[sfq.TileArrays],
+                products: sfq.ProductBuffers, counters: sfq.Counters, *, max_rel_error: float,
+                allow_bw_fast: bool = False, seed: int = 0, step: int = 1,
+                candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES,
+                repeats: int = 4) -> Dict:
+    """The accuracy/speed dial (the analogue of the paper's choice of coefficient counts, Sec. 4.5,
+    and of its _fast pair functions, App. A functions 7 and 11): times every arithmetic form
+    whose error bound is within `max_rel_error` (FP64 always; MIXED from 2e-5; each also with
+    bw_fast when `allow_bw_fast`), each at its own best launch shape, on the caller's tiles, and
+    returns the fastest as {'handle', 'precision', 'bw_fast', 'shape', 'ms', 'error_bound',
+    'timings'}.  The other handles are closed; the particle state, product counts and counters
+    are restored.  handle_kwargs are the sfq.Handle arguments other than precision and bw_fast
+    (units, dt, decision, blcfa, device)."""
+    forms = [p for p in (sfq.FP64, sfq.MIXED)
+             if max(FORM_ERRORS[p].values()) <= max_rel_error]
+    if not forms:
+        raise ValueError(f"no form meets a relative error of {max_rel_error:g} "
+                         f"(FP64: {max(FORM_ERRORS[sfq.FP64].values()):g})")
+    fast = (False, True) if allow_bw_fast else (False,)
+    snap = _snapshot(tiles)
+    timings, best, handles = {}, None, []
+    try:
+        for prec in forms:
+            for bw in fast:
+                h = sfq.Handle(**handle_kwargs, precision=prec, bw_fast=bw)
+                handles.append(h)
+                r = tune(h, tiles, products, counters, seed=seed, step=step,
+                         candidates=candidates, repeats=repeats, cache_path=None)
+                _restore(tiles, snap)
+                name = ("fp64" if prec == sfq.FP64 else "mixed") + ("+bw_fast" if bw else "")
+                timings[name] = r["ms"]
+                if best is None or r["ms"] < best["ms"]:
+                    best = dict(handle=h, precision=prec, bw_fast=bw, shape=r["shape"],
+                                ms=r["ms"], name=name)
+    finally:
+        for h in handles:
+            if best is None or h is not best["handle"]:
+                h.close()
+    torch.cuda.synchronize()
+    bound = dict(FORM_ERRORS[best["precision"]])
+    if best["bw_fast"]:
+        bound["bw_fast"] = BW_FAST_BOUND
+    best.update(error_bound=bound, timings=timings)
+    return best

@@ -186,3 +186,41 @@ def test_extreme_launch_shapes_give_identical_results(dev, precision):
     assert c0["emitted"] > 1000 and c0["overflow"] == 0
     for st, ps, c in results[1:]:
         assert same(st, results[0][0]) and same(ps, results[0][1]) and c == c0
+
+
+def test_select_form_dial(dev):
+    """The accuracy/speed dial times only the forms within the error budget, returns the fastest
+    with its error bound, leaves the particle state as it was, and its handle steps exactly like
+    a fresh handle of the chosen form."""
+    kw = dict(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    h0 = sfq.Handle(**kw)
+    tiles = make_tiles(dev, h0, sizes=(40000, 30000, 20000, 10000))
+    before = state(tiles)
+    prods = sfq.ProductBuffers.empty(100000, 100000, dev)
+    cnt = sfq.Counters(dev)
+    cand = [(2, 4096), (8, 1024)]
+    r = autotune.select_form(kw, tiles, prods, cnt, max_rel_error=1e-8, candidates=cand, repeats=2)
+    assert r["precision"] == sfq.FP64 and not r["bw_fast"] and list(r["timings"]) == ["fp64"]
+    assert r["error_bound"] == {"rate": 1e-12, "sample": 1e-9}
+    assert all(np.array_equal(a, b) for a, b in zip(before, state(tiles)))
+    r["handle"].close()
+    r = autotune.select_form(kw, tiles, prods, cnt, max_rel_error=1e-4, allow_bw_fast=True,
+                             candidates=cand, repeats=2)
+    assert set(r["timings"]) == {"fp64", "fp64+bw_fast", "mixed", "mixed+bw_fast"}
+    assert r["ms"] == min(r["timings"].values())
+    assert ("bw_fast" in r["error_bound"]) == r["bw_fast"]
+    assert all(np.array_equal(a, b) for a, b in zip(before, state(tiles)))
+    assert prods.host_counts() == [0, 0, 0] and cnt.as_dict()["processed"] == 0
+    # the chosen handle is ready to use and gives the results of its form
+    a, b = clone_tiles(tiles), clone_tiles(tiles)
+    pa, pb = sfq.ProductBuffers.empty(100000, 100000, dev), sfq.ProductBuffers.empty(100000, 100000, dev)
+    r["handle"].step(a, seed=4, step=2, products=pa, counters=sfq.Counters(dev))
+    ref = sfq.Handle(**kw, precision=r["precision"], bw_fast=r["bw_fast"])
+    ref.step(b, seed=4, step=2, products=pb, counters=sfq.Counters(dev))
+    torch.cuda.synchronize()
+    assert all(np.array_equal(x, y) for x, y in zip(state(a), state(b)))
+    assert same(product_set(pa), product_set(pb))
+    r["handle"].close()
+    ref.close()
+    with pytest.raises(ValueError):
+        autotune.select_form(kw, tiles, prods, cnt, max_rel_error=1e-13)
