@@ -19,9 +19,11 @@
  *     available from sfq_last_error(); nothing is enqueued in that case.  Conditions found on
  *     the device (product-buffer overflow, chi beyond the tables) are reported in the
  *     sfq_counters structure of sfq_step.  No C++ exception crosses this interface.
- *   - A handle may be used from several host threads and streams at once for sfq_rates,
- *     sfq_chi, sfq_sample_* and sfq_philox; sfq_step calls that share a handle must be
- *     serialised by the caller (they share the handle's emitter queue).
+ *   - A handle may be used from several host threads and streams at once.  sfq_step calls on
+ *     different streams share the handle's emitter queue: the library orders them on the
+ *     device (a step waits for the previous step of the handle when it was enqueued on another
+ *     stream), so they are correct but do not overlap; use one handle per stream for
+ *     concurrency.  Inside a stream capture that ordering is the caller's graph's.
  */
 #ifndef SFQ_H
 #define SFQ_H

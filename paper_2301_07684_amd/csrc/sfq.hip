@@ -1011,6 +1011,10 @@ struct sfq_ctx {
     void* d_queue = nullptr;
     size_t queue_entries = 0;
     int queue_blocks = 0;
+    // the queue's last user: a step on another stream waits for this event before using it
+    hipEvent_t queue_free = nullptr;
+    hipStream_t queue_stream = nullptr;
+    bool queue_used = false;
     Staging staging[N_STAGING];
     int next_staging = 0;
     // launch shape of the step kernel (tunable)
@@ -1144,6 +1148,10 @@ static void release(sfq_ctx* h)
     for (auto* v : {&h->prof_used, &h->prof_free})
         for (auto& pe : *v)
             for (auto& e : pe.e) (void)hipEventDestroy(e);
+    if (h->queue_free) {
+        (void)hipEventSynchronize(h->queue_free);
+        (void)hipEventDestroy(h->queue_free);
+    }
     if (h->d_queue) (void)hipFree(h->d_queue);
     if (h->d_tab64) (void)hipFree(h->d_tab64);
     if (h->d_tab32) (void)hipFree(h->d_tab32);
@@ -1700,6 +1708,17 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     if (desc->nsets > 0)
         memcpy(hb + set_pos, desc->product_sets, desc->nsets * sizeof(sfq_product_set));
     HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, used, hipMemcpyHostToDevice, (hipStream_t)stream));
+    // steps on different streams share the emitter queue: order them on the device (outside
+    // stream capture, where the caller's graph orders its own nodes)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(h, hipStreamIsCapturing((hipStream_t)stream, &cap));
+    const bool order = cap == hipStreamCaptureStatusNone;
+    if (order) {
+        if (!h->queue_free)
+            HIP_TRY(h, hipEventCreateWithFlags(&h->queue_free, hipEventDisableTiming));
+        if (h->queue_used && h->queue_stream != (hipStream_t)stream)
+            HIP_TRY(h, hipStreamWaitEvent((hipStream_t)stream, h->queue_free, 0));
+    }
     // the queue shape must describe the allocation actually bound
     QueueShape bound = qs;
     bound.entries = h->queue_entries;
@@ -1714,6 +1733,11 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, prof_events(h));
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
+    if (order) {
+        HIP_TRY(h, hipEventRecord(h->queue_free, (hipStream_t)stream));
+        h->queue_stream = (hipStream_t)stream;
+        h->queue_used = true;
+    }
     return SFQ_OK;
 }
 

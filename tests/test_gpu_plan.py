@@ -224,3 +224,33 @@ def test_select_form_dial(dev):
     ref.close()
     with pytest.raises(ValueError):
         autotune.select_form(kw, tiles, prods, cnt, max_rel_error=1e-13)
+
+
+def test_one_handle_on_two_streams(dev):
+    """sfq_step calls of one handle on two streams, enqueued back to back with no host
+    synchronisation, give what sequential steps give (the handle orders its queue use)."""
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    ref_h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    a = make_tiles(dev, h, sizes=(300000, 1000))
+    b = make_tiles(dev, h, sizes=(5000, 200000, 7000))
+    ra, rb = clone_tiles(a), clone_tiles(b)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    pa, pb = sfq.ProductBuffers.empty(400000, 400000, dev), sfq.ProductBuffers.empty(400000, 400000, dev)
+    qa, qb = sfq.ProductBuffers.empty(400000, 400000, dev), sfq.ProductBuffers.empty(400000, 400000, dev)
+    ca, cb = sfq.Counters(dev), sfq.Counters(dev)
+    torch.cuda.synchronize()
+    for step in range(3):
+        h.step(a, seed=6, step=step, products=pa, counters=ca, stream=s1)
+        h.step(b, seed=6, step=step, products=pb, counters=cb, stream=s2)
+    torch.cuda.synchronize()
+    rca, rcb = sfq.Counters(dev), sfq.Counters(dev)
+    for step in range(3):
+        ref_h.step(ra, seed=6, step=step, products=qa, counters=rca)
+        ref_h.step(rb, seed=6, step=step, products=qb, counters=rcb)
+    torch.cuda.synchronize()
+    assert same(state(a), state(ra)) and same(state(b), state(rb))
+    assert pa.host_counts() == qa.host_counts() and pb.host_counts() == qb.host_counts()
+    assert same(product_set(pa), product_set(qa)) and same(product_set(pb), product_set(qb))
+    assert ca.as_dict() == rca.as_dict() and cb.as_dict() == rcb.as_dict()
+    assert ca.as_dict()["processed"] > 3 * 300000 and ca.as_dict()["overflow"] == 0
+    assert cb.as_dict()["overflow"] == 0
