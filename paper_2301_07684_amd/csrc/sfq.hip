@@ -1447,9 +1447,18 @@ static QueueShape queue_shape(const sfq_ctx* h, int nchunks, int blocks_per_cu, 
     return q;
 }
 
-// per entry: 8 doubles + 2 uint32 (72 bytes, 80 reserved); per block: 2 uint32 counts, the
-// processed count and 3 product bases
-static size_t queue_bytes(const QueueShape& q) { return q.entries * 80 + 40 * (size_t)q.grid + 256; }
+// Bytes per queue entry for the handle's form: chi, gamma, p (5 doubles) and index and tile
+// (2 uint32), plus the uid with local decisions and the two beyond-LCFA values.  Per block:
+// 2 uint32 counts, the processed count and 3 product bases.
+static size_t queue_entry_bytes(const sfq_ctx* h)
+{
+    return 48 + (h->decision == SFQ_LOCAL ? 8 : 0) + (h->blcfa ? 16 : 0);
+}
+
+static size_t queue_bytes(const sfq_ctx* h, const QueueShape& q)
+{
+    return q.entries * queue_entry_bytes(h) + 40 * (size_t)q.grid + 256;
+}
 
 // Emitter blocks per queue slice: enough emitter blocks to keep every compute unit busy with
 // the latency-bound emitter pass even when the streaming pass runs few, large blocks.
@@ -1461,7 +1470,10 @@ static int emit_split_for(const sfq_ctx* h, int grid)
     return std::max(1, std::min(16, (h->num_cus * SFQ_EMIT_BPC) / std::max(1, grid)));
 }
 
-static void bind_queue(StepArgs& A, void* mem, const QueueShape& qs)
+// The arrays of a queue of qs.entries entries at `mem` (layout of queue_entry_bytes): the
+// fields a form does not use are not allocated, and their pointers are null (the kernels
+// touch them only in the forms that use them).
+static void bind_queue(const sfq_ctx* h, StepArgs& A, void* mem, const QueueShape& qs)
 {
     char* q = (char*)mem;
     const size_t E = qs.entries;
@@ -1470,14 +1482,24 @@ static void bind_queue(StepArgs& A, void* mem, const QueueShape& qs)
     A.q_px = (double*)(q + 16 * E);
     A.q_py = (double*)(q + 24 * E);
     A.q_pz = (double*)(q + 32 * E);
-    A.q_uid = (uint64_t*)(q + 40 * E);
-    A.q_aux = (double*)(q + 48 * E);
-    A.q_aux2 = (double*)(q + 56 * E);
-    A.q_idx = (uint32_t*)(q + 64 * E);
-    A.q_tile = (uint32_t*)(q + 68 * E);
-    A.q_count = (uint32_t*)(q + 72 * E);
-    A.q_proc = (unsigned long long*)(q + 72 * E + 8 * (size_t)qs.grid);
-    A.q_base = (unsigned long long*)(q + 72 * E + 16 * (size_t)qs.grid);
+    size_t pos = 40 * E;
+    A.q_uid = nullptr;
+    A.q_aux = A.q_aux2 = nullptr;
+    if (h->decision == SFQ_LOCAL) {
+        A.q_uid = (uint64_t*)(q + pos);
+        pos += 8 * E;
+    }
+    if (h->blcfa) {
+        A.q_aux = (double*)(q + pos);
+        A.q_aux2 = (double*)(q + pos + 8 * E);
+        pos += 16 * E;
+    }
+    A.q_idx = (uint32_t*)(q + pos);
+    A.q_tile = (uint32_t*)(q + pos + 4 * E);
+    pos += 8 * E;
+    A.q_count = (uint32_t*)(q + pos);
+    A.q_proc = (unsigned long long*)(q + pos + 8 * (size_t)qs.grid);
+    A.q_base = (unsigned long long*)(q + pos + 16 * (size_t)qs.grid);
     A.q_cap_per_block = qs.cap_per_block;
     A.grid = qs.grid;
 }
@@ -1616,7 +1638,7 @@ static sfq_status ensure_queue(sfq_ctx* h, const QueueShape& qs, const char* who
         h->queue_entries = 0;
         h->queue_blocks = 0;
     }
-    if (hipMalloc(&h->d_queue, queue_bytes(want)) != hipSuccess) {
+    if (hipMalloc(&h->d_queue, queue_bytes(h, want)) != hipSuccess) {
         h->d_queue = nullptr;
         return fail(h, SFQ_E_NOMEM, std::string(who) + ": cannot allocate the emitter queue");
     }
@@ -1727,7 +1749,7 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     A.tiles = (const sfq_tile*)S.dev;
     A.chunk_off = (const uint32_t*)((char*)S.dev + off_pos);
     if (desc->nsets > 0) A.sets = (const sfq_product_set*)((char*)S.dev + set_pos);
-    bind_queue(A, h->d_queue, bound);
+    bind_queue(h, A, h->d_queue, bound);
     A.q_cap_per_block = qs.cap_per_block;
     A.emit_split = emit_split_for(h, qs.grid);
     launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, prof_events(h));
@@ -1765,7 +1787,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     sfq_plan_t* p = new sfq_plan_t();
     p->h = h;
     p->zero_counts = zero_product_counts ? 1 : 0;
-    if (hipMalloc(&p->d_mem, q_pos + queue_bytes(qs)) != hipSuccess) {
+    if (hipMalloc(&p->d_mem, q_pos + queue_bytes(h, qs)) != hipSuccess) {
         p->d_mem = nullptr;
         plan_release(p);
         return fail(h, SFQ_E_NOMEM, "sfq_plan_create: cannot allocate the plan");
@@ -1789,7 +1811,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     p->A.chunk_off = (const uint32_t*)((char*)p->d_mem + off_pos);
     p->A.step_ptr = p->d_step;
     if (desc->nsets > 0) p->A.sets = (const sfq_product_set*)((char*)p->d_mem + set_pos);
-    bind_queue(p->A, (char*)p->d_mem + q_pos, qs);
+    bind_queue(h, p->A, (char*)p->d_mem + q_pos, qs);
     p->A.emit_split = emit_split_for(h, qs.grid);
     *out = p;
     return SFQ_OK;
