@@ -179,7 +179,7 @@ def run_batched(steps, warmup, dev):
 
 def run_served(dev, jobs_per_client=16, steps=40):
     """Served form: 8 clients, Exp(2e6)-sized simulations (clamped to [1e4, 2e7]) arriving in a
-    burst, beyond-LCFA leptons, MIXED, admission under a 12 GiB budget, 2 lanes."""
+    burst, beyond-LCFA leptons, MIXED, admission under a 12 GiB budget, 3 lanes."""
     import torch
 
     from paper_2301_07684_amd import serve
@@ -188,7 +188,7 @@ def run_served(dev, jobs_per_client=16, steps=40):
     warm.add_jobs(serve.workload(clients=2, jobs_per_client=1, steps=3, mean=1e5, hi=2e5))
     warm.run()
     warm.close()
-    srv = serve.Server(dev, hbm_budget=12 << 30, lanes=2)
+    srv = serve.Server(dev, hbm_budget=12 << 30, lanes=3)
     srv.add_jobs(serve.workload(clients=8, jobs_per_client=jobs_per_client, steps=steps,
                                 think=0.002))
     res = srv.run(time_limit=300)
@@ -452,7 +452,7 @@ def main():
                          "workload": f"8 clients, {served['jobs']} simulations of Exp(2e6) "
                                      "particles (clamped [1e4, 2e7], half electrons with "
                                      "beyond-LCFA state, half photons), 40 steps each, burst "
-                                     "arrivals, 12 GiB HBM budget, 2 lanes",
+                                     "arrivals, 12 GiB HBM budget, 3 lanes",
                          "p50_request_ms": served["p50_ms"], "p99_request_ms": served["p99_ms"],
                          "requests": served["requests"], "batches": served["batches"],
                          "mean_batch_requests": served["mean_batch"],

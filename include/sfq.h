@@ -223,7 +223,9 @@ typedef struct {
                                   push supplies p^{(n+1/2)} to the force update of Sec. 5, so
                                   px_prev.. are not needed; lepton tiles then need E and B.
                                   0: momenta are taken as given                                   */
-    int32_t reserved2;         /* 0                                                               */
+    int32_t zero_product_counts; /* 1: the product counts (product_counts, or every set's) are
+                                  set to zero on the stream before the step, so that the buffers
+                                  receive this step's products only; 0: products are appended    */
 } sfq_step_desc;
 
 #define SFQ_MAX_TILES 4096
@@ -255,8 +257,9 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream);
 typedef struct sfq_plan_t* sfq_plan;
 
 /* Creates a plan for the tiles and buffers of `desc` (pointers are kept, the tile array is
- * copied; desc->step is the first step index).  zero_product_counts = 1 zeroes
- * desc->product_counts at the start of every step (with a kernel).  The handle's launch shape
+ * copied; desc->step is the first step index).  zero_product_counts = 1 (or
+ * desc->zero_product_counts = 1) zeroes the product counts at the start of every step (with a
+ * kernel).  The handle's launch shape
  * (sfq_set_launch) at creation time is used.  The plan must be destroyed before the handle. */
 sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_product_counts,
                            sfq_plan* out);

@@ -1382,6 +1382,8 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
         return fail(h, SFQ_E_ARG, "sfq_step: NULL product sets");
     if (desc->push != 0 && desc->push != 1)
         return fail(h, SFQ_E_ARG, "sfq_step: push must be 0 or 1");
+    if (desc->zero_product_counts != 0 && desc->zero_product_counts != 1)
+        return fail(h, SFQ_E_ARG, "sfq_step: zero_product_counts must be 0 or 1");
     const int nt = desc->ntiles;
     off.assign(nt + 1, 0);
     for (int t = 0; t < nt; ++t) {
@@ -1610,15 +1612,19 @@ static void plan_release(sfq_plan_t* p)
     delete p;
 }
 
+// zeroes the product counts of a step (a kernel, not a memset, so graphs replay it safely)
+static void enqueue_zero_counts(const StepArgs& A, hipStream_t st)
+{
+    if (A.nsets > 0)
+        hipLaunchKernelGGL(zero_set_counts_kernel, dim3((3 * A.nsets + 255) / 256), dim3(256), 0, st,
+                           A.sets, A.nsets);
+    else
+        hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, st, A.prod_counts);
+}
+
 static void plan_enqueue(sfq_plan_t* p, hipStream_t st, const ProfEvents* pe = nullptr)
 {
-    if (p->zero_counts) {
-        if (p->A.nsets > 0)
-            hipLaunchKernelGGL(zero_set_counts_kernel, dim3((3 * p->A.nsets + 255) / 256), dim3(256),
-                               0, st, p->A.sets, p->A.nsets);
-        else
-            hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, st, p->A.prod_counts);
-    }
+    if (p->zero_counts) enqueue_zero_counts(p->A, st);
     launch_step_kernels(p->h, p->A, p->grid, st, pe);
     hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, p->d_step);
 }
@@ -1752,6 +1758,7 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     bind_queue(h, A, h->d_queue, bound);
     A.q_cap_per_block = qs.cap_per_block;
     A.emit_split = emit_split_for(h, qs.grid);
+    if (desc->zero_product_counts) enqueue_zero_counts(A, (hipStream_t)stream);
     launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, prof_events(h));
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
@@ -1786,7 +1793,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     const size_t q_pos = step_pos + 256;
     sfq_plan_t* p = new sfq_plan_t();
     p->h = h;
-    p->zero_counts = zero_product_counts ? 1 : 0;
+    p->zero_counts = (zero_product_counts || desc->zero_product_counts) ? 1 : 0;
     if (hipMalloc(&p->d_mem, q_pos + queue_bytes(h, qs)) != hipSuccess) {
         p->d_mem = nullptr;
         plan_release(p);

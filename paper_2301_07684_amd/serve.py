@@ -104,12 +104,14 @@ class Scheduler:
         self.waiting: Deque[JobSpec] = collections.deque()
         self.ready: Deque[object] = collections.deque()
         self.deferred = set()  # jobs that had to wait for memory at least once
+        self._unmarked = 0     # jobs at the end of `waiting` not yet in `deferred`
 
     def arrive(self, spec: JobSpec):
         if spec.footprint > self.budget:
             raise ValueError(f"job {spec.job_id} needs {spec.footprint} B, more than the whole "
                              f"HBM budget of {self.budget} B")
         self.waiting.append(spec)
+        self._unmarked += 1
 
     def admit(self) -> List[JobSpec]:
         """Jobs admitted now, in arrival order; stops at the first that does not fit."""
@@ -118,7 +120,11 @@ class Scheduler:
             spec = self.waiting.popleft()
             self.used += spec.footprint
             out.append(spec)
-        self.deferred.update(spec.job_id for spec in self.waiting)
+        # the jobs left waiting had to wait for memory; only the latest arrivals are new
+        k = min(self._unmarked, len(self.waiting))
+        for i in range(len(self.waiting) - k, len(self.waiting)):
+            self.deferred.add(self.waiting[i].job_id)
+        self._unmarked = 0
         return out
 
     def release(self, spec: JobSpec):
@@ -195,7 +201,10 @@ class Simulation:
             2.0 * dt * self.step, dt, C.c_void_p(self.stream.cuda_stream))
         if st != 0:
             raise RuntimeError(f"harness push failed with HIP error {st}")
-        self.ready_event = torch.cuda.Event()
+        if self.ready_event is None:
+            self.ready_event = torch.cuda.Event()
+        # re-recording is safe: the lane's wait on the previous record was enqueued when that
+        # step was dispatched, before this push could be issued
         self.ready_event.record(self.stream)
 
     def tiles(self, product_set: int) -> List[sfq.TileArrays]:
@@ -297,11 +306,9 @@ class Server:
                 lane.stream.wait_event(req.sim.ready_event)
                 sets.append(req.sim.products)
                 tiles += req.sim.tiles(k)
-            with _on(lane.stream):
-                for pb in sets:
-                    pb.counts.zero_()
+            # every set receives this step's products only (zeroed by the step itself)
             lane.handle.step(tiles, seed=self.seed, step=0, counters=lane.counters,
-                             product_sets=sets, stream=lane.stream)
+                             product_sets=sets, zero_product_counts=True, stream=lane.stream)
             lane.event = _event(lane.stream)
             now = self._now()
             for req in batch:
@@ -366,12 +373,6 @@ class Server:
     def close(self):
         for lane in self.lanes:
             lane.handle.close()
-
-
-def _on(stream):
-    import torch
-
-    return torch.cuda.stream(stream)
 
 
 def _event(stream):

@@ -69,8 +69,10 @@ class StepDesc(C.Structure):
                 ("nsets", C.c_int32), ("tiles", C.POINTER(Tile)), ("photons", ProductsC),
                 ("electrons", ProductsC), ("positrons", ProductsC), ("product_counts", _P),
                 ("counters", _P), ("product_sets", C.POINTER(ProductSetC)),
-                ("push", C.c_int32), ("reserved2", C.c_int32)]
+                ("push", C.c_int32), ("zero_product_counts", C.c_int32)]
 
+
+_TILE_POINTERS = tuple(nm for nm, _ in Tile._fields_[3:-3])
 
 COUNTER_NAMES = ("processed", "emitted", "converted", "blcfa_rejected", "out_of_domain",
                  "clamped", "overflow", "reserved")
@@ -277,7 +279,8 @@ class Handle:
         return out
 
     @staticmethod
-    def _desc(tiles, seed, step, products, counters, product_sets=None, push=False):
+    def _desc(tiles, seed, step, products, counters, product_sets=None, push=False,
+              zero_product_counts=False):
         """Step descriptor.  With `product_sets` (a list of ProductBuffers), tile k's products go
         to product_sets[tiles[k].product_set] and `products` may be None.  push=True gives every
         alive lepton the Boris push through its tile's fields before the step."""
@@ -306,16 +309,19 @@ class Handle:
                         electrons=products.electrons.to_c() if products else none,
                         positrons=products.positrons.to_c() if products else none,
                         product_counts=_ptr(products.counts) if products else None,
-                        counters=_ptr(counters.t), product_sets=sets, push=int(bool(push)))
+                        counters=_ptr(counters.t), product_sets=sets, push=int(bool(push)),
+                        zero_product_counts=int(bool(zero_product_counts)))
         return desc, (arr, sets)
 
     def step(self, tiles: Sequence["TileArrays"], *, seed: int, step: int,
              products: Optional["ProductBuffers"] = None, counters: "Counters",
              product_sets: Optional[Sequence["ProductBuffers"]] = None, push: bool = False,
-             stream=None):
+             zero_product_counts: bool = False, stream=None):
         """One Monte Carlo step over all tiles (one launch sequence on `stream`); with
-        push=True the leptons' momenta are first pushed through their fields (fused)."""
-        desc, _keep = self._desc(tiles, seed, step, products, counters, product_sets, push)
+        push=True the leptons' momenta are first pushed through their fields (fused); with
+        zero_product_counts=True the product buffers receive this step's products only."""
+        desc, _keep = self._desc(tiles, seed, step, products, counters, product_sets, push,
+                                 zero_product_counts)
         self._check(self._L.sfq_step(self._h, C.byref(desc), _stream(stream)))
 
     def plan(self, tiles, *, seed: int, step: int, products: Optional["ProductBuffers"] = None,
@@ -421,11 +427,10 @@ class TileArrays:
         return self.px.numel()
 
     def to_c(self) -> Tile:
-        t = Tile(species=self.species, product_set=self.product_set, n=self.n,
-                 step_offset=self.step_offset, uniform_fields=int(bool(self.uniform_fields)))
-        for nm, _ in Tile._fields_[3:-3]:
-            setattr(t, nm, _ptr(getattr(self, nm)))
-        return t
+        ptrs = [None if a is None else a.data_ptr() for a in
+                (getattr(self, nm) for nm in _TILE_POINTERS)]
+        return Tile(self.species, self.product_set, self.n, *ptrs, self.step_offset,
+                    int(bool(self.uniform_fields)), 0)
 
 
 @dataclass

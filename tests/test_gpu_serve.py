@@ -209,3 +209,38 @@ def test_harness_push_matches_its_formula(dev):
     assert np.array_equal(sim.p_prev.cpu().numpy(), p0)
     assert np.allclose(sim.p.cpu().numpy(), ref, rtol=1e-14, atol=1e-12)
     assert np.array_equal(sim.p.cpu().numpy()[2], p0[2])
+
+
+def test_step_zeroes_product_counts(dev):
+    """zero_product_counts=True: the buffers (one set, or every set) hold this step's products
+    only, exactly as fresh buffers would."""
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    base = [owner_tiles(dev, h, o, sz) for o, sz in enumerate(OWNERS)]
+    flat = [t for tiles in base for t in tiles]
+    used = sfq.ProductBuffers.empty(20000, 20000, dev)
+    h.step(clone(flat), seed=1, step=1, products=used, counters=sfq.Counters(dev))
+    assert sum(used.host_counts()) > 0
+    fresh = sfq.ProductBuffers.empty(20000, 20000, dev)
+    a, b = clone(flat), clone(flat)
+    h.step(a, seed=1, step=2, products=used, counters=sfq.Counters(dev), zero_product_counts=True)
+    h.step(b, seed=1, step=2, products=fresh, counters=sfq.Counters(dev))
+    torch.cuda.synchronize()
+    assert same(state(a), state(b))
+    ca, pa = product_set(used)
+    cb, pb = product_set(fresh)
+    assert ca == cb and same(pa, pb)
+    # per-owner sets
+    sets_used = [sfq.ProductBuffers.empty(6000, 6000, dev) for _ in OWNERS]
+    sets_fresh = [sfq.ProductBuffers.empty(6000, 6000, dev) for _ in OWNERS]
+    mixed = lambda: [t for o, tiles in enumerate(base) for t in clone(tiles, product_set=o)]
+    h.step(mixed(), seed=1, step=1, counters=sfq.Counters(dev), product_sets=sets_used)
+    a, b = mixed(), mixed()
+    h.step(a, seed=1, step=2, counters=sfq.Counters(dev), product_sets=sets_used,
+           zero_product_counts=True)
+    h.step(b, seed=1, step=2, counters=sfq.Counters(dev), product_sets=sets_fresh)
+    torch.cuda.synchronize()
+    assert same(state(a), state(b))
+    for x, y in zip(sets_used, sets_fresh):
+        cx, px = product_set(x)
+        cy, py = product_set(y)
+        assert cx == cy and same(px, py)
