@@ -15,7 +15,11 @@ tiles (chi, rates, decisions, sampling, recoil, products).  Then, on the same GP
   * the served form: continuous batching of step requests from 8 clients' simulations with
     beyond-LCFA electrons, admitted under an HBM budget (request latency p50/p99);
   * the fused form: the headline workload with every electron's momentum pushed through its
-    fields (Boris) inside the streaming kernel before the QED step.
+    fields (Boris) inside the streaming kernel before the QED step;
+  * the plane-wave-fields form: the headline workload with its fields given as the plane wave
+    they come from (per-particle amplitude and phase; E and B computed in the kernel);
+  * the constant-field run: 2^30 electrons of 10 GeV at chi = 1 in a uniform magnetic field
+    (one value per tile) for 1.3 fs, fused push, recoil.
 
 Prints ONE JSON line: value = FP64 particle-updates/s over the timed steps; p50/p99 step
 latency; the roofline of the dominant (streaming) kernel from its own duration measured with HIP
@@ -66,7 +70,14 @@ def emit_kernel_bytes(emitted, converted):
     return 88 * emitted + 105 * converted
 
 
-def device_tiles(dev, sfq, h, workloads):
+def wave_stream_kernel_bytes(n_total, processed, emitted, converted):
+    """The streaming kernel with plane-wave tiles (fields computed in the kernel): as
+    stream_kernel_bytes, with the wave's amplitude and phase (16 B) read instead of E and B
+    (48 B)."""
+    return n_total + 48 * processed + 8 * (processed - emitted - converted)
+
+
+def device_tiles(dev, sfq, h, workloads, wave=False):
     import torch
 
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -74,15 +85,20 @@ def device_tiles(dev, sfq, h, workloads):
     for w in workloads:
         n = len(w["uid"])
         uid = t(w["uid"])
+        if wave:  # the same fields, E_y = B_z = a cos(phase), computed in the step
+            fields = dict(field_mode=sfq.FIELDS_PLANE_WAVE, wave_amp=t(w["wave_a"]),
+                          wave_phase=t(w["wave_phase"]), wave_k=(1.0, 0.0, 0.0),
+                          wave_pol=(0.0, 1.0, 0.0))
+        else:
+            fields = dict(ex=t(w["E"][0]), ey=t(w["E"][1]), ez=t(w["E"][2]), bx=t(w["B"][0]),
+                          by=t(w["B"][1]), bz=t(w["B"][2]))
         tiles.append(sfq.TileArrays(int(w["species"]), *[t(w["p"][k]) for k in range(3)],
-                                    *[t(w["E"][k]) for k in range(3)],
-                                    *[t(w["B"][k]) for k in range(3)],
-                                    tau=h.init_optical_depth(uid, seed=0), uid=uid,
+                                    **fields, tau=h.init_optical_depth(uid, seed=0), uid=uid,
                                     alive=torch.ones(n, dtype=torch.uint8, device=dev)))
     return tiles
 
 
-def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False):
+def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False, wave=False):
     import torch
 
     from paper_2301_07684_amd import autotune, inputs, sfq
@@ -94,7 +110,7 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False
             w = inputs.plane_wave(n, species=species)
         else:
             w = inputs.plane_wave(n, seed=inputs.SEED_SKEW, species=species, chi_range=(1e-4, 1e3))
-        tiles += device_tiles(dev, sfq, h, [w])
+        tiles += device_tiles(dev, sfq, h, [w], wave=wave)
         del w
     prods = sfq.ProductBuffers.empty(n // 4, n // 16, dev)
     cnt = sfq.Counters(dev)
@@ -221,7 +237,7 @@ def run_constant_field(dev, n, warmup=2):
                       torch.tensor([1.0], dtype=torch.float64, device=dev))[0])
     tau = h.init_optical_depth(s["uid"], seed=seed)
     tile = sfq.TileArrays(sfq.ELECTRON, s["p"][0], s["p"][1], s["p"][2], *s["E"], *s["B"],
-                          tau=tau, uid=s["uid"], uniform_fields=True)
+                          tau=tau, uid=s["uid"], field_mode=sfq.FIELDS_UNIFORM)
     pb = sfq.ProductBuffers.empty(int(n * W * h.dt * 1.5) + 10000, 1, dev)
     cnt = sfq.Counters(dev)
     h.reserve(n, 1)
@@ -327,6 +343,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-push", action="store_true")
     ap.add_argument("--no-constant-field", action="store_true")
+    ap.add_argument("--no-wave", action="store_true")
     ap.add_argument("--constant-field-n", type=int, default=1 << 30,
                     help="electrons of the constant-field run")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -365,6 +382,11 @@ def main():
                                                dev, tuple(f64["shape"]), push=True)
     if fused is not None:
         print(f"# fused push form done: {fused['wall'] / args.steps * 1e3:.3f} ms/step",
+              file=sys.stderr, flush=True)
+    wave = None if args.no_wave else run_form(0, "plane_wave", args.n, args.steps, args.warmup,
+                                              dev, tuple(f64["shape"]), wave=True)
+    if wave is not None:
+        print(f"# plane-wave fields form done: {wave['wall'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
     const = None if args.no_constant_field else run_constant_field(dev, args.constant_field_n)
     if const is not None:
@@ -479,6 +501,22 @@ def main():
                              "bulk_roofline_frac": fb / (fused["bulk_ms"] * 1e-3) / HBM_PEAK,
                              "emitted_per_step": pf("emitted"),
                              "converted_per_step": pf("converted")}
+    if wave is not None:
+        cw = wave["counters"]
+        pw = lambda k: cw[k] / K
+        wb = wave_stream_kernel_bytes(wave["n_total"], pw("processed"), pw("emitted"),
+                                      pw("converted"))
+        out["plane_wave_fields"] = {
+            "value": cw["processed"] / wave["wall"], "unit": "particle-updates/s", "dtype": "f64",
+            "workload": "the headline workload with its fields given as the plane wave they come "
+                        "from (per-particle amplitude and phase, E and B computed in the kernel)",
+            "ms_per_step": wave["wall"] / K * 1e3,
+            "p50_step_ms": float(np.percentile(wave["step_ms"], 50)),
+            "p99_step_ms": float(np.percentile(wave["step_ms"], 99)),
+            "bulk_kernel_ms": wave["bulk_ms"], "emitter_pass_ms": wave["emit_ms"],
+            "bulk_algorithmic_bytes": wb,
+            "bulk_roofline_frac": wb / (wave["bulk_ms"] * 1e-3) / HBM_PEAK,
+            "emitted_per_step": pw("emitted"), "converted_per_step": pw("converted")}
     if const is not None:
         cc = const["counters"]
         kb = constant_field_kernel_bytes(cc["processed"] / const["K"], cc["emitted"] / const["K"])

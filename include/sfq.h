@@ -56,6 +56,14 @@ typedef enum { SFQ_FP64 = 0, SFQ_MIXED = 1 } sfq_precision;
 /* Paper Sec. 2: optical-depth method (Eq. (any_event)) or local method (R dt > r). */
 typedef enum { SFQ_OPTICAL_DEPTH = 0, SFQ_LOCAL = 1 } sfq_decision;
 
+/* How a tile gives the fields at its particles (sfq_tile.field_mode).  ARRAYS: ex..bz are
+ * arrays of n.  UNIFORM: ex..bz each point to ONE double, the field of every particle of the
+ * tile (a constant, uniform external field such as the paper's Sec. 4.3 validation set-up).
+ * PLANE_WAVE: the step computes the fields of a linearly polarised plane wave,
+ * E = a_i cos(phi_i + theta) e, B = k x E, from the tile's wave_* members (ex..bz unused):
+ * the field traffic is that of a_i and phi_i (16 B per particle instead of 48). */
+typedef enum { SFQ_FIELDS_ARRAYS = 0, SFQ_FIELDS_UNIFORM = 1, SFQ_FIELDS_PLANE_WAVE = 2 } sfq_field_mode;
+
 /* Philox draw purposes (counter word 3).  See sfq_philox. */
 enum { SFQ_P_INIT = 0, SFQ_P_EMIT = 1, SFQ_P_CHILD = 2, SFQ_P_CHILD2 = 3, SFQ_P_LOCAL = 4 };
 
@@ -142,8 +150,9 @@ typedef struct {
     double *px, *py, *pz;      /* momentum, updated in place by recoil.  With blcfa leptons this
                                   is the pushed momentum p_L^{(n+1/2)} of Sec. 5, or, with
                                   desc->push, p^{(n-1/2)} (the step pushes it)                    */
-    const double *ex, *ey, *ez;/* electric field at the particle (blcfa leptons: only with push)  */
-    const double *bx, *by, *bz;/* magnetic field at the particle (blcfa leptons: only with push)  */
+    const double *ex, *ey, *ez;/* electric field at the particle (blcfa leptons: only with push);
+                                  see field_mode                                                  */
+    const double *bx, *by, *bz;/* magnetic field at the particle (as E)                           */
     double* tau;               /* remaining optical depth tau_d (OPTICAL_DEPTH; else nullable)    */
     const uint64_t* uid;       /* particle identifiers: the Philox counter of every draw          */
     uint8_t* alive;            /* nullable (all alive).  Converted photons are set to 0           */
@@ -160,11 +169,14 @@ typedef struct {
     uint64_t step_offset;      /* this tile's draws use step index desc->step + step_offset
                                   (mod 2^32): lets one launch advance tiles that are at different
                                   steps of their own simulations                                  */
-    int32_t uniform_fields;    /* 1: ex..bz each point to ONE double, the field of every particle
-                                  of the tile (a constant, uniform external field such as the
-                                  paper's Sec. 4.3 validation set-up: no per-particle field
-                                  traffic); 0: arrays of n                                        */
+    int32_t field_mode;        /* sfq_field_mode                                                  */
     int32_t reserved3;         /* 0                                                               */
+    const double* wave_amp;    /* PLANE_WAVE: amplitude a_i at each particle (n doubles, in
+                                  m c omega_r / e)                                                */
+    const double* wave_phase;  /* PLANE_WAVE: phase phi_i at each particle (n doubles, radians)  */
+    double wave_k[3];          /* PLANE_WAVE: unit propagation direction k                        */
+    double wave_pol[3];        /* PLANE_WAVE: unit polarisation e, perpendicular to k             */
+    double wave_phase0;        /* PLANE_WAVE: theta, added to every phase (omega t of the step)  */
 } sfq_tile;
 
 /* Product buffers of one species (device SoA arrays of `capacity` elements). */

@@ -2,8 +2,7 @@
 
     python -m paper_2301_07684_amd.build
 
-compiles csrc/sfq.hip into libsfq.so next to this file (hipcc, --offload-arch=gfx950), the
-serving harness's client push (csrc/harness.hip) into libsfq_harness.so, and
+compiles csrc/sfq.hip into libsfq.so next to this file (hipcc, --offload-arch=gfx950) and
 (re)generates data/sfq_tables.bin when the table generator's source changed.
 """
 from __future__ import annotations
@@ -17,9 +16,6 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libsfq.so")
 SOURCES = [os.path.join(HERE, "csrc", "sfq.hip")]
-# client-side push kernel of the serving harness (not part of the QED library)
-HARNESS_LIB = os.path.join(HERE, "libsfq_harness.so")
-HARNESS_SOURCES = [os.path.join(HERE, "csrc", "harness.hip")]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -58,10 +54,6 @@ def build_library(verbose: bool = True) -> str:
     return _hipcc_shared(LIB, SOURCES, verbose)
 
 
-def build_harness(verbose: bool = True) -> str:
-    return _hipcc_shared(HARNESS_LIB, HARNESS_SOURCES, verbose)
-
-
 def build_tables(verbose: bool = True) -> str:
     from . import tablegen
 
@@ -72,7 +64,6 @@ def build_tables(verbose: bool = True) -> str:
 def build(verbose: bool = True):
     build_tables(verbose)
     build_library(verbose)
-    build_harness(verbose)
 
 
 if __name__ == "__main__":

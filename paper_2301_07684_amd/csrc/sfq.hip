@@ -83,6 +83,7 @@ struct StepArgs {
     const sfq_product_set* sets; // nsets > 0: per-tile product destinations (device copy)
     int nsets;
     int push;                    // leptons get the Boris push before the step
+    int wave;                    // some tile gives its fields as a plane wave
 };
 
 enum { CNT_PROCESSED, CNT_EMITTED, CNT_CONVERTED, CNT_REJECTED, CNT_OOD, CNT_CLAMPED, CNT_OVERFLOW,
@@ -270,12 +271,15 @@ constexpr int STEP_BLOCK = 256;
 // form fits 93 registers (5 waves) and the mixed form 67 (6 waves); the mixed beyond-LCFA form
 // fits 128 (4 waves), while the FP64 beyond-LCFA form and the beyond-LCFA forms with the fused
 // push would spill to scratch at 128 and get 168 (3 waves).
+// The kernels that take plane-wave tiles (fields computed in the kernel, two particles per
+// lane in the LCFA loop) get 4 waves (LCFA) or one wave less than their array forms
+// (beyond-LCFA), for the same reason.
 #ifdef SFQ_BULK_WAVES
-constexpr int bulk_waves(bool, bool, bool) { return SFQ_BULK_WAVES; }
+constexpr int bulk_waves(bool, bool, bool, bool) { return SFQ_BULK_WAVES; }
 #else
-constexpr int bulk_waves(bool mixed, bool blcfa, bool push)
+constexpr int bulk_waves(bool mixed, bool blcfa, bool push, bool wave)
 {
-    return blcfa ? ((mixed && !push) ? 4 : 3) : (mixed ? 6 : 5);
+    return blcfa ? ((mixed && !push) ? 4 : 3) - (wave ? 1 : 0) : (wave ? 4 : (mixed ? 6 : 5));
 }
 #endif
 #ifndef SFQ_EMIT_WAVES
@@ -301,6 +305,11 @@ __device__ __forceinline__ P* uniform_ptr(P* p)
     return (P*)uniform64((uint64_t)p);
 }
 
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    return __longlong_as_double((long long)uniform64((uint64_t)__double_as_longlong(v)));
+}
+
 __device__ __forceinline__ sfq_tile uniform_tile(const sfq_tile& src)
 {
     sfq_tile T;
@@ -321,8 +330,43 @@ __device__ __forceinline__ sfq_tile uniform_tile(const sfq_tile& src)
     T.chi_out = uniform_ptr(src.chi_out);
     T.rate_out = uniform_ptr(src.rate_out);
     T.step_offset = uniform64(src.step_offset);
-    T.uniform_fields = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)src.uniform_fields);
+    T.field_mode = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)src.field_mode);
     return T;
+}
+
+// A tile's plane wave (field_mode SFQ_FIELDS_PLANE_WAVE), in scalar registers.
+struct Wave {
+    const double *amp, *phase;
+    double k[3], pol[3], phase0;
+};
+
+__device__ __forceinline__ Wave uniform_wave(const sfq_tile& src)
+{
+    Wave w;
+    w.amp = uniform_ptr(src.wave_amp);
+    w.phase = uniform_ptr(src.wave_phase);
+    for (int k = 0; k < 3; ++k) {
+        w.k[k] = uniform_f64(src.wave_k[k]);
+        w.pol[k] = uniform_f64(src.wave_pol[k]);
+    }
+    w.phase0 = uniform_f64(src.wave_phase0);
+    return w;
+}
+
+// Fields of a linearly polarised plane wave at a particle of amplitude a and phase ph:
+// E = a cos(ph + theta) e, B = k x E (units m c omega_r / e, so |B| = |E|); phases below
+// 2^20 pi/2 in magnitude (the domain of cos_cw).
+__device__ __forceinline__ void plane_wave_fields(const Wave& w, double a, double ph, double& ex,
+                                                  double& ey, double& ez, double& bx, double& by,
+                                                  double& bz)
+{
+    const double c = a * cos_cw(ph + w.phase0);
+    ex = c * w.pol[0];
+    ey = c * w.pol[1];
+    ez = c * w.pol[2];
+    bx = w.k[1] * ez - w.k[2] * ey;
+    by = w.k[2] * ex - w.k[0] * ez;
+    bz = w.k[0] * ey - w.k[1] * ex;
 }
 
 __device__ __forceinline__ int find_tile(const uint32_t* off, int ntiles, int c)
@@ -374,8 +418,101 @@ __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
 // was fetched one iteration earlier), so an iteration costs one memory round trip.  With
 // optical-depth decisions the particle id is not read here: only emitters need it, and the
 // emitter pass fetches it.
-template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH>
-__global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bulk_kernel(StepArgs A)
+// The LCFA particle loop of a plane-wave chunk, two particles per lane per iteration (see
+// bulk_kernel for the one-particle loop and its comments; the arithmetic is the same).
+template <bool MIXED, bool LOCAL, bool PUSH, typename RT>
+__device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_tile& T,
+                                                const Wave& WV, int t, uint64_t start,
+                                                uint64_t end, const uint8_t* alive,
+                                                uint64_t amask, uint32_t step, bool photon,
+                                                uint64_t qbase, const RT* s_rad,
+                                                const RT* s_pair, unsigned* s_qn,
+                                                unsigned long long& c_proc,
+                                                unsigned long long& c_ood)
+{
+    const int tid = threadIdx.x;
+    const double dt = A.ph.dt;
+    for (uint64_t base = start; base < end; base += 2 * STEP_BLOCK) {
+        uint64_t ii[2], quid[2];
+        uint8_t al[2];
+        double px[2], py[2], pz[2], wa[2], wp[2], tau0[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            ii[u] = base + (uint64_t)(u * STEP_BLOCK + tid);
+            const uint64_t j = min(ii[u], end - 1);
+            al[u] = ld_stream(&alive[j & amask]);
+            px[u] = ld_stream(&T.px[j]);
+            py[u] = ld_stream(&T.py[j]);
+            pz[u] = ld_stream(&T.pz[j]);
+            wa[u] = ld_stream(&WV.amp[j]);
+            wp[u] = ld_stream(&WV.phase[j]);
+            quid[u] = 0;
+            tau0[u] = 0.0;
+            if (LOCAL) quid[u] = ld_stream(&T.uid[j]);
+            else tau0[u] = ld_stream(&T.tau[j]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint64_t i = ii[u];
+            const bool live = i < end && al[u] != 0;
+            double ex, ey, ez, bx, by, bz;
+            double qx = px[u], qy = py[u], qz = pz[u];
+            plane_wave_fields(WV, wa[u], wp[u], ex, ey, ez, bx, by, bz);
+            const bool pushed = PUSH && !photon;
+            if (pushed) {
+                const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
+                boris_push(hq, ex, ey, ez, bx, by, bz, qx, qy, qz);
+            }
+            double gamma, chi;
+            bool ood = false;
+            gamma_chi(photon, qx, qy, qz, ex, ey, ez, bx, by, bz, A.ph.lc_over_lr, gamma, chi);
+            const double W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
+                                    : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+            bool emit;
+            if (!LOCAL) {
+                const double tau = tau0[u] - W * dt;
+                emit = live && tau < 0.0;
+                if (live && !emit) st_stream(&T.tau[i], tau);
+            } else {
+                const Draw d = philox_draw(A.seed, quid[u], step, SFQ_P_LOCAL);
+                emit = live && W * dt > uniform53(d.a);
+            }
+            if (pushed && live && !emit) {
+                st_stream(&T.px[i], qx); st_stream(&T.py[i], qy); st_stream(&T.pz[i], qz);
+            }
+            if (live) {
+                ++c_proc;
+                if (T.chi_out) T.chi_out[i] = chi;
+                if (T.rate_out) T.rate_out[i] = W;
+                c_ood += ood ? 1 : 0;
+            }
+            const unsigned long long mask = __ballot(emit);
+            if (mask) {
+                const int lane = lane_id();
+                const int leader = __ffsll((long long)mask) - 1;
+                unsigned off = 0;
+                if (lane == leader) off = atomicAdd(&s_qn[photon ? 1 : 0], (unsigned)__popcll(mask));
+                off = __shfl(off, leader);
+                if (emit) {
+                    const unsigned rank = off + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
+                    const uint64_t slot = photon ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
+                    A.q_idx[slot] = (uint32_t)i;
+                    A.q_tile[slot] = (uint32_t)t;
+                    A.q_chi[slot] = chi;
+                    A.q_gamma[slot] = gamma;
+                    A.q_px[slot] = qx;
+                    A.q_py[slot] = qy;
+                    A.q_pz[slot] = qz;
+                    if (LOCAL) A.q_uid[slot] = quid[u];
+                }
+            }
+        }
+    }
+}
+
+template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE>
+__global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) void bulk_kernel(StepArgs A)
 {
     static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
     using RT = typename std::conditional<MIXED, float, double>::type;
@@ -410,12 +547,27 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
         // tiles without an alive array read a constant 1 instead (no branch)
         const uint8_t* alive = T.alive ? T.alive : k_alive_one;
         const uint64_t amask = T.alive ? ~0ull : 0ull;
-        // uniform fields: every lane reads element 0 (one cache line for the wave)
-        const uint64_t fmask = T.uniform_fields ? 0ull : ~0ull;
+        // uniform fields: every lane reads element 0 (one cache line for the wave); a plane
+        // wave: the fields are computed from two loaded values per particle
+        const uint64_t fmask = T.field_mode == SFQ_FIELDS_UNIFORM ? 0ull : ~0ull;
+        const bool wave = WAVE && T.field_mode == SFQ_FIELDS_PLANE_WAVE;
+        Wave WV{};
+        if (WAVE) WV = uniform_wave(A.tiles[t]);
         // Every lane issues every load of an iteration in one group, the alive flag included
         // (lanes past the end of the chunk read its last particle and drop the result): one
         // memory round trip per iteration, with no load behind a data-dependent branch.  The
         // price is reading the fields of dead particles.
+        if constexpr (!BLCFA && WAVE) {
+            // LCFA chunks of plane-wave tiles read 16 B of fields per particle instead of 48,
+            // so one particle per lane leaves too few bytes in flight to cover HBM latency:
+            // every lane takes two particles per iteration, all loads in one group.
+            if (wave) {
+                lcfa_wave_pairs<MIXED, LOCAL, PUSH>(A, T, WV, t, start, end, alive, amask, step,
+                                                    photon, qbase, s_rad, s_pair, s_qn, c_proc,
+                                                    c_ood);
+                continue;
+            }
+        }
         for (uint64_t base = start; base < end; base += STEP_BLOCK) {
             const uint64_t i = base + tid;
             const uint64_t j = min(i, end - 1);
@@ -433,6 +585,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
                 // is p^{(n-1/2)}, and lepton chunks read F_perp and Delta F in six more slots.
                 const uint64_t n = T.n;
                 const uint64_t jf = j & ((blcfa && !PUSH) ? ~0ull : fmask);  // slots 0..5
+                const bool wave_f = wave && !(blcfa && !PUSH);  // slots 0..5 hold a plane wave
                 const double* q0 = (blcfa && !PUSH) ? T.px_prev : T.ex;
                 const double* q1 = (blcfa && !PUSH) ? T.py_prev : T.ey;
                 const double* q2 = (blcfa && !PUSH) ? T.pz_prev : T.ez;
@@ -447,8 +600,14 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
                 const double* q11 = blcfa ? T.fperp + n : T.py;
                 const double* q12 = blcfa ? T.fperp + 2 * n : T.pz;
                 double ux = ld_stream(&T.px[j]), uy = ld_stream(&T.py[j]), uz = ld_stream(&T.pz[j]);
-                const double a0 = ld_stream(&q0[jf]), a1 = ld_stream(&q1[jf]), a2 = ld_stream(&q2[jf]);
-                const double a3 = ld_stream(&q3[jf]), a4 = ld_stream(&q4[jf]), a5 = ld_stream(&q5[jf]);
+                double a0, a1, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0;
+                if (wave_f) {
+                    a0 = ld_stream(&WV.amp[j]);
+                    a1 = ld_stream(&WV.phase[j]);
+                } else {
+                    a0 = ld_stream(&q0[jf]); a1 = ld_stream(&q1[jf]); a2 = ld_stream(&q2[jf]);
+                    a3 = ld_stream(&q3[jf]); a4 = ld_stream(&q4[jf]); a5 = ld_stream(&q5[jf]);
+                }
                 const double rx = ld_stream(&q6[j]), ry = ld_stream(&q7[j]), rz = ld_stream(&q8[j]);
                 double o0 = 0.0, o1 = 0.0, o2 = 0.0;
                 if (PUSH) {
@@ -460,6 +619,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
                 quid = ld_stream(&T.uid[j]);
                 __builtin_amdgcn_sched_barrier(0);
                 live = i < end && al != 0;
+                if (wave_f) plane_wave_fields(WV, a0, a1, a0, a1, a2, a3, a4, a5);
                 // p^{(n-1/2)} and F_perp^{(n-1)}: loaded, or (with the push) the tile's momentum
                 // before the push and the six extra slots
                 double vx, vy, vz, ox, oy, oz;
@@ -537,10 +697,14 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
             } else {
                 qx = ld_stream(&T.px[j]); qy = ld_stream(&T.py[j]); qz = ld_stream(&T.pz[j]);
                 const uint64_t jf = j & fmask;
-                const double ex = ld_stream(&T.ex[jf]), ey = ld_stream(&T.ey[jf]),
-                             ez = ld_stream(&T.ez[jf]);
-                const double bx = ld_stream(&T.bx[jf]), by = ld_stream(&T.by[jf]),
-                             bz = ld_stream(&T.bz[jf]);
+                double ex, ey, ez = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+                if (wave) {
+                    ex = ld_stream(&WV.amp[j]);
+                    ey = ld_stream(&WV.phase[j]);
+                } else {
+                    ex = ld_stream(&T.ex[jf]); ey = ld_stream(&T.ey[jf]); ez = ld_stream(&T.ez[jf]);
+                    bx = ld_stream(&T.bx[jf]); by = ld_stream(&T.by[jf]); bz = ld_stream(&T.bz[jf]);
+                }
                 double tau0 = 0.0;
                 if (LOCAL) quid = ld_stream(&T.uid[j]);
                 else tau0 = ld_stream(&T.tau[j]);
@@ -549,6 +713,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH)) void bu
                 // one counter here), so a use scheduled between the loads would split the group
                 __builtin_amdgcn_sched_barrier(0);
                 live = i < end && al != 0;
+                if (wave) plane_wave_fields(WV, ex, ey, ex, ey, ez, bx, by, bz);
                 const bool pushed = PUSH && !photon;
                 if (pushed) {
                     const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
@@ -1391,8 +1556,8 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
         const std::string tn = " (tile " + std::to_string(t) + ")";
         if (T.species < 0 || T.species > 2)
             return fail(h, SFQ_E_ARG, "sfq_step: bad tile species" + tn);
-        if (T.uniform_fields != 0 && T.uniform_fields != 1)
-            return fail(h, SFQ_E_ARG, "sfq_step: uniform_fields must be 0 or 1" + tn);
+        if (T.field_mode < SFQ_FIELDS_ARRAYS || T.field_mode > SFQ_FIELDS_PLANE_WAVE)
+            return fail(h, SFQ_E_ARG, "sfq_step: bad field_mode" + tn);
         if (desc->nsets == 0 ? T.product_set != 0
                              : (T.product_set < 0 || T.product_set >= desc->nsets))
             return fail(h, SFQ_E_ARG, "sfq_step: product set index out of range" + tn);
@@ -1403,8 +1568,23 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
         if (T.n > 0) {
             if (!T.px || !T.py || !T.pz || !T.uid)
                 return fail(h, SFQ_E_ARG, "sfq_step: NULL momentum/uid" + tn);
-            if ((!bl || desc->push) && (!T.ex || !T.ey || !T.ez || !T.bx || !T.by || !T.bz))
+            const bool fields = !bl || desc->push;
+            if (fields && T.field_mode != SFQ_FIELDS_PLANE_WAVE &&
+                (!T.ex || !T.ey || !T.ez || !T.bx || !T.by || !T.bz))
                 return fail(h, SFQ_E_ARG, "sfq_step: NULL field array" + tn);
+            if (fields && T.field_mode == SFQ_FIELDS_PLANE_WAVE) {
+                if (!T.wave_amp || !T.wave_phase)
+                    return fail(h, SFQ_E_ARG, "sfq_step: NULL plane-wave array" + tn);
+                const double* k = T.wave_k;
+                const double* e = T.wave_pol;
+                const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+                const double ee = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+                const double ke = k[0] * e[0] + k[1] * e[1] + k[2] * e[2];
+                if (!(std::fabs(kk - 1.0) < 1e-12 && std::fabs(ee - 1.0) < 1e-12 &&
+                      std::fabs(ke) < 1e-12) || !std::isfinite(T.wave_phase0))
+                    return fail(h, SFQ_E_ARG,
+                                "sfq_step: plane wave needs unit k and e with k.e = 0" + tn);
+            }
             if (!bl && h->decision == SFQ_OPTICAL_DEPTH && !T.tau)
                 return fail(h, SFQ_E_ARG, "sfq_step: NULL tau" + tn);
             if (photon && !T.alive)
@@ -1527,6 +1707,9 @@ static void fill_args(const sfq_ctx* h, const sfq_step_desc* desc, StepArgs& A, 
     A.sets = nullptr;
     A.nsets = desc->nsets;
     A.push = desc->push;
+    A.wave = 0;
+    for (int t = 0; t < desc->ntiles; ++t)
+        if (desc->tiles[t].field_mode == SFQ_FIELDS_PLANE_WAVE) A.wave = 1;
 }
 
 // A set of timing events for one step (caller holds h->mu); nullptr when timing is off or the
@@ -1565,8 +1748,13 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
     } while (0)
 #define SFQ_LAUNCH_BULK(M, BL, L)                                                              \
     do {                                                                                       \
-        if (A.push) hipLaunchKernelGGL((bulk_kernel<M, BL, L, true>), g, b, 0, st, A);         \
-        else hipLaunchKernelGGL((bulk_kernel<M, BL, L, false>), g, b, 0, st, A);               \
+        if (A.push) {                                                                          \
+            if (A.wave) hipLaunchKernelGGL((bulk_kernel<M, BL, L, true, true>), g, b, 0, st, A); \
+            else hipLaunchKernelGGL((bulk_kernel<M, BL, L, true, false>), g, b, 0, st, A);     \
+        } else {                                                                               \
+            if (A.wave) hipLaunchKernelGGL((bulk_kernel<M, BL, L, false, true>), g, b, 0, st, A); \
+            else hipLaunchKernelGGL((bulk_kernel<M, BL, L, false, false>), g, b, 0, st, A);    \
+        }                                                                                      \
     } while (0)
     if (h->blcfa) {
         if (mixed) SFQ_LAUNCH_BULK(true, true, true);

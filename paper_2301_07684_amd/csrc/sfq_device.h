@@ -158,6 +158,50 @@ __device__ __forceinline__ void gamma_chi(bool photon, double px, double py, dou
 }
 
 // ---------------------------------------------------------------------------------------------
+// cos(x) for |x| < 2^20 pi/2 (about 1.6e6), register-light: x = k pi/2 + r with k = rint(2x/pi),
+// where pi/2 is split into parts of 33, 33 and 53 significant bits so that k times each of the
+// first two is exact (Cody and Waite's argument reduction) and r keeps a few-ulp relative
+// accuracy even where cos x is near zero; then the Taylor series of cos r (to r^16) or sin r
+// (to r^17) on |r| <= pi/4, whose truncation is below 1e-17 of the result.  Coefficients are
+// 1/n! rounded to double.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ double cos_cw(double x)
+{
+    constexpr double TWO_OVER_PI = 0.6366197723675814;
+    constexpr double P1 = 1.5707963267341256;     // pi/2 to 33 bits
+    constexpr double P2 = 6.077100506303966e-11;  // next 33 bits
+    constexpr double P3 = 2.0222662487959506e-21; // the rest
+    const double k = rint(x * TWO_OVER_PI);
+    double r = fma(-k, P1, x);
+    r = fma(-k, P2, r);
+    r = fma(-k, P3, r);
+    const double z = r * r;
+    // cos r = sum_j (-1)^j z^j / (2j)!,  sin r = r sum_j (-1)^j z^j / (2j+1)!,  j = 0..8
+    double c = 4.779477332387385e-14;             // 1/16!
+    c = fma(c, z, -1.1470745597729725e-11);       // 1/14!
+    c = fma(c, z, 2.08767569878681e-09);          // 1/12!
+    c = fma(c, z, -2.755731922398589e-07);        // 1/10!
+    c = fma(c, z, 2.48015873015873e-05);          // 1/8!
+    c = fma(c, z, -0.001388888888888889);         // 1/6!
+    c = fma(c, z, 0.041666666666666664);          // 1/4!
+    c = fma(c, z, -0.5);                          // 1/2!
+    c = fma(c, z, 1.0);
+    double s = 2.8114572543455206e-15;            // 1/17!
+    s = fma(s, z, -7.647163731819816e-13);        // 1/15!
+    s = fma(s, z, 1.6059043836821613e-10);        // 1/13!
+    s = fma(s, z, -2.505210838544172e-08);        // 1/11!
+    s = fma(s, z, 2.7557319223985893e-06);        // 1/9!
+    s = fma(s, z, -0.0001984126984126984);        // 1/7!
+    s = fma(s, z, 0.008333333333333333);          // 1/5!
+    s = fma(s, z, -0.16666666666666666);          // 1/3!
+    s = fma(s * z, r, r);
+    // cos(k pi/2 + r) = cos r, -sin r, -cos r, sin r for k = 0, 1, 2, 3 (mod 4)
+    const int q = (int)((long long)k & 3);
+    const double v = (q & 1) ? s : c;
+    return ((q + 1) & 2) ? -v : v;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Boris push (the leapfrog momentum update of the PIC cycle the step sits in, paper Fig. 7):
 // half an electric kick, a rotation about B by the angle 2 atan(|hq B| / gamma^-) evaluated at
 // the half-kicked momentum, and the second half kick; hq = q dt / 2 in the step's units (p in

@@ -110,18 +110,23 @@ def plane_wave(n: int, idx=None, seed: int = SEED_WAVE, species: int = ELECTRON,
     pm = gamma if species == PHOTON else np.sqrt((gamma - 1.0) * (gamma + 1.0))
     if chi_range is None:
         a = a_range[0] + (a_range[1] - a_range[0]) * uniforms(seed, stream0 + 1, idx)
-        amp = a * np.cos(2.0 * math.pi * uniforms(seed, stream0 + 2, idx))
+        phase = 2.0 * math.pi * uniforms(seed, stream0 + 2, idx)
+        amp = a * np.cos(phase)
         chi_t = None
     else:
         chi_t = _loguniform(uniforms(seed, stream0 + 3, idx), *chi_range)
         sign = np.where(uniforms(seed, stream0 + 4, idx) < 0.5, -1.0, 1.0)
-        amp = sign * chi_t / ((gamma + pm) * LC_OVER_LR)
+        a = sign * chi_t / ((gamma + pm) * LC_OVER_LR)
+        phase = np.zeros_like(a)
+        amp = a
     z = np.zeros_like(gamma)
     p = np.stack([-pm, z, z])
     E = np.stack([z, amp, z])
     B = np.stack([z, z, amp.copy()])
+    # wave_a, wave_phase: the same fields as a plane wave along +x polarised along y,
+    # E_y = B_z = wave_a cos(wave_phase)
     return dict(species=species, p=p, E=E, B=B, uid=ids(seed + species, idx), chi_target=chi_t,
-                gamma=gamma)
+                gamma=gamma, wave_a=a, wave_phase=phase)
 
 
 SEED_GENERAL = 106

@@ -12,54 +12,31 @@ step per tick of their own time loop.  The server
   what it was batched with (draws depend only on seed, uid, step and purpose);
 * keeps one batch in flight per lane, so requests that become ready while others run on the GPU
   are dispatched as soon as a lane frees up, and their work overlaps on the device;
-* records each request's latency, from submission (its client's push enqueued) until its
-  results are ready (the batch's completion event observed), plus throughput and admission
-  waits.
+* records each request's latency, from submission until its results are ready (the batch's
+  completion event observed), plus throughput and admission waits.
 
-The client side is a test harness, not part of the library.  Each simulation holds electrons
-with beyond-LCFA state (paper Sec. 5: the step needs p before and after the push) and photons,
-all in a linearly polarised plane wave.  Before every step the client pushes its electrons with
-a Lorentz-force kick (explicit, one kernel of the harness library libsfq_harness.so on the
-client's stream), which supplies p^{(n-1/2)} and p_L^{(n+1/2)}.
+The clients are a test harness, not part of the library.  Each simulation holds electrons with
+beyond-LCFA state (paper Sec. 5) and photons in a linearly polarised plane wave travelling along
++x, E = a cos(phi + 2 t) y, B = E_y z (each particle's amplitude a and phase phi; the phase
+advances by 2 dt per step for particles meeting the wave head-on).  The step computes those
+fields itself (plane-wave tiles) and pushes the electrons (Boris) before the QED step, which
+supplies p^{(n-1/2)} and p^{(n+1/2)} to the beyond-LCFA force update: a client's tick enqueues
+no GPU work of its own.
 """
 from __future__ import annotations
 
 import collections
-import ctypes as C
 import math
-import os
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Deque, Dict, List, Optional, Sequence
 
 from . import inputs, sfq
 
-_HARNESS = None
-
-
-def _harness():
-    """The harness's push kernel library (built next to the QED library; raises if missing)."""
-    global _HARNESS
-    if _HARNESS is None:
-        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsfq_harness.so")
-        if not os.path.exists(path):
-            raise RuntimeError(f"serving harness library not built: {path} is missing "
-                               "(run `python -m paper_2301_07684_amd.build`)")
-        L = C.CDLL(path)
-        L.harness_push_plane_wave.restype = C.c_int
-        L.harness_push_plane_wave.argtypes = [C.c_size_t] + [C.c_void_p] * 8 + \
-            [C.c_double, C.c_double, C.c_void_p]
-        _HARNESS = L
-    return _HARNESS
-
-
-def _p(t):
-    return C.c_void_p(t.data_ptr())
-
 
 # Device bytes per particle of a simulation (the footprint admission charges)
-LEPTON_BYTES = 8 * 3 * 4 + 8 + 1 + 8 + 8  # p, p_prev, F_perp, dF; uid; just_created; a; phi
-PHOTON_BYTES = 8 * 3 * 3 + 8 + 1           # p, E, B; uid; alive
+LEPTON_BYTES = 8 * 3 * 3 + 8 + 1 + 8 + 8  # p, F_perp, dF; uid; just_created; wave a, phi
+PHOTON_BYTES = 8 * 3 + 8 + 1 + 8 + 8       # p; uid; alive; wave a, phi
 PRODUCT_BYTES = 6 * 8                      # p, tau, uid, parent
 
 
@@ -169,58 +146,49 @@ class Simulation:
         self.spec, self.dev, self.stream = spec, dev, stream
         self.step = 0                 # steps done = the Philox step offset of the next one
         self.in_flight = False
-        self.ready_event = None
         self.last_batch = 0           # requests in the batch of the last step
         self._tiles = None
         with torch.cuda.stream(stream):
             e = inputs.plane_wave_t(spec.n_leptons, dev, seed=spec.seed, species=sfq.ELECTRON)
             self.p = e["p"].contiguous()
-            self.p_prev = self.p.clone()
             self.a, self.phi = e["a"], e["phi"]
             self.e_uid = e["uid"]
             self.fperp = torch.zeros(3 * spec.n_leptons, dtype=torch.float64, device=dev)
             self.dfperp = torch.zeros_like(self.fperp)
             self.just_created = torch.ones(spec.n_leptons, dtype=torch.uint8, device=dev)
             g = inputs.plane_wave_t(spec.n_photons, dev, seed=spec.seed, species=sfq.PHOTON)
-            self.k, self.kE, self.kB = g["p"].contiguous(), g["E"].contiguous(), g["B"].contiguous()
+            self.k = g["p"].contiguous()
+            self.ka, self.kphi = g["a"], g["phi"]
             self.g_uid = g["uid"]
             self.alive = torch.ones(spec.n_photons, dtype=torch.uint8, device=dev)
             self.products = sfq.ProductBuffers.empty(spec.photon_capacity, spec.pair_capacity, dev)
             del e, g
+        # the set-up ran on the client's stream: the first step waits for it
+        self.ready_event = torch.cuda.Event()
+        self.ready_event.record(stream)
 
-    def push(self, dt: float):
-        """Client work before a step: electrons get the Lorentz-force kick of the plane wave
-        E = a cos(phi + 2 t) y, B = a cos(phi + 2 t) z (charge -1), with p_prev the momentum
-        before the kick (one harness kernel on the client's stream)."""
-        import torch
+    def wave_phase0(self, dt: float) -> float:
+        """The phase the wave has advanced by at the current step (2 dt per step)."""
+        return 2.0 * dt * self.step
 
-        n = self.spec.n_leptons
-        st = _harness().harness_push_plane_wave(
-            n, _p(self.p[0]), _p(self.p[1]), _p(self.p[2]), _p(self.p_prev[0]),
-            _p(self.p_prev[1]), _p(self.p_prev[2]), _p(self.a), _p(self.phi),
-            2.0 * dt * self.step, dt, C.c_void_p(self.stream.cuda_stream))
-        if st != 0:
-            raise RuntimeError(f"harness push failed with HIP error {st}")
-        if self.ready_event is None:
-            self.ready_event = torch.cuda.Event()
-        # re-recording is safe: the lane's wait on the previous record was enqueued when that
-        # step was dispatched, before this push could be issued
-        self.ready_event.record(self.stream)
-
-    def tiles(self, product_set: int) -> List[sfq.TileArrays]:
-        """The simulation's tiles for a batched step (built once; the product set and the
-        Philox step offset change per step)."""
+    def tiles(self, product_set: int, dt: float) -> List[sfq.TileArrays]:
+        """The simulation's tiles for a batched step (built once; the product set, the Philox
+        step offset and the wave's phase change per step).  Both species are plane-wave tiles:
+        the step computes their fields and pushes the electrons."""
         if self._tiles is None:
+            wave = dict(field_mode=sfq.FIELDS_PLANE_WAVE, wave_k=(1.0, 0.0, 0.0),
+                        wave_pol=(0.0, 1.0, 0.0))
             lep = sfq.TileArrays(sfq.ELECTRON, self.p[0], self.p[1], self.p[2], uid=self.e_uid,
-                                 px_prev=self.p_prev[0], py_prev=self.p_prev[1],
-                                 pz_prev=self.p_prev[2], fperp=self.fperp, dfperp=self.dfperp,
-                                 just_created=self.just_created)
-            pho = sfq.TileArrays(sfq.PHOTON, self.k[0], self.k[1], self.k[2], *self.kE,
-                                 *self.kB, uid=self.g_uid, alive=self.alive)
+                                 fperp=self.fperp, dfperp=self.dfperp,
+                                 just_created=self.just_created, wave_amp=self.a,
+                                 wave_phase=self.phi, **wave)
+            pho = sfq.TileArrays(sfq.PHOTON, self.k[0], self.k[1], self.k[2], uid=self.g_uid,
+                                 alive=self.alive, wave_amp=self.ka, wave_phase=self.kphi, **wave)
             self._tiles = [t for t in (lep, pho) if t.n > 0]
         for t in self._tiles:
             t.product_set = product_set
             t.step_offset = self.step
+            t.wave_phase0 = self.wave_phase0(dt)
         return self._tiles
 
     @property
@@ -290,9 +258,9 @@ class Server:
             self.active[spec.job_id] = Simulation(spec, self.dev, stream)
 
     def _clients(self):
+        # a client's tick: the next step request (its fields and push are part of the step)
         for sim in self.active.values():
             if not sim.in_flight and sim.step < sim.spec.steps:
-                sim.push(self.dt)
                 sim.in_flight = True
                 self.sched.submit(Request(sim, self._now()))
 
@@ -303,12 +271,16 @@ class Server:
             batch = self.sched.next_batch(lambda r: r.sim.particles, lambda r: 2)
             tiles, sets = [], []
             for k, req in enumerate(batch):
-                lane.stream.wait_event(req.sim.ready_event)
+                if req.sim.ready_event is not None:  # its set-up, on its client's stream
+                    lane.stream.wait_event(req.sim.ready_event)
+                    req.sim.ready_event = None
                 sets.append(req.sim.products)
-                tiles += req.sim.tiles(k)
-            # every set receives this step's products only (zeroed by the step itself)
+                tiles += req.sim.tiles(k, self.dt)
+            # every set receives this step's products only (zeroed by the step itself); a
+            # simulation's previous step is complete (observed before its request was made)
             lane.handle.step(tiles, seed=self.seed, step=0, counters=lane.counters,
-                             product_sets=sets, zero_product_counts=True, stream=lane.stream)
+                             product_sets=sets, push=True, zero_product_counts=True,
+                             stream=lane.stream)
             lane.event = _event(lane.stream)
             now = self._now()
             for req in batch:

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libsfq.so")
 ELECTRON, POSITRON, PHOTON = 0, 1, 2
 FP64, MIXED = 0, 1
 OPTICAL_DEPTH, LOCAL = 0, 1
+FIELDS_ARRAYS, FIELDS_UNIFORM, FIELDS_PLANE_WAVE = 0, 1, 2
 P_INIT, P_EMIT, P_CHILD, P_CHILD2, P_LOCAL = 0, 1, 2, 3, 4
 MAX_TILES = 4096
 
@@ -50,8 +51,10 @@ class Tile(C.Structure):
                 ("bx", _P), ("by", _P), ("bz", _P), ("tau", _P), ("uid", _P), ("alive", _P),
                 ("px_prev", _P), ("py_prev", _P), ("pz_prev", _P), ("fperp", _P),
                 ("dfperp", _P), ("just_created", _P), ("chi_out", _P), ("rate_out", _P),
-                ("step_offset", C.c_uint64), ("uniform_fields", C.c_int32),
-                ("reserved3", C.c_int32)]
+                ("step_offset", C.c_uint64), ("field_mode", C.c_int32),
+                ("reserved3", C.c_int32), ("wave_amp", _P), ("wave_phase", _P),
+                ("wave_k", C.c_double * 3), ("wave_pol", C.c_double * 3),
+                ("wave_phase0", C.c_double)]
 
 
 class ProductsC(C.Structure):
@@ -72,7 +75,7 @@ class StepDesc(C.Structure):
                 ("push", C.c_int32), ("zero_product_counts", C.c_int32)]
 
 
-_TILE_POINTERS = tuple(nm for nm, _ in Tile._fields_[3:-3])
+_TILE_POINTERS = tuple(nm for nm, _ in Tile._fields_[3:23])
 
 COUNTER_NAMES = ("processed", "emitted", "converted", "blcfa_rejected", "out_of_domain",
                  "clamped", "overflow", "reserved")
@@ -400,17 +403,26 @@ class TileArrays:
     rate_out: Optional[torch.Tensor] = None
     product_set: int = 0
     step_offset: int = 0
-    uniform_fields: bool = False  # ex..bz hold one value each, the field of every particle
+    # how the fields are given: FIELDS_ARRAYS (ex..bz of n), FIELDS_UNIFORM (ex..bz of one
+    # value each), FIELDS_PLANE_WAVE (E = wave_amp cos(wave_phase + wave_phase0) wave_pol,
+    # B = wave_k x E, computed in the step)
+    field_mode: int = FIELDS_ARRAYS
+    wave_amp: Optional[torch.Tensor] = None
+    wave_phase: Optional[torch.Tensor] = None
+    wave_k: Sequence[float] = (1.0, 0.0, 0.0)
+    wave_pol: Sequence[float] = (0.0, 1.0, 0.0)
+    wave_phase0: float = 0.0
 
     def __post_init__(self):
         n = self.px.numel()
         f64 = ("px", "py", "pz", "ex", "ey", "ez", "bx", "by", "bz", "tau", "px_prev", "py_prev",
-               "pz_prev", "chi_out", "rate_out")
+               "pz_prev", "chi_out", "rate_out", "wave_amp", "wave_phase")
         fields = ("ex", "ey", "ez", "bx", "by", "bz")
+        uniform = self.field_mode == FIELDS_UNIFORM
         for nm in f64:
             a = getattr(self, nm)
             if a is not None:
-                _dev(a, torch.float64, 1 if (self.uniform_fields and nm in fields) else n, nm)
+                _dev(a, torch.float64, 1 if (uniform and nm in fields) else n, nm)
         for nm in ("fperp", "dfperp"):
             a = getattr(self, nm)
             if a is not None:
@@ -429,8 +441,11 @@ class TileArrays:
     def to_c(self) -> Tile:
         ptrs = [None if a is None else a.data_ptr() for a in
                 (getattr(self, nm) for nm in _TILE_POINTERS)]
+        wa, wp = self.wave_amp, self.wave_phase
         return Tile(self.species, self.product_set, self.n, *ptrs, self.step_offset,
-                    int(bool(self.uniform_fields)), 0)
+                    int(self.field_mode), 0, None if wa is None else wa.data_ptr(),
+                    None if wp is None else wp.data_ptr(), (C.c_double * 3)(*self.wave_k),
+                    (C.c_double * 3)(*self.wave_pol), float(self.wave_phase0))
 
 
 @dataclass

@@ -1,6 +1,6 @@
 """Uniform-field tiles and the constant-field validation run.
 
-1. A tile whose fields are uniform (one value per component, sfq_tile.uniform_fields) steps
+1. A tile whose fields are uniform (one value per component, sfq_tile.field_mode FIELDS_UNIFORM) steps
    exactly as the same tile with those values repeated in per-particle arrays: bit for bit, in
    every form (FP64 / MIXED, optical depth / local, with and without the fused push,
    beyond-LCFA with the push).
@@ -58,7 +58,7 @@ def _tiles(dev, h, n, uniform, field):
         else:
             fl = [torch.full((m,), v, dtype=torch.float64, device=dev) for v in (*E, *B)]
         kw = dict(uid=uid, alive=torch.ones(m, dtype=torch.uint8, device=dev),
-                  uniform_fields=uniform)
+                  field_mode=sfq.FIELDS_UNIFORM if uniform else sfq.FIELDS_ARRAYS)
         if h.blcfa and sp != sfq.PHOTON:
             kw.update(fperp=torch.zeros(3 * m, dtype=torch.float64, device=dev),
                       dfperp=torch.zeros(3 * m, dtype=torch.float64, device=dev),
@@ -118,7 +118,7 @@ def test_uniform_fields_validation(dev):
     z = torch.zeros(10, dtype=torch.float64, device=dev)
     with pytest.raises(ValueError):  # per-particle arrays where one value is expected
         sfq.TileArrays(sfq.ELECTRON, z, z, z, z, z, z, z, z, z, tau=z,
-                       uid=torch.arange(10, device=dev), uniform_fields=True)
+                       uid=torch.arange(10, device=dev), field_mode=sfq.FIELDS_UNIFORM)
 
 
 # ------------------------------------------------------------------------------------------------
@@ -137,7 +137,7 @@ def _run_synchrotron(dev, precision, n):
     g0 = inputs.GAMMA_10GEV
     tile = sfq.TileArrays(sfq.ELECTRON, s["p"][0], s["p"][1], s["p"][2], *s["E"], *s["B"],
                           tau=h.init_optical_depth(s["uid"], seed=seed), uid=s["uid"],
-                          uniform_fields=True)
+                          field_mode=sfq.FIELDS_UNIFORM)
     # bin edges of equal probability under the LCFA spectrum at (gamma_0, chi = 1)
     r = np.arange(1, BINS) / BINS
     edges = O.sample_photon(np.full(BINS - 1, g0), np.ones(BINS - 1), r)[0] / g0

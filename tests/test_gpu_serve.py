@@ -147,8 +147,8 @@ def _recorder(target_id, log):
         if sim.spec.job_id != target_id:
             return
         torch.cuda.synchronize()
-        st = [x.cpu().numpy().copy() for x in (sim.p, sim.p_prev, sim.fperp, sim.dfperp,
-                                                 sim.just_created, sim.k, sim.alive)]
+        st = [x.cpu().numpy().copy() for x in (sim.p, sim.fperp, sim.dfperp, sim.just_created,
+                                                 sim.k, sim.alive)]
         log.append((sim.step, sim.last_batch, st, product_set(sim.products)))
     return on_step
 
@@ -186,29 +186,6 @@ def test_served_results_are_the_same_alone_and_in_the_mix(dev):
     assert logs["mix_tight"][1]["waited"] > 0
     tot = logs["mix"][1]["counters"]
     assert tot["emitted"] > 0 and tot["blcfa_rejected"] >= 0
-
-
-def test_harness_push_matches_its_formula(dev):
-    """The serving harness's client push (not part of the library) against the same kick
-    written in numpy."""
-    n = 5000
-    spec = serve.JobSpec(9, n, 1, steps=1)
-    sim = serve.Simulation(spec, dev, torch.cuda.current_stream())
-    torch.cuda.synchronize()
-    p0 = sim.p.cpu().numpy().copy()
-    a, phi = sim.a.cpu().numpy(), sim.phi.cpu().numpy()
-    sim.step = 3
-    dt = inputs.DT
-    sim.push(dt)
-    torch.cuda.synchronize()
-    g = 1.0 / np.sqrt(1.0 + np.sum(p0 * p0, axis=0))
-    amp = a * np.cos(phi + 2.0 * dt * 3)
-    ref = p0.copy()
-    ref[0] = p0[0] - dt * (p0[1] * g) * amp
-    ref[1] = p0[1] - dt * (1.0 - p0[0] * g) * amp
-    assert np.array_equal(sim.p_prev.cpu().numpy(), p0)
-    assert np.allclose(sim.p.cpu().numpy(), ref, rtol=1e-14, atol=1e-12)
-    assert np.array_equal(sim.p.cpu().numpy()[2], p0[2])
 
 
 def test_step_zeroes_product_counts(dev):
