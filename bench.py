@@ -424,7 +424,7 @@ def main():
         "converted_per_step": per("converted"),
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": measured_traffic(),
-                     "kernel": "bulk_kernel<false, false, false, false> (streaming pass)",
+                     "kernel": "bulk_kernel<false, false, false, false, false> (streaming pass)",
                      "kernel_ms": f64["bulk_ms"], "algorithmic_bytes_per_launch": bulk_bytes},
         "emitter_pass": {"kernels": "scan_kernel + emit_kernel<false, false, false>",
                          "ms": f64["emit_ms"], "algorithmic_bytes_per_launch": emit_bytes,
