@@ -20,13 +20,39 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
+def _strip_comments(src: str) -> str:
+    """C/C++ source without its comments and blank-space runs (string and character literals
+    kept as they are), so that editing a comment does not change the hash below."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            i = src.find("\n", i)
+            i = n if i < 0 else i
+        elif src.startswith("/*", i):
+            k = src.find("*/", i + 2)
+            i = n if k < 0 else k + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources and the ABI header (identifies the kernels a profile was taken of)."""
+    """Hash of the HIP sources and the ABI header without their comments (identifies the
+    kernels a profile was taken of)."""
     h = hashlib.sha256()
     for f in (*SOURCES, os.path.join(HERE, "csrc", "sfq_device.h"),
               os.path.join(os.path.dirname(HERE), "include", "sfq.h")):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(_strip_comments(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

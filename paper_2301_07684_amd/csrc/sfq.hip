@@ -4,14 +4,19 @@
 // equation behind every device function.
 //
 // Kernel design (gfx950, wave64):
-//   bulk_kernel  persistent streaming pass over all tiles of a step: coalesced FP64 SoA loads,
-//                gamma, chi, the rate from LDS-staged coefficient tables and the decision;
-//                emitters are compacted with a wave ballot + popcount prefix into the block's
-//                own slice of a queue (one LDS atomic per wave, no global atomics).  It carries
-//                none of the sampling code, so its register footprint allows high occupancy.
-//   emit_kernel  block b samples the slice of block b with all lanes busy: Philox draws, the
-//                inverse-CDF tables (L2-resident), recoil and products (one global atomic per
-//                wave and product buffer).
+//   bulk_kernel  persistent streaming pass over all tiles of a step: coalesced FP64 SoA loads
+//                in one group per iteration, the fields (arrays, one uniform value, or a plane
+//                wave computed here), the optional Boris push, gamma, chi, the rate from
+//                LDS-staged coefficient tables and the decision (or the beyond-LCFA force
+//                update); emitters are compacted with a wave ballot + popcount prefix into the
+//                block's own slice of a queue (one LDS atomic per wave, no global atomics).  It
+//                carries none of the sampling code, so its register footprint allows high
+//                occupancy.
+//   scan_kernel  one block: prefix sums of the queued emitters over blocks give every block its
+//                product slots; the step's counters are written once.
+//   emit_kernel  each queue slice is sampled by a few blocks with all lanes busy: Philox draws,
+//                the inverse-CDF tables (L2-resident), recoil and products at the scanned slots
+//                (per-wave reservations only for beyond-LCFA photons and per-set products).
 //   rates/chi/sample/philox kernels: grid-stride elementwise kernels behind the batched calls.
 #include <hip/hip_runtime.h>
 

@@ -165,3 +165,18 @@ def test_inputs_are_counter_based():
     assert np.allclose(chi, full["chi_target"], rtol=1e-12)
     sizes, species = inputs.tile_sizes()
     assert sizes.min() >= 1000 and sizes.max() <= 4_000_000 and set(species) == {0, 1, 2}
+
+
+def test_kernel_source_hash_ignores_comments_only():
+    """The hash that ties committed profiles to the kernel sources changes with the code, not
+    with its comments."""
+    from paper_2301_07684_amd import build
+
+    a = 'int f(int x) { return x + 1; } // one\n/* two */ const char* s = "// kept";'
+    b = 'int f(int x) {\n  // a different comment\n  return x + 1;\n}\nconst char* s = "// kept";'
+    c = 'int f(int x) { return x + 2; }\nconst char* s = "// kept";'
+    d = 'int f(int x) { return x + 1; }\nconst char* s = "// changed";'
+    sa, sb = build._strip_comments(a), build._strip_comments(b)
+    assert sa == sb
+    assert build._strip_comments(c) != sa and build._strip_comments(d) != sa
+    assert len(build.kernel_source_hash()) == 16
