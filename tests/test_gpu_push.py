@@ -499,3 +499,75 @@ def test_plane_wave_validation(dev):
         t = sfq.TileArrays(sfq.ELECTRON, z + 10.0, z, z, **dict(kw, **bad))
         with pytest.raises(sfq.SFQError):
             h.step([t], seed=0, step=0, products=pb, counters=cnt)
+
+
+@pytest.mark.parametrize("push", [False, True])
+def test_mixed_field_modes_in_one_step(dev, push):
+    """Tiles with array, uniform and plane-wave fields in one step give exactly what each gives
+    stepped alone (a step with any plane-wave tile runs the kernel that also takes the other
+    modes; the arithmetic per particle is the same)."""
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    k, e = _orthonormal(5)
+    n = 7001
+
+    def make():
+        tiles = []
+        for j, mode in enumerate((sfq.FIELDS_ARRAYS, sfq.FIELDS_UNIFORM, sfq.FIELDS_PLANE_WAVE,
+                                  sfq.FIELDS_PLANE_WAVE)):
+            sp = (sfq.ELECTRON, sfq.POSITRON, sfq.ELECTRON, sfq.PHOTON)[j]
+            w = inputs.general_fields(n, seed=70 + 3 * j, species=sp)  # distinct uids
+            kw = dict(tau=h.init_optical_depth(T(w["uid"], dev), seed=2) * 0.05,
+                      uid=T(w["uid"], dev), alive=torch.ones(n, dtype=torch.uint8, device=dev),
+                      field_mode=mode)
+            if mode == sfq.FIELDS_ARRAYS:
+                kw.update({nm: T(w[f][i], dev) for f, names in (("E", ("ex", "ey", "ez")),
+                                                                ("B", ("bx", "by", "bz")))
+                           for i, nm in enumerate(names)})
+            elif mode == sfq.FIELDS_UNIFORM:
+                kw.update({nm: T(np.array([v]), dev) for nm, v in
+                           zip(("ex", "ey", "ez", "bx", "by", "bz"), (30., -70., 10., 5., 90., -40.))})
+            else:
+                idx = np.arange(n)
+                kw.update(wave_amp=T(10.0 ** (1 + 2 * inputs.uniforms(80 + j, 0, idx)), dev),
+                          wave_phase=T(2 * np.pi * inputs.uniforms(80 + j, 1, idx), dev),
+                          wave_k=tuple(k), wave_pol=tuple(e), wave_phase0=0.4 * j)
+            tiles.append(sfq.TileArrays(sp, *[T(w["p"][i], dev) for i in range(3)], **kw))
+        return tiles
+
+    def state_of(tiles, pb):
+        out = [torch.cat([t.px, t.py, t.pz, t.tau]).cpu().numpy() for t in tiles]
+        out += [t.alive.cpu().numpy() for t in tiles]
+        c = pb.host_counts()
+        for kk, name in enumerate(("photons", "electrons", "positrons")):
+            ps = getattr(pb, name)
+            m = c[kk]
+            order = np.lexsort((ps.uid[:m].cpu().numpy(), ps.parent[:m].cpu().numpy()))
+            out += [getattr(ps, f)[:m].cpu().numpy()[order] for f in ("px", "py", "pz", "tau", "uid")]
+        return out
+
+    together = make()
+    pb = sfq.ProductBuffers.empty(4 * n, 2 * n, dev)
+    h.step(together, seed=9, step=3, products=pb, counters=sfq.Counters(dev), push=push)
+    got = state_of(together, pb)
+    alone = make()
+    pbs = [sfq.ProductBuffers.empty(4 * n, 2 * n, dev) for _ in alone]
+    for t, p in zip(alone, pbs):
+        h.step([t], seed=9, step=3, products=p, counters=sfq.Counters(dev), push=push)
+    torch.cuda.synchronize()
+    # merge the separate products and compare everything
+    ref = [x for t in alone for x in state_of([t], sfq.ProductBuffers.empty(1, 1, dev))[:1]]
+    ref += [t.alive.cpu().numpy() for t in alone]
+    merged = sfq.ProductBuffers.empty(4 * n, 2 * n, dev)
+    for kk, name in enumerate(("photons", "electrons", "positrons")):
+        dst = getattr(merged, name)
+        pos = 0
+        for p in pbs:
+            m = p.host_counts()[kk]
+            for f in ("px", "py", "pz", "tau", "uid", "parent"):
+                getattr(dst, f)[pos:pos + m].copy_(getattr(getattr(p, name), f)[:m])
+            pos += m
+        merged.counts[kk] = pos
+    ref += state_of([], merged)
+    assert len(got) == len(ref)
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    assert pb.host_counts()[0] > 100 and pb.host_counts()[1] > 10
