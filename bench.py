@@ -122,8 +122,8 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False
     h.reserve(2 * n, 2)
     stream = torch.cuda.current_stream()
     for s in range(warmup):
-        prods.reset()
-        h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt, push=push)
+        h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt, push=push,
+               zero_product_counts=True)
     torch.cuda.synchronize()
     cnt.reset()
     h.profile(True)
@@ -133,9 +133,10 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        prods.reset()
         ev[s][0].record(stream)
-        h.step(tiles, seed=0, step=warmup + s + 1, products=prods, counters=cnt, push=push)
+        # the step zeroes the product counts itself: the buffers hold this step's products
+        h.step(tiles, seed=0, step=warmup + s + 1, products=prods, counters=cnt, push=push,
+               zero_product_counts=True)
         ev[s][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -242,8 +243,8 @@ def run_constant_field(dev, n, warmup=2):
     cnt = sfq.Counters(dev)
     h.reserve(n, 1)
     for k in range(warmup):
-        pb.reset()
-        h.step([tile], seed=seed, step=k, products=pb, counters=cnt, push=True)
+        h.step([tile], seed=seed, step=k, products=pb, counters=cnt, push=True,
+               zero_product_counts=True)
     # back to the initial state for the measured run
     torch.cuda.synchronize()
     s["p"][0].fill_(s["pm"])
@@ -258,9 +259,9 @@ def run_constant_field(dev, n, warmup=2):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
-        pb.reset()
         ev[k][0].record(stream)
-        h.step([tile], seed=seed, step=k, products=pb, counters=cnt, push=True)
+        h.step([tile], seed=seed, step=k, products=pb, counters=cnt, push=True,
+               zero_product_counts=True)
         ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
