@@ -254,3 +254,66 @@ def test_one_handle_on_two_streams(dev):
     assert ca.as_dict() == rca.as_dict() and cb.as_dict() == rcb.as_dict()
     assert ca.as_dict()["processed"] > 3 * 300000 and ca.as_dict()["overflow"] == 0
     assert cb.as_dict()["overflow"] == 0
+
+
+def test_maximum_tile_count_and_overflow_rerun(dev):
+    """SFQ_MAX_TILES ragged tiles (sizes 0..40, mixed species) give what the same particles give
+    in one tile per species; one tile more is refused.  A step that overflows its product
+    buffers, re-run from the restored state with buffers of the size it reported, gives what a
+    step with large buffers gives."""
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    sizes = (inputs.uniforms(5, 0, np.arange(sfq.MAX_TILES)) * 41).astype(int)
+    species = [sfq.ELECTRON, sfq.POSITRON, sfq.PHOTON]
+    tot = [int(sizes[k::3].sum()) for k in range(3)]
+    big = []
+    for k, sp in enumerate(species):
+        w = inputs.plain_compton(tot[k], seed=600 + k, species=sp)
+        uid = T(w["uid"], dev)
+        big.append(sfq.TileArrays(sp, *[T(w["p"][i], dev) for i in range(3)],
+                                  *[T(w["E"][i], dev) for i in range(3)],
+                                  *[T(w["B"][i], dev) for i in range(3)],
+                                  tau=h.init_optical_depth(uid, seed=4) * 0.3, uid=uid,
+                                  alive=torch.ones(tot[k], dtype=torch.uint8, device=dev)))
+    ref = clone_tiles(big)
+    # the same particles cut into MAX_TILES views, species cycling
+    small, pos = [], [0, 0, 0]
+    for t in range(sfq.MAX_TILES):
+        k, n = t % 3, int(sizes[t])
+        b = big[k]
+        sl = slice(pos[k], pos[k] + n)
+        small.append(sfq.TileArrays(b.species, b.px[sl], b.py[sl], b.pz[sl], b.ex[sl], b.ey[sl],
+                                    b.ez[sl], b.bx[sl], b.by[sl], b.bz[sl], tau=b.tau[sl],
+                                    uid=b.uid[sl], alive=b.alive[sl]))
+        pos[k] += n
+    assert pos == tot
+    cap = sum(tot)
+    pa, pr = sfq.ProductBuffers.empty(cap, cap, dev), sfq.ProductBuffers.empty(cap, cap, dev)
+    ca, cr = sfq.Counters(dev), sfq.Counters(dev)
+    h.step(small, seed=8, step=6, products=pa, counters=ca)
+    h.step(ref, seed=8, step=6, products=pr, counters=cr)
+    torch.cuda.synchronize()
+    assert same(state(big), state(ref))
+    assert same(product_set(pa), product_set(pr)) and ca.as_dict() == cr.as_dict()
+    assert ca.as_dict()["emitted"] > 100 and ca.as_dict()["converted"] > 10
+    with pytest.raises(ValueError):
+        h.step(small + small[:1], seed=8, step=6, products=pa, counters=ca)
+    # overflow, then re-run with the reported sizes
+    base = clone_tiles(ref)
+    a = clone_tiles(base)
+    tiny = sfq.ProductBuffers.empty(16, 4, dev)
+    ct = sfq.Counters(dev)
+    h.step(a, seed=3, step=1, products=tiny, counters=ct)
+    torch.cuda.synchronize()
+    need = tiny.host_counts()
+    assert ct.as_dict()["overflow"] > 0 and need[0] > 16
+    b = clone_tiles(base)
+    fit = sfq.ProductBuffers.empty(need[0], max(need[1], need[2]), dev)
+    cf = sfq.Counters(dev)
+    h.step(b, seed=3, step=1, products=fit, counters=cf)
+    c = clone_tiles(base)
+    large = sfq.ProductBuffers.empty(cap, cap, dev)
+    h.step(c, seed=3, step=1, products=large, counters=sfq.Counters(dev))
+    torch.cuda.synchronize()
+    assert cf.as_dict()["overflow"] == 0 and fit.host_counts() == need
+    assert same(state(a), state(c)) and same(state(b), state(c))
+    assert same(product_set(fit), product_set(large))
