@@ -173,7 +173,9 @@ typedef struct {
     int32_t reserved3;         /* 0                                                               */
     const double* wave_amp;    /* PLANE_WAVE: amplitude a_i at each particle (n doubles, in
                                   m c omega_r / e)                                                */
-    const double* wave_phase;  /* PLANE_WAVE: phase phi_i at each particle (n doubles, radians)  */
+    const double* wave_phase;  /* PLANE_WAVE: phase phi_i at each particle (n doubles, radians);
+                                  |phi_i + wave_phase0| must stay below 2^20 pi/2 (about 1.6e6),
+                                  the range of the step's cosine argument reduction             */
     double wave_k[3];          /* PLANE_WAVE: unit propagation direction k                        */
     double wave_pol[3];        /* PLANE_WAVE: unit polarisation e, perpendicular to k             */
     double wave_phase0;        /* PLANE_WAVE: theta, added to every phase (omega t of the step)  */
