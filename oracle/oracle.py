@@ -5,8 +5,8 @@ benchmark use this module; the product library never imports it.  The oracle com
 plain definitions of the strong-field QED step of Montefiori & Tamburini (arXiv:2301.07684):
 Bessel functions from their integral representations, the rates of Sec. 4.1-4.2 by adaptive
 quadrature, the energy samples of Sec. 4.3-4.4 by inverse transform sampling with Brent's root
-finder, the decisions of Sec. 2 and the beyond-LCFA steps of Sec. 5.  See the C source for the
-equation each function follows.
+finder, the decisions of Sec. 2, the beyond-LCFA steps of Sec. 5 and the Boris momentum push of
+the PIC cycle (Fig. 7).  See the C source for the equation each function follows.
 """
 from __future__ import annotations
 

@@ -16,6 +16,8 @@
  *                  Sec. 4.4 Eq. (again_pp), solved by Brent's root finder
  *   - decisions  : optical-depth method (paper Sec. 2, Eq. (any_event)) or local method (Sec. 2)
  *   - beyond-LCFA: paper Sec. 5, Eqs. (fl)-(condit), (gammaLCFA), (rej_cond)
+ *   - the momentum push of the PIC cycle the step sits in (paper Fig. 7): the Boris scheme,
+ *     in long double (the paper names no pusher; see orc_boris_push)
  *   - Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11), written from
  *     the published round definition.
  * No tabulation, no caching across calls, no approximation scheme of its own.
