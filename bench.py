@@ -8,7 +8,8 @@ counter-propagating through a linearly polarised plane wave (a ~ U[10, 500], ran
 gamma log-uniform [1e2, 1e5]), nonlinear Compton and Breit-Wheeler both active, optical-depth
 decisions, dt = 0.01 fs, FP64 SoA arrays resident in HBM.  A step is one sfq_step over both
 tiles (chi, rates, decisions, sampling, recoil, products).  Then, on the same GPU:
-  * the MIXED form on the skewed-chi ensemble (chi log-uniform [1e-4, 1e3]);
+  * the MIXED form on the skewed-chi ensemble (chi log-uniform [1e-4, 1e3]), and on the
+    headline workload itself (the FP32 / FP64 comparison on the same inputs);
   * the batched form: 64 uneven tiles of mixed species (sizes log-uniform 1e3..4e6, static-B
     geometry, chi log-uniform [1e-3, 1e2]), MIXED, launch shape from the autotuner, each step
     one replay of a HIP graph captured from a plan;
@@ -345,6 +346,7 @@ def main():
     ap.add_argument("--no-push", action="store_true")
     ap.add_argument("--no-constant-field", action="store_true")
     ap.add_argument("--no-wave", action="store_true")
+    ap.add_argument("--no-mixed-same", action="store_true")
     ap.add_argument("--constant-field-n", type=int, default=1 << 30,
                     help="electrons of the constant-field run")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -372,6 +374,11 @@ def main():
     if mixed is not None:
         print(f"# mixed form done: {mixed['wall'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
+    mixed_same = None if args.no_mixed_same else run_form(1, "plane_wave", args.n, args.steps,
+                                                          args.warmup, dev, launch)
+    if mixed_same is not None:
+        print(f"# mixed form on the headline workload done: "
+              f"{mixed_same['wall'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     batched = None if args.no_batched else run_batched(args.steps, args.warmup, dev)
     if batched is not None:
         print(f"# batched form done: {batched['wall'] / args.steps * 1e3:.3f} ms/step",
@@ -449,6 +456,22 @@ def main():
                         "bulk_roofline_frac": bb / (mixed["bulk_ms"] * 1e-3) / HBM_PEAK,
                         "emitted_per_step": pm("emitted"),
                         "converted_per_step": pm("converted")}
+    if mixed_same is not None:
+        cs_ = mixed_same["counters"]
+        ps_ = lambda k: cs_[k] / K
+        bs_ = stream_kernel_bytes(mixed_same["n_total"], ps_("processed"), ps_("emitted"),
+                                  ps_("converted"))
+        out["mixed_headline_workload"] = {
+            "value": cs_["processed"] / mixed_same["wall"], "unit": "particle-updates/s",
+            "dtype": "f32 (f64 chi, optical depth and tails)",
+            "workload": "the headline workload (plane wave, 2^24 + 2^24) in the MIXED form",
+            "ms_per_step": mixed_same["wall"] / K * 1e3,
+            "p50_step_ms": float(np.percentile(mixed_same["step_ms"], 50)),
+            "p99_step_ms": float(np.percentile(mixed_same["step_ms"], 99)),
+            "bulk_kernel_ms": mixed_same["bulk_ms"], "emitter_pass_ms": mixed_same["emit_ms"],
+            "bulk_roofline_frac": bs_ / (mixed_same["bulk_ms"] * 1e-3) / HBM_PEAK,
+            "speedup_over_fp64": (cs_["processed"] / mixed_same["wall"]) / value,
+            "emitted_per_step": ps_("emitted"), "converted_per_step": ps_("converted")}
     if batched is not None:
         cb = batched["counters"]
         pb = lambda k: cb[k] / K
