@@ -74,7 +74,7 @@ struct StepArgs {
     double* q_py;
     double* q_pz;
     uint64_t* q_uid;
-    double* q_aux;              // beyond-LCFA threshold gamma_{gamma,LCFA}
+    double* q_aux;              // beyond-LCFA tau/tau_C for the threshold (negative: LCFA)
     double* q_aux2;             // beyond-LCFA: gamma of the pushed momentum minus gamma^{(n)}
     uint32_t* q_count;          // [2 grid]: lepton and photon emitters queued by each block
     unsigned long long* q_proc; // [grid]: particles processed by each block of the streaming pass
@@ -273,18 +273,18 @@ __device__ __forceinline__ unsigned long long keyed_reserve(const sfq_product_se
 constexpr int STEP_BLOCK = 256;
 // minimum waves per SIMD requested from the register allocator for the two step kernels.  The
 // streaming kernel's register budget decides how many waves hide HBM latency: the FP64 LCFA
-// form fits 93 registers (5 waves) and the mixed form 67 (6 waves); the mixed beyond-LCFA form
-// fits 128 (4 waves), while the FP64 beyond-LCFA form and the beyond-LCFA forms with the fused
-// push would spill to scratch at 128 and get 168 (3 waves).
-// The kernels that take plane-wave tiles (fields computed in the kernel, two particles per
-// lane in the LCFA loop) get 4 waves (LCFA) or one wave less than their array forms
-// (beyond-LCFA), for the same reason.
+// form fits 93 registers (5 waves) and the mixed form 67 (6 waves).  The beyond-LCFA forms
+// (which leave the emission threshold's transcendentals to the emitter pass) fit 5 waves
+// (mixed), 4 (mixed with the push, FP64) or 3 (FP64 with the push).  The kernels that take
+// plane-wave tiles (fields computed in the kernel, two particles per lane in the LCFA loop)
+// get 4 waves (LCFA) or 3 (beyond-LCFA).
 #ifdef SFQ_BULK_WAVES
 constexpr int bulk_waves(bool, bool, bool, bool) { return SFQ_BULK_WAVES; }
 #else
 constexpr int bulk_waves(bool mixed, bool blcfa, bool push, bool wave)
 {
-    return blcfa ? ((mixed && !push) ? 4 : 3) - (wave ? 1 : 0) : (wave ? 4 : (mixed ? 6 : 5));
+    if (blcfa) return wave ? 3 : (mixed ? (push ? 4 : 5) : (push ? 3 : 4));
+    return wave ? 4 : (mixed ? 6 : 5);
 }
 #endif
 #ifndef SFQ_EMIT_WAVES
@@ -680,14 +680,13 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                             // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
                             const double pu2 = ux * ux + uy * uy + uz * uz;
                             aux2 = (pu2 - (g2 - 1.0)) / (sqrt(1.0 + pu2) + gamma);
+                            // tau / tau_C of Sec. 5 for the threshold gamma_{gamma,LCFA}, which
+                            // the emitter pass evaluates (only emitting lanes pay for its
+                            // transcendentals there); a negative value: LCFA throughout
                             if (flag) {
-                                const double tau_ratio = 2.0 * PI * sqrt(F2 / delta);
-                                const double arg = chi / (8.0 * gamma) * tau_ratio;
-                                aux = 0.7 * gamma /
-                                      (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
-                                if (!(aux < 0.75 * gamma)) emit = false;  // Eq. (gammaLCFA) check
+                                aux = 2.0 * PI * sqrt(F2 / delta);
                             } else if (chi > ZETA) {
-                                aux = 0.0;  // fields effectively constant: LCFA throughout
+                                aux = -1.0;  // fields effectively constant
                             } else {
                                 emit = false;
                             }
@@ -921,11 +920,23 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
             const double pn = sqrt(fma(px, px, fma(py, py, pz * pz)));
             if (!pair) {
                 const double gph = gamma * (s / (1.0 + s));
-                bool accept = true;
+                bool accept = true, none = false;
                 double gem = gamma / (1.0 + s);
                 if (BLCFA) {
-                    const double limit = A.q_aux[slot];
-                    if (!(gph > limit)) {  // Eq. (rej_cond)
+                    // the threshold gamma_{gamma,LCFA} (Eq. gammaLCFA) from the queued tau/tau_C
+                    const double tau_ratio = A.q_aux[slot];
+                    double limit = 0.0;
+                    if (tau_ratio >= 0.0) {
+                        const double arg = chi / (8.0 * gamma) * tau_ratio;
+                        limit = 0.7 * gamma /
+                                (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
+                    }
+                    // no emission at all when the threshold reaches 0.75 gamma (Sec. 5; it
+                    // cannot for finite input, as the threshold is at most 0.7 gamma)
+                    none = !(limit < 0.75 * gamma);
+                    if (none) {
+                        accept = false;
+                    } else if (!(gph > limit)) {  // Eq. (rej_cond)
                         const Draw dl = philox_draw(A.seed, uid, step, SFQ_P_LOCAL);
                         const double r2 = uniform53(dl.b);
                         const double lp_s = log_photon_pdf(A.tb.ka, A.tb.kb, gph, gamma, chi);
@@ -951,7 +962,7 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
                     // rejected: the lepton keeps the pushed momentum, which with the fused push
                     // the tile does not hold yet
                     if (A.push) { T.px[i] = px; T.py[i] = py; T.pz[i] = pz; }
-                    ++c_rej;
+                    if (!none) ++c_rej;
                 }
             } else {
                 const Draw d3 = philox_draw(A.seed, uid, step, SFQ_P_CHILD2);
