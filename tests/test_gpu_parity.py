@@ -417,21 +417,29 @@ def test_step_edge_cases(h64, dev):
     assert torch.all(tg.rate_out == 0)
 
 
-def test_step_full_size_plane_wave(h64, dev):
+@pytest.mark.parametrize("precision", [sfq.FP64, sfq.MIXED])
+def test_step_full_size_plane_wave(dev, precision):
     """The benchmark workload at full size (2^24 electrons + 2^24 photons) in the benchmark's
-    launch configuration: properties over all particles, oracle values on a sample."""
+    launch configuration (2 blocks per compute unit x 4096 particles per chunk): energy
+    conservation over every emitter, and the full outcome (rate, decision, recoil, products)
+    against the oracle on sampled particles, random ones and emitters."""
+    mixed = precision == sfq.MIXED
+    tol_rate, tol_sample, band = (TOL_MIXED, TOL_MIXED, TOL_MIXED) if mixed else \
+        (TOL_RATE, TOL_SAMPLE, BAND)
+    h = handle(precision=precision)
+    h.set_launch(2, 4096)
     n = 1 << 24
     rng = np.random.default_rng(11)
     tiles, ws, taus = [], [], []
     for species in (sfq.ELECTRON, sfq.PHOTON):
         w = inputs.plane_wave(n, species=species)
-        tau0 = h64.init_optical_depth(T(w["uid"], dev), seed=0)
+        tau0 = h.init_optical_depth(T(w["uid"], dev), seed=0)
         tiles.append(make_tile(w, dev, tau0.cpu().numpy()))
         ws.append(w)
         taus.append(tau0.cpu().numpy())
     prods = sfq.ProductBuffers.empty(n // 8, n // 32, dev)
     cnt = sfq.Counters(dev)
-    h64.step(tiles, seed=0, step=1, products=prods, counters=cnt)
+    h.step(tiles, seed=0, step=1, products=prods, counters=cnt)
     torch.cuda.synchronize()
     c = cnt.as_dict()
     assert c["processed"] == 2 * n and c["overflow"] == 0
@@ -448,12 +456,55 @@ def test_step_full_size_plane_wave(h64, dev):
     g_before = ws[0]["gamma"][idx]
     ok = g_after > 1.0 + 1e-6  # clamped recoils excluded
     assert np.max(rel(g_after[ok] + g_ph[ok], g_before[ok])) < 1e-9
-    # sampled particles: rate and decision against the oracle
-    for w, tile, tau0 in zip(ws, tiles, taus):
-        pick = rng.choice(n, 96, replace=False)
+    # sampled particles (random ones and emitters): the oracle's full step on each
+    maps = {name: products_by_parent(prods, name) for name in ("photons", "electrons",
+                                                              "positrons")}
+    for w, tile, tau0, key in zip(ws, tiles, taus, ("photons", "electrons")):
+        photon = w["species"] == sfq.PHOTON
+        got = maps[key]
+        base = np.uint64(w["uid"].view(np.uint64)[0])
+        emitters = np.array([int(np.uint64(u) - base) for u in list(got)[:4000]], dtype=np.int64)
+        assert emitters.size >= 60
+        pick = np.unique(np.concatenate([rng.choice(n, 80, replace=False),
+                                         rng.choice(emitters, 60, replace=False)]))
+        uids = w["uid"].view(np.uint64)[pick]
         sub = {kk: w[kk][:, pick] for kk in ("p", "E", "B")}
-        og, oc = O.chi(w["species"], sub["p"], sub["E"], sub["B"], h64.lc_over_lr)
-        W = O.rates(w["species"], og, oc, h64.lr_over_lc)
+        ref = O.step(w["species"], sub["p"], sub["E"], sub["B"], tau0[pick], uids, dt=h.dt,
+                     lc_over_lr=h.lc_over_lr, seed=0, step=1)
+        W = ref["rate"]
         rate = tile.rate_out.cpu().numpy()[pick]
-        assert np.array_equal(rate == 0, W == 0)
-        assert np.max(rel(rate[W > 0], W[W > 0])) < TOL_RATE
+        if mixed:
+            # where e^{-8/(3chi)} of the pair rate underflows in FP32 (to zero, too), an
+            # absolute tolerance
+            tiny = np.finfo(np.float32).tiny * h.lr_over_lc
+            assert np.all((np.abs(rate - W) <= tol_rate * W) | (np.abs(rate - W) <= tiny))
+        else:
+            assert np.array_equal(rate == 0, W == 0)
+            assert np.max(rel(rate[W > 0], W[W > 0])) < tol_rate
+        thr = W * h.dt
+        in_band = np.abs(tau0[pick] - thr) <= band * np.maximum(tau0[pick], thr)
+        emit_gpu = np.array([int(u) in got for u in uids])
+        emitted = ref["emitted"].astype(bool)
+        assert not ((emit_gpu != emitted) & ~in_band).any()
+        assert (emitted & ~in_band).sum() >= 50
+        # outcomes of the sampled emitters: recoil (leptons) and every product
+        em = emitted & ~in_band
+        if not photon:
+            p_gpu = np.stack([tile.px.cpu().numpy()[pick], tile.py.cpu().numpy()[pick],
+                              tile.pz.cpu().numpy()[pick]])
+            assert np.max(rel(np.linalg.norm(p_gpu[:, em], axis=0),
+                              np.linalg.norm(ref["p"][:, em], axis=0))) < tol_sample
+        band_uids = {int(u) for u in uids[in_band]}
+        checked = 0
+        for q in ref["products"]:
+            if q["parent"] in band_uids:
+                continue
+            name = {O.PHOTON: "photons", O.ELECTRON: "electrons", O.POSITRON: "positrons"}[
+                q["species"]]
+            pv, tau_q, uid_q = maps[name][q["parent"]]
+            assert uid_q == q["uid"] and abs(tau_q / q["tau"] - 1) < 1e-15
+            mref = math.sqrt(q["px"] ** 2 + q["py"] ** 2 + q["pz"] ** 2)
+            if mref > 0:
+                assert abs(np.linalg.norm(pv) / mref - 1) < tol_sample
+            checked += 1
+        assert checked >= 50
