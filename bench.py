@@ -336,7 +336,7 @@ def copy_calibration(dev, nbytes=1 << 31, reps=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 24, help="particles per species")
     ap.add_argument("--no-cpu-baseline", action="store_true")

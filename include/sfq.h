@@ -153,9 +153,14 @@ typedef struct {
     const double *ex, *ey, *ez;/* electric field at the particle (blcfa leptons: only with push);
                                   see field_mode                                                  */
     const double *bx, *by, *bz;/* magnetic field at the particle (as E)                           */
-    double* tau;               /* remaining optical depth tau_d (OPTICAL_DEPTH; else nullable)    */
+    double* tau;               /* remaining optical depth tau_d (OPTICAL_DEPTH; else nullable).
+                                  After the step: the decremented depth, a fresh one for a lepton
+                                  that emitted; a photon that converted keeps its decremented
+                                  (negative) depth                                                */
     const uint64_t* uid;       /* particle identifiers: the Philox counter of every draw          */
-    uint8_t* alive;            /* nullable (all alive).  Converted photons are set to 0           */
+    uint8_t* alive;            /* nullable (all alive).  Converted photons are set to 0.  Dead
+                                  particles are not processed; the step may rewrite their tau and
+                                  momentum slots with the values they hold                       */
     /* beyond-LCFA state (blcfa handles, lepton tiles; else NULL): the momentum before the push
      * p^{(n-1/2)} (not read, and may be NULL, with desc->push), the stored transverse Lorentz
      * force F_perp^{(n-1)} and its last difference (3n doubles each, component-major:

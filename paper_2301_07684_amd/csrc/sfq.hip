@@ -465,7 +465,7 @@ __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_til
             double qx = px[u], qy = py[u], qz = pz[u];
             plane_wave_fields(WV, wa[u], wp[u], ex, ey, ez, bx, by, bz);
             const bool pushed = PUSH && !photon;
-            if (pushed) {
+            if (pushed && live) {  // dead slots keep (and write back) their momentum
                 const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
                 boris_push(hq, ex, ey, ez, bx, by, bz, qx, qy, qz);
             }
@@ -478,12 +478,12 @@ __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_til
             if (!LOCAL) {
                 const double tau = tau0[u] - W * dt;
                 emit = live && tau < 0.0;
-                if (live && !emit) st_stream(&T.tau[i], tau);
+                if (i < end) st_stream(&T.tau[i], live ? tau : tau0[u]);  // whole lines
             } else {
                 const Draw d = philox_draw(A.seed, quid[u], step, SFQ_P_LOCAL);
                 emit = live && W * dt > uniform53(d.a);
             }
-            if (pushed && live && !emit) {
+            if (pushed && i < end) {
                 st_stream(&T.px[i], qx); st_stream(&T.py[i], qy); st_stream(&T.pz[i], qz);
             }
             if (live) {
@@ -631,7 +631,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                 if (PUSH) {
                     vx = ux; vy = uy; vz = uz;
                     ox = o0; oy = o1; oz = o2;
-                    if (blcfa) {
+                    if (blcfa && live) {  // dead slots keep (and write back) their momentum
                         const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
                         boris_push(hq, a0, a1, a2, a3, a4, a5, ux, uy, uz);
                     }
@@ -692,9 +692,10 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                             }
                         }
                     }
-                    // the pushed momentum of the leptons that do not emit (emitters: from the
-                    // queue in the emitter pass, after the recoil or the rejection)
-                    if (PUSH && live && !emit) {
+                    // the pushed momentum of every slot of the chunk, so that whole cache lines
+                    // are written (emitters get theirs again in the emitter pass, after the
+                    // recoil or the rejection; dead slots write back their own)
+                    if (PUSH && i < end) {
                         st_stream(&T.px[i], ux); st_stream(&T.py[i], uy); st_stream(&T.pz[i], uz);
                     }
                 }
@@ -719,7 +720,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                 live = i < end && al != 0;
                 if (wave) plane_wave_fields(WV, ex, ey, ex, ey, ez, bx, by, bz);
                 const bool pushed = PUSH && !photon;
-                if (pushed) {
+                if (pushed && live) {  // dead slots keep (and write back) their momentum
                     const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
                     boris_push(hq, ex, ey, ez, bx, by, bz, qx, qy, qz);
                 }
@@ -729,14 +730,19 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                 if (!LOCAL) {
                     const double tau = tau0 - W * dt;
                     emit = live && tau < 0.0;
-                    if (live && !emit) st_stream(&T.tau[i], tau);  // emitters: fresh depth later
+                    // Every slot of the chunk is written, dead ones with their own value: a
+                    // partly written cache line costs the memory a read-modify-write.  Emitters
+                    // get a fresh depth in the emitter pass; a converting photon keeps the
+                    // decremented one.
+                    if (i < end) st_stream(&T.tau[i], live ? tau : tau0);
                 } else {
                     const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
                     emit = live && W * dt > uniform53(d.a);
                 }
-                // the pushed momentum of the particles that do not emit (emitters recoil from
-                // the queued, pushed momentum in the emitter pass)
-                if (pushed && live && !emit) {
+                // the pushed momentum of every slot (whole cache lines, as for tau): emitters
+                // recoil from the queued, pushed momentum in the emitter pass, which then
+                // overwrites it
+                if (pushed && i < end) {
                     st_stream(&T.px[i], qx); st_stream(&T.py[i], qy); st_stream(&T.pz[i], qz);
                 }
             }
@@ -959,9 +965,8 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
                     want_ph = true;
                     ++c_emit;
                 } else {
-                    // rejected: the lepton keeps the pushed momentum, which with the fused push
-                    // the tile does not hold yet
-                    if (A.push) { T.px[i] = px; T.py[i] = py; T.pz[i] = pz; }
+                    // rejected: the lepton keeps the pushed momentum, which the streaming pass
+                    // has already written to the tile with the fused push
                     if (!none) ++c_rej;
                 }
             } else {

@@ -282,6 +282,9 @@ def check_step_against_oracle(w, tile, tau0, prods, h, *, seed, step, tol_rate, 
     else:
         alive = tile.alive.cpu().numpy()[pick]
         assert np.array_equal(alive, ref["alive"])
+        # every photon, converted or not, holds tau0 - W dt
+        err = np.abs(tau_gpu - ref["tau"])
+        assert np.all(err <= tol_rate * W[pick] * h.dt + 4e-16 * np.abs(tau0[pick]))
     prods_ref = {}
     for q in ref["products"]:
         prods_ref.setdefault(q["species"], {})[q["parent"]] = q

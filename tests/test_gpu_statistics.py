@@ -52,7 +52,7 @@ def run_steps(h, tile, pm, products, counters, seed):
         tile.px.fill_(pm)  # restore: no recoil, no conversion between steps
         tile.py.zero_()
         tile.pz.zero_()
-        # a converted photon is dead and keeps its old depth: revive it with a fresh,
+        # a converted photon is dead and keeps its spent depth: revive it with a fresh,
         # independent exponential depth (leptons get theirs from the step itself)
         dead = tile.alive == 0
         fresh = h.init_optical_depth(tile.uid, seed=seed + 1000 + s)
