@@ -230,6 +230,21 @@ __device__ __forceinline__ void st_stream(T* p, T v)
 #endif
 }
 
+// A streaming load or store at a uniform base plus a 32-bit lane byte offset: the particle
+// loops address a chunk (at most 2^22 particles) from its first element, so that every array
+// access is a global instruction with a scalar base and one shared 32-bit offset register,
+// with no 64-bit address arithmetic per array and lane.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off)
+{
+    return ld_stream((const T*)((const char*)base + byte_off));
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T* base, uint32_t byte_off, T v)
+{
+    st_stream((T*)((char*)base + byte_off), v);
+}
+
 // wave-aggregated reservation of `want` slots on a global counter; returns this lane's slot
 __device__ __forceinline__ unsigned long long wave_reserve(unsigned long long* counter, bool want)
 {
@@ -437,24 +452,27 @@ __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_til
 {
     const int tid = threadIdx.x;
     const double dt = A.ph.dt;
+    const uint32_t cn = (uint32_t)(end - start);  // chunk-relative offsets, as in bulk_kernel
     for (uint64_t base = start; base < end; base += 2 * STEP_BLOCK) {
         uint64_t ii[2], quid[2];
+        uint32_t oo[2];
         uint8_t al[2];
         double px[2], py[2], pz[2], wa[2], wp[2], tau0[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             ii[u] = base + (uint64_t)(u * STEP_BLOCK + tid);
-            const uint64_t j = min(ii[u], end - 1);
-            al[u] = ld_stream(&alive[j & amask]);
-            px[u] = ld_stream(&T.px[j]);
-            py[u] = ld_stream(&T.py[j]);
-            pz[u] = ld_stream(&T.pz[j]);
-            wa[u] = ld_stream(&WV.amp[j]);
-            wp[u] = ld_stream(&WV.phase[j]);
+            oo[u] = (uint32_t)(base - start) + (uint32_t)(u * STEP_BLOCK + tid);
+            const uint32_t oj = min(oo[u], cn - 1u), ob = oj * 8u;
+            al[u] = ld_off(alive + (start & amask), oj & (uint32_t)amask);
+            px[u] = ld_off(T.px + start, ob);
+            py[u] = ld_off(T.py + start, ob);
+            pz[u] = ld_off(T.pz + start, ob);
+            wa[u] = ld_off(WV.amp + start, ob);
+            wp[u] = ld_off(WV.phase + start, ob);
             quid[u] = 0;
             tau0[u] = 0.0;
-            if (LOCAL) quid[u] = ld_stream(&T.uid[j]);
-            else tau0[u] = ld_stream(&T.tau[j]);
+            if (LOCAL) quid[u] = ld_off(T.uid + start, ob);
+            else tau0[u] = ld_off(T.tau + start, ob);
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -478,13 +496,14 @@ __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_til
             if (!LOCAL) {
                 const double tau = tau0[u] - W * dt;
                 emit = live && tau < 0.0;
-                if (i < end) st_stream(&T.tau[i], live ? tau : tau0[u]);  // whole lines
+                if (oo[u] < cn) st_off(T.tau + start, oo[u] * 8u, live ? tau : tau0[u]);  // whole lines
             } else {
                 const Draw d = philox_draw(A.seed, quid[u], step, SFQ_P_LOCAL);
                 emit = live && W * dt > uniform53(d.a);
             }
-            if (pushed && i < end) {
-                st_stream(&T.px[i], qx); st_stream(&T.py[i], qy); st_stream(&T.pz[i], qz);
+            if (pushed && oo[u] < cn) {
+                st_off(T.px + start, oo[u] * 8u, qx); st_off(T.py + start, oo[u] * 8u, qy);
+                st_off(T.pz + start, oo[u] * 8u, qz);
             }
             if (live) {
                 ++c_proc;
@@ -573,10 +592,13 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                 continue;
             }
         }
+        const uint32_t cn = (uint32_t)(end - start);  // chunk-relative offsets below
         for (uint64_t base = start; base < end; base += STEP_BLOCK) {
             const uint64_t i = base + tid;
             const uint64_t j = min(i, end - 1);
-            const uint8_t al = ld_stream(&alive[j & amask]);
+            const uint32_t o = (uint32_t)(base - start) + (uint32_t)tid;  // i - start
+            const uint32_t oj = min(o, cn - 1u), ob = oj * 8u;               // j - start, bytes
+            const uint8_t al = ld_off(alive + (start & amask), oj & (uint32_t)amask);
             bool live = false, emit = false;
             double chi = 0.0, gamma = 0.0, aux = 0.0, aux2 = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
             uint64_t quid = 0;
@@ -588,8 +610,11 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                 // the lepton-only Delta F and flag slots re-read the momentum and alive flag on
                 // photon chunks.  With the push every chunk reads E and B, the tile's momentum
                 // is p^{(n-1/2)}, and lepton chunks read F_perp and Delta F in six more slots.
+                // (chunk-relative: each slot's array is addressed from the chunk's first element)
                 const uint64_t n = T.n;
-                const uint64_t jf = j & ((blcfa && !PUSH) ? ~0ull : fmask);  // slots 0..5
+                const uint64_t m05 = (blcfa && !PUSH) ? ~0ull : fmask;  // slots 0..5
+                const uint64_t s05 = start & m05;
+                const uint32_t ob05 = ob & (uint32_t)m05;
                 const bool wave_f = wave && !(blcfa && !PUSH);  // slots 0..5 hold a plane wave
                 const double* q0 = (blcfa && !PUSH) ? T.px_prev : T.ex;
                 const double* q1 = (blcfa && !PUSH) ? T.py_prev : T.ey;
@@ -600,28 +625,32 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                 const double* q6 = blcfa ? T.dfperp : T.px;
                 const double* q7 = blcfa ? T.dfperp + n : T.py;
                 const double* q8 = blcfa ? T.dfperp + 2 * n : T.pz;
-                const uint8_t* q9 = blcfa ? T.just_created + j : alive + (j & amask);
+                const uint8_t* q9 = blcfa ? T.just_created + start : alive + (start & amask);
+                const uint32_t o9 = blcfa ? oj : (oj & (uint32_t)amask);
                 const double* q10 = blcfa ? T.fperp : T.px;
                 const double* q11 = blcfa ? T.fperp + n : T.py;
                 const double* q12 = blcfa ? T.fperp + 2 * n : T.pz;
-                double ux = ld_stream(&T.px[j]), uy = ld_stream(&T.py[j]), uz = ld_stream(&T.pz[j]);
+                double ux = ld_off(T.px + start, ob), uy = ld_off(T.py + start, ob),
+                       uz = ld_off(T.pz + start, ob);
                 double a0, a1, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0;
                 if (wave_f) {
-                    a0 = ld_stream(&WV.amp[j]);
-                    a1 = ld_stream(&WV.phase[j]);
+                    a0 = ld_off(WV.amp + start, ob);
+                    a1 = ld_off(WV.phase + start, ob);
                 } else {
-                    a0 = ld_stream(&q0[jf]); a1 = ld_stream(&q1[jf]); a2 = ld_stream(&q2[jf]);
-                    a3 = ld_stream(&q3[jf]); a4 = ld_stream(&q4[jf]); a5 = ld_stream(&q5[jf]);
+                    a0 = ld_off(q0 + s05, ob05); a1 = ld_off(q1 + s05, ob05);
+                    a2 = ld_off(q2 + s05, ob05); a3 = ld_off(q3 + s05, ob05);
+                    a4 = ld_off(q4 + s05, ob05); a5 = ld_off(q5 + s05, ob05);
                 }
-                const double rx = ld_stream(&q6[j]), ry = ld_stream(&q7[j]), rz = ld_stream(&q8[j]);
+                const double rx = ld_off(q6 + start, ob), ry = ld_off(q7 + start, ob),
+                             rz = ld_off(q8 + start, ob);
                 double o0 = 0.0, o1 = 0.0, o2 = 0.0;
                 if (PUSH) {
-                    o0 = ld_stream(&q10[j]);
-                    o1 = ld_stream(&q11[j]);
-                    o2 = ld_stream(&q12[j]);
+                    o0 = ld_off(q10 + start, ob);
+                    o1 = ld_off(q11 + start, ob);
+                    o2 = ld_off(q12 + start, ob);
                 }
-                const bool fresh = ld_stream(q9) != 0;
-                quid = ld_stream(&T.uid[j]);
+                const bool fresh = ld_off(q9, o9) != 0;
+                quid = ld_off(T.uid + start, ob);
                 __builtin_amdgcn_sched_barrier(0);
                 live = i < end && al != 0;
                 if (wave_f) plane_wave_fields(WV, a0, a1, a0, a1, a2, a3, a4, a5);
@@ -658,21 +687,23 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                     chi = tc * gamma * sqrt(F2);
                     W = rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
                     if (live) {
-                        st_stream(&T.fperp[i], Fx); st_stream(&T.fperp[n + i], Fy);
-                        st_stream(&T.fperp[2 * n + i], Fz);
+                        st_off(T.fperp + start, o * 8u, Fx); st_off(T.fperp + n + start, o * 8u, Fy);
+                        st_off(T.fperp + 2 * n + start, o * 8u, Fz);
                     }
                     if (live && fresh) {
-                        st_stream(&T.dfperp[i], 0.0); st_stream(&T.dfperp[n + i], 0.0);
-                        st_stream(&T.dfperp[2 * n + i], 0.0);
-                        st_stream(&T.just_created[i], (uint8_t)0);
+                        st_off(T.dfperp + start, o * 8u, 0.0);
+                        st_off(T.dfperp + n + start, o * 8u, 0.0);
+                        st_off(T.dfperp + 2 * n + start, o * 8u, 0.0);
+                        st_off(T.just_created + start, o, (uint8_t)0);
                     } else if (live) {
                         const double ax = Fx - ox, ay = Fy - oy, az = Fz - oz;
                         const double d1x = ax * idt, d1y = ay * idt, d1z = az * idt;
                         const double d2x = (ax - rx) * idt2, d2y = (ay - ry) * idt2, d2z = (az - rz) * idt2;
                         const double delta = tc * tc * ((d1x * d1x + d1y * d1y + d1z * d1z) +
                                                         fabs(Fx * d2x + Fy * d2y + Fz * d2z));
-                        st_stream(&T.dfperp[i], ax); st_stream(&T.dfperp[n + i], ay);
-                        st_stream(&T.dfperp[2 * n + i], az);
+                        st_off(T.dfperp + start, o * 8u, ax);
+                        st_off(T.dfperp + n + start, o * 8u, ay);
+                        st_off(T.dfperp + 2 * n + start, o * 8u, az);
                         const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
                         const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
                         emit = W * dt > uniform53(d.a);
@@ -696,23 +727,27 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                     // are written (emitters get theirs again in the emitter pass, after the
                     // recoil or the rejection; dead slots write back their own)
                     if (PUSH && i < end) {
-                        st_stream(&T.px[i], ux); st_stream(&T.py[i], uy); st_stream(&T.pz[i], uz);
+                        st_off(T.px + start, o * 8u, ux); st_off(T.py + start, o * 8u, uy);
+                        st_off(T.pz + start, o * 8u, uz);
                     }
                 }
             } else {
-                qx = ld_stream(&T.px[j]); qy = ld_stream(&T.py[j]); qz = ld_stream(&T.pz[j]);
-                const uint64_t jf = j & fmask;
+                qx = ld_off(T.px + start, ob); qy = ld_off(T.py + start, ob);
+                qz = ld_off(T.pz + start, ob);
+                const uint64_t fs = start & fmask;         // uniform fields: element 0
+                const uint32_t obf = ob & (uint32_t)fmask;
                 double ex, ey, ez = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
                 if (wave) {
-                    ex = ld_stream(&WV.amp[j]);
-                    ey = ld_stream(&WV.phase[j]);
+                    ex = ld_off(WV.amp + start, ob);
+                    ey = ld_off(WV.phase + start, ob);
                 } else {
-                    ex = ld_stream(&T.ex[jf]); ey = ld_stream(&T.ey[jf]); ez = ld_stream(&T.ez[jf]);
-                    bx = ld_stream(&T.bx[jf]); by = ld_stream(&T.by[jf]); bz = ld_stream(&T.bz[jf]);
+                    ex = ld_off(T.ex + fs, obf); ey = ld_off(T.ey + fs, obf);
+                    ez = ld_off(T.ez + fs, obf); bx = ld_off(T.bx + fs, obf);
+                    by = ld_off(T.by + fs, obf); bz = ld_off(T.bz + fs, obf);
                 }
                 double tau0 = 0.0;
-                if (LOCAL) quid = ld_stream(&T.uid[j]);
-                else tau0 = ld_stream(&T.tau[j]);
+                if (LOCAL) quid = ld_off(T.uid + start, ob);
+                else tau0 = ld_off(T.tau + start, ob);
                 // keep the whole load group ahead of the arithmetic: the first use of a loaded
                 // value waits for every outstanding memory operation (loads and stores share
                 // one counter here), so a use scheduled between the loads would split the group
@@ -734,7 +769,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                     // partly written cache line costs the memory a read-modify-write.  Emitters
                     // get a fresh depth in the emitter pass; a converting photon keeps the
                     // decremented one.
-                    if (i < end) st_stream(&T.tau[i], live ? tau : tau0);
+                    if (o < cn) st_off(T.tau + start, o * 8u, live ? tau : tau0);
                 } else {
                     const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
                     emit = live && W * dt > uniform53(d.a);
@@ -742,8 +777,9 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                 // the pushed momentum of every slot (whole cache lines, as for tau): emitters
                 // recoil from the queued, pushed momentum in the emitter pass, which then
                 // overwrites it
-                if (pushed && i < end) {
-                    st_stream(&T.px[i], qx); st_stream(&T.py[i], qy); st_stream(&T.pz[i], qz);
+                if (pushed && o < cn) {
+                    st_off(T.px + start, o * 8u, qx); st_off(T.py + start, o * 8u, qy);
+                    st_off(T.pz + start, o * 8u, qz);
                 }
             }
             if (live) {
