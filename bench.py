@@ -22,9 +22,11 @@ tiles (chi, rates, decisions, sampling, recoil, products).  Then, on the same GP
   * the constant-field run: 2^30 electrons of 10 GeV at chi = 1 in a uniform magnetic field
     (one value per tile) for 1.3 fs, fused push, recoil.
 
-Prints ONE JSON line: value = FP64 particle-updates/s over the timed steps; p50/p99 step
-latency; the roofline of the dominant (streaming) kernel from its own duration measured with HIP
-events on its launch stream; the other forms' numbers; and the CPU oracle timed on a bounded
+Prints ONE JSON line: value = FP64 particle-updates/s over the timed steps (wall clock); p50/p99
+step latency (each step's kernels, from before the streaming kernel to the end of the emitter
+pass, with the library's timing-only HIP events on the step's stream; graph replays of the
+batched form with events around each replay); the roofline of the dominant (streaming) kernel
+from its own duration measured with those events; the other forms' numbers; and the CPU oracle timed on a bounded
 sample on the host cores.  `--copy-calibration` instead times a plain device copy of known size
 (the reference for HBM counter scaling) and exits.
 """
@@ -121,28 +123,29 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False
         h.set_launch(*launch)
         tuned = {"shape": list(launch)}
     h.reserve(2 * n, 2)
-    stream = torch.cuda.current_stream()
     for s in range(warmup):
         h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt, push=push,
                zero_product_counts=True)
     torch.cuda.synchronize()
     cnt.reset()
+    # the library's timing events (before the streaming kernel, between it and the emitter
+    # pass, after that; no system-scope fence) time every step's kernels on the step's stream
     h.profile(True)
     h.profile_read()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
-        ev[s][0].record(stream)
         # the step zeroes the product counts itself: the buffers hold this step's products
         h.step(tiles, seed=0, step=warmup + s + 1, products=prods, counters=cnt, push=push,
                zero_product_counts=True)
-        ev[s][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    bulk_ms, emit_ms, nprof = h.profile_read()
-    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    bulk, emit = h.profile_read_steps(steps)
+    h.profile(False)
+    if len(bulk) != steps:
+        raise RuntimeError("the step timing events did not cover every timed step")
+    step_ms = (bulk + emit).astype(np.float64)   # per step: streaming kernel to emitter pass end
+    bulk_ms, emit_ms, nprof = float(bulk.sum()), float(emit.sum()), len(bulk)
     c = cnt.as_dict()
     if c["overflow"]:
         raise RuntimeError("product buffers overflowed during the benchmark")
@@ -252,21 +255,19 @@ def run_constant_field(dev, n, warmup=2):
     s["p"][1:].zero_()
     h.init_optical_depth(s["uid"], seed=seed, out=tau)
     cnt.reset()
-    h.profile(True)
+    h.profile(True)   # the library's timing events, as in run_form
     h.profile_read()
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(K):
-        ev[k][0].record(stream)
         h.step([tile], seed=seed, step=k, products=pb, counters=cnt, push=True,
                zero_product_counts=True)
-        ev[k][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    bulk_ms, emit_ms, nprof = h.profile_read()
+    bulk, emit = h.profile_read_steps(K)
+    h.profile(False)
+    if len(bulk) != K:
+        raise RuntimeError("the step timing events did not cover every timed step")
     c = cnt.as_dict()
     if c["overflow"]:
         raise RuntimeError("product buffers overflowed during the constant-field run")
@@ -274,8 +275,8 @@ def run_constant_field(dev, n, warmup=2):
     del tile, s, tau, pb
     torch.cuda.empty_cache()
     return dict(wall=wall, K=K, n=n, counters=c, W=W, dt=inputs.DT,
-                step_ms=np.array([a.elapsed_time(b) for a, b in ev]),
-                bulk_ms=bulk_ms / nprof, emit_ms=emit_ms / nprof)
+                step_ms=(bulk + emit).astype(np.float64),
+                bulk_ms=float(bulk.mean()), emit_ms=float(emit.mean()))
 
 
 def cpu_baseline(n_sample=24576):

@@ -306,11 +306,21 @@ sfq_status sfq_reserve(sfq_handle h, uint64_t max_particles, int max_tiles);
 
 /* Kernel timing (instrumentation).  With enable = 1, every sfq_step and sfq_plan_launch on this
  * handle records HIP events on its stream before the streaming kernel, between it and the
- * emitter kernel, and after that (not inside sfq_plan_capture).  sfq_profile_read waits for the
+ * emitter kernel, and after that (not inside sfq_plan_capture); they are timing-only events
+ * (hipEventDisableSystemFence), so recording them does not write back the caches.  sfq_profile_read waits for the
  * recorded events, returns the summed durations in ms of the streaming and emitter kernels and
  * the number of steps timed since the previous read, and clears them.  Any output may be NULL. */
 sfq_status sfq_profile_enable(sfq_handle h, int enable);
 sfq_status sfq_profile_read(sfq_handle h, double* stream_ms, double* emit_ms, uint64_t* steps);
+
+/* The same timings step by step (for latency percentiles): for each step timed since the
+ * previous read, in order, the streaming kernel's and the emitter pass's (scan and emitter
+ * kernels) durations in ms go to stream_ms[k] and emit_ms[k] (host arrays of max_steps floats,
+ * owned by the caller); *steps receives the count, and the timings are cleared.  The events are
+ * timing-only (no system-scope fence on record).  SFQ_E_CAPACITY, and nothing cleared, when
+ * more than max_steps steps are pending; SFQ_E_ARG for NULL arrays when steps are pending. */
+sfq_status sfq_profile_read_steps(sfq_handle h, uint64_t max_steps, float* stream_ms,
+                                  float* emit_ms, uint64_t* steps);
 
 #ifdef __cplusplus
 }

@@ -89,6 +89,8 @@ struct StepArgs {
     int nsets;
     int push;                    // leptons get the Boris push before the step
     int wave;                    // some tile gives its fields as a plane wave
+    int zero_counts;             // the step's product counts start from zero (nsets == 0: the
+                                 // scan kernel takes the bases as 0 instead of reading them)
 };
 
 enum { CNT_PROCESSED, CNT_EMITTED, CNT_CONVERTED, CNT_REJECTED, CNT_OOD, CNT_CLAMPED, CNT_OVERFLOW,
@@ -870,9 +872,11 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
         tl += s_w[0][k]; tp += s_w[1][k]; tn += s_w[2][k];
     }
     const bool multi = A.nsets > 0;
-    const unsigned long long b0 = multi ? 0ull : A.prod_counts[0];
-    const unsigned long long b1 = multi ? 0ull : A.prod_counts[1];
-    const unsigned long long b2 = multi ? 0ull : A.prod_counts[2];
+    // zeroed counts: the bases are 0 (no separate zeroing kernel before the step)
+    const bool from0 = multi || A.zero_counts;
+    const unsigned long long b0 = from0 ? 0ull : A.prod_counts[0];
+    const unsigned long long b1 = from0 ? 0ull : A.prod_counts[1];
+    const unsigned long long b2 = from0 ? 0ull : A.prod_counts[2];
     unsigned long long run_l = il - nl, run_p = ip - np;
     for (int b = lo; b < hi; ++b) {
         A.q_base[3 * b] = b0 + run_l;
@@ -884,7 +888,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
     __syncthreads();  // every read of the product counts happens before they are advanced
     if (tid == 0) {
         if (!multi) {
+            // beyond-LCFA photons take their slots in the emitter kernel, from this count
             if (!A.blcfa) A.prod_counts[0] = b0 + tl;
+            else if (A.zero_counts) A.prod_counts[0] = 0;
             A.prod_counts[1] = b1 + tp;
             A.prod_counts[2] = b2 + tp;
         }
@@ -1068,13 +1074,8 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
     block_add_counters(s_cnt, A.counters, vals);
 }
 
-// plan helpers: zero the product counts (a kernel, not a memset, so graphs replay it safely)
-// and advance the device step counter after a step
-__global__ void zero_counts_kernel(unsigned long long* counts)
-{
-    if (threadIdx.x < 3) counts[threadIdx.x] = 0;
-}
-
+// step helpers: zero the product counts of product sets (a kernel, not a memset, so graphs
+// replay it safely) and advance a plan's device step counter after a step
 __global__ void zero_set_counts_kernel(const sfq_product_set* sets, int nsets)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1239,6 +1240,10 @@ struct sfq_ctx {
     bool queue_used = false;
     Staging staging[N_STAGING];
     int next_staging = 0;
+    // the descriptor bytes last uploaded and the staging slot whose device copy holds them: a
+    // step with the same descriptors (the same tiles, step after step) reuses that copy
+    std::vector<char> last_desc, desc_bytes;
+    int last_slot = -1;
     // launch shape of the step kernel (tunable)
     int blocks_per_cu = 8;
     int chunk = 2048;
@@ -1764,6 +1769,7 @@ static void fill_args(const sfq_ctx* h, const sfq_step_desc* desc, StepArgs& A, 
     A.sets = nullptr;
     A.nsets = desc->nsets;
     A.push = desc->push;
+    A.zero_counts = desc->zero_product_counts;
     A.wave = 0;
     for (int t = 0; t < desc->ntiles; ++t)
         if (desc->tiles[t].field_mode == SFQ_FIELDS_PLANE_WAVE) A.wave = 1;
@@ -1777,7 +1783,10 @@ static ProfEvents* prof_events(sfq_ctx* h)
     if (h->prof_free.empty()) {
         ProfEvents pe{};
         for (auto& e : pe.e)
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            // timing only: no system-scope fence on record (a cache writeback and invalidation
+            // per event would slow the steps being timed)
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+                return nullptr;
         h->prof_free.push_back(pe);
     }
     h->prof_used.push_back(h->prof_free.back());
@@ -1857,14 +1866,13 @@ static void plan_release(sfq_plan_t* p)
     delete p;
 }
 
-// zeroes the product counts of a step (a kernel, not a memset, so graphs replay it safely)
+// Zeroes the product counts of a step with product sets (a kernel, not a memset, so graphs
+// replay it safely).  Steps without sets need none: their scan kernel starts from zero.
 static void enqueue_zero_counts(const StepArgs& A, hipStream_t st)
 {
     if (A.nsets > 0)
         hipLaunchKernelGGL(zero_set_counts_kernel, dim3((3 * A.nsets + 255) / 256), dim3(256), 0, st,
                            A.sets, A.nsets);
-    else
-        hipLaunchKernelGGL(zero_counts_kernel, dim3(1), dim3(64), 0, st, A.prod_counts);
 }
 
 static void plan_enqueue(sfq_plan_t* p, hipStream_t st, const ProfEvents* pe = nullptr)
@@ -1920,6 +1928,29 @@ sfq_status sfq_profile_enable(sfq_handle h, int enable)
     return SFQ_OK;
 }
 
+sfq_status sfq_profile_read_steps(sfq_handle h, uint64_t max_steps, float* stream_ms,
+                                  float* emit_ms, uint64_t* steps)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_profile_read_steps: NULL handle");
+    std::lock_guard<std::mutex> lock(h->mu);
+    if (h->prof_used.size() > max_steps)
+        return fail(h, SFQ_E_CAPACITY, "sfq_profile_read_steps: more timed steps than max_steps");
+    if (h->prof_used.size() > 0 && (!stream_ms || !emit_ms))
+        return fail(h, SFQ_E_ARG, "sfq_profile_read_steps: NULL output arrays");
+    HIP_TRY(h, hipSetDevice(h->device));
+    uint64_t k = 0;
+    for (auto& pe : h->prof_used) {
+        HIP_TRY(h, hipEventSynchronize(pe.e[2]));
+        HIP_TRY(h, hipEventElapsedTime(&stream_ms[k], pe.e[0], pe.e[1]));
+        HIP_TRY(h, hipEventElapsedTime(&emit_ms[k], pe.e[1], pe.e[2]));
+        ++k;
+    }
+    h->prof_free.insert(h->prof_free.end(), h->prof_used.begin(), h->prof_used.end());
+    h->prof_used.clear();
+    if (steps) *steps = k;
+    return SFQ_OK;
+}
+
 sfq_status sfq_profile_read(sfq_handle h, double* stream_ms, double* emit_ms, uint64_t* steps)
 {
     if (!h) return fail(h, SFQ_E_STATE, "sfq_profile_read: NULL handle");
@@ -1960,32 +1991,47 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
         const sfq_status q = ensure_queue(h, qs, "sfq_step");
         if (q != SFQ_OK) return q;
     }
-    // descriptors through a ring of pinned staging buffers
-    Staging& S = h->staging[h->next_staging];
-    h->next_staging = (h->next_staging + 1) % N_STAGING;
-    const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
-    const size_t set_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
-    const size_t used = set_pos + (size_t)desc->nsets * sizeof(sfq_product_set);
-    if (used > STAGING_BYTES) return fail(h, SFQ_E_CAPACITY, "sfq_step: too many tiles");
-    if (!S.host) {
-        HIP_TRY(h, hipHostMalloc(&S.host, STAGING_BYTES, hipHostMallocDefault));
-        HIP_TRY(h, hipMalloc(&S.dev, STAGING_BYTES));
-        HIP_TRY(h, hipEventCreateWithFlags(&S.done, hipEventDisableTiming));
-        S.bytes = STAGING_BYTES;
-    } else {
-        HIP_TRY(h, hipEventSynchronize(S.done));
-    }
-    char* hb = (char*)S.host;
-    memcpy(hb, desc->tiles, nt * sizeof(sfq_tile));
-    memcpy(hb + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
-    if (desc->nsets > 0)
-        memcpy(hb + set_pos, desc->product_sets, desc->nsets * sizeof(sfq_product_set));
-    HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, used, hipMemcpyHostToDevice, (hipStream_t)stream));
     // steps on different streams share the emitter queue: order them on the device (outside
     // stream capture, where the caller's graph orders its own nodes)
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     HIP_TRY(h, hipStreamIsCapturing((hipStream_t)stream, &cap));
     const bool order = cap == hipStreamCaptureStatusNone;
+    // descriptors through a ring of pinned staging buffers and their device copies
+    const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
+    const size_t set_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
+    const size_t used = set_pos + (size_t)desc->nsets * sizeof(sfq_product_set);
+    if (used > STAGING_BYTES) return fail(h, SFQ_E_CAPACITY, "sfq_step: too many tiles");
+    std::vector<char>& db = h->desc_bytes;
+    db.assign(used, 0);
+    memcpy(db.data(), desc->tiles, nt * sizeof(sfq_tile));
+    memcpy(db.data() + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
+    if (desc->nsets > 0)
+        memcpy(db.data() + set_pos, desc->product_sets, desc->nsets * sizeof(sfq_product_set));
+    // The same descriptors as the last upload (outside capture, where steps are ordered on the
+    // device, see below): the kernels read that device copy again, with no copy from the host
+    // (a copy costs a transfer and its dispatch latency on every step).  Device copies are
+    // read-only; a slot is overwritten only after the last step that used it (its event).
+    const bool reuse = order && h->last_slot >= 0 && h->last_desc == db;
+    Staging& S = h->staging[reuse ? h->last_slot : h->next_staging];
+    if (!reuse) {
+        const int slot = h->next_staging;
+        h->next_staging = (h->next_staging + 1) % N_STAGING;
+        if (!S.host) {
+            HIP_TRY(h, hipHostMalloc(&S.host, STAGING_BYTES, hipHostMallocDefault));
+            HIP_TRY(h, hipMalloc(&S.dev, STAGING_BYTES));
+            HIP_TRY(h, hipEventCreateWithFlags(&S.done, hipEventDisableTiming));
+            S.bytes = STAGING_BYTES;
+        } else {
+            HIP_TRY(h, hipEventSynchronize(S.done));
+        }
+        memcpy(S.host, db.data(), used);
+        HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, used, hipMemcpyHostToDevice,
+                                  (hipStream_t)stream));
+        // under capture the graph copies from the host buffer when it runs, so that buffer
+        // (which the ring reuses) is not a cache for later steps
+        h->last_slot = order ? slot : -1;
+        if (order) h->last_desc.swap(db);
+    }
     if (order) {
         if (!h->queue_free)
             HIP_TRY(h, hipEventCreateWithFlags(&h->queue_free, hipEventDisableTiming));
@@ -2059,6 +2105,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     p->grid = qs.grid;
     p->d_step = (unsigned long long*)((char*)p->d_mem + step_pos);
     fill_args(h, desc, p->A, nchunks, chunk);
+    p->A.zero_counts = p->zero_counts;
     p->A.tiles = (const sfq_tile*)p->d_mem;
     p->A.chunk_off = (const uint32_t*)((char*)p->d_mem + off_pos);
     p->A.step_ptr = p->d_step;

@@ -12,6 +12,7 @@ import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,7 +33,7 @@ EXPORTS = ("sfq_create", "sfq_destroy", "sfq_last_error", "sfq_units", "sfq_chi"
            "sfq_sample_photon", "sfq_sample_pair", "sfq_philox", "sfq_init_optical_depth",
            "sfq_step", "sfq_set_launch", "sfq_get_launch", "sfq_plan_create", "sfq_plan_destroy",
            "sfq_plan_launch", "sfq_plan_set_step", "sfq_plan_capture", "sfq_plan_replay",
-           "sfq_reserve", "sfq_profile_enable", "sfq_profile_read")
+           "sfq_reserve", "sfq_profile_enable", "sfq_profile_read", "sfq_profile_read_steps")
 
 
 class Config(C.Structure):
@@ -138,6 +139,9 @@ def load(path: str = LIB_PATH):
     L.sfq_profile_read.restype = st
     L.sfq_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                    C.POINTER(C.c_uint64)]
+    L.sfq_profile_read_steps.restype = st
+    L.sfq_profile_read_steps.argtypes = [vp, C.c_uint64, C.POINTER(C.c_float),
+                                         C.POINTER(C.c_float), C.POINTER(C.c_uint64)]
     _lib = L
     return L
 
@@ -225,6 +229,17 @@ class Handle:
         a, b, n = C.c_double(), C.c_double(), C.c_uint64()
         self._check(self._L.sfq_profile_read(self._h, C.byref(a), C.byref(b), C.byref(n)))
         return a.value, b.value, n.value
+
+    def profile_read_steps(self, max_steps: int = 100000):
+        """Per-step (stream-kernel ms, emitter-pass ms) arrays of the steps timed since the
+        previous read (numpy float32, in launch order)."""
+        a = np.zeros(max_steps, dtype=np.float32)
+        b = np.zeros(max_steps, dtype=np.float32)
+        n = C.c_uint64()
+        fp = C.POINTER(C.c_float)
+        self._check(self._L.sfq_profile_read_steps(self._h, max_steps, a.ctypes.data_as(fp),
+                                                   b.ctypes.data_as(fp), C.byref(n)))
+        return a[:n.value].copy(), b[:n.value].copy()
 
     # ---- batched calls ------------------------------------------------------------------------
     def chi(self, species, p, E, B, stream=None):

@@ -1,7 +1,8 @@
 """Nothing outside a tile is written: tiles are views into larger buffers, with sentinel values
 before, between and after them, and every step form (optical-depth and local decisions, FP64 and
 MIXED, with and without the fused push, array and plane-wave fields, beyond-LCFA) must leave the
-sentinels bit for bit.  The streaming kernels write every slot of a chunk (whole cache lines),
+sentinels bit for bit; and a step that zeroes its product counts leaves exactly its own products
+in the buffers.  The streaming kernels write every slot of a chunk (whole cache lines),
 so the chunk tails of ragged tiles are where a missing bound would show.  Paper: Montefiori &
 Tamburini, arXiv:2301.07684 (the step of Sec. 2-4 and Sec. 5 acts on the given particles only).
 """
@@ -135,4 +136,11 @@ def test_steps_write_nothing_outside_the_tiles(dev, form):
     after = snapshot(bufs, masks)
     for name in before:
         assert np.array_equal(before[name].view(np.uint8), after[name].view(np.uint8)), name
+    # zero_product_counts: the buffers hold exactly the last step's products
+    last = sfq.Counters(dev)
+    h.step(tiles, seed=3, step=4, products=prods, counters=last, push=push,
+           zero_product_counts=True)
+    torch.cuda.synchronize()
+    c = last.as_dict()
+    assert prods.host_counts() == [c["emitted"], c["converted"], c["converted"]]
     h.close()

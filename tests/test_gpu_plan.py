@@ -154,8 +154,17 @@ def test_reserve_and_kernel_timing(dev):
     bulk_ms, emit_ms, n = h.profile_read()
     assert n == 6 and bulk_ms > 0 and emit_ms > 0
     assert h.profile_read() == (0.0, 0.0, 0)  # cleared by the read
+    # step by step: one entry per timed step, in order, summing to the totals
+    for s in range(3, 6):
+        h.step(a, seed=5, step=s, products=pa, counters=ca)
+        plan.launch()
+    with pytest.raises(sfq.SFQError):
+        h.profile_read_steps(5)          # more steps pending than room: nothing cleared
+    bulk, emit = h.profile_read_steps(6)
+    assert len(bulk) == len(emit) == 6 and np.all(bulk > 0) and np.all(emit > 0)
+    assert h.profile_read() == (0.0, 0.0, 0)
     h.profile(False)
-    h.step(a, seed=5, step=3, products=pa, counters=ca)
+    h.step(a, seed=5, step=6, products=pa, counters=ca)
     torch.cuda.synchronize()
     assert h.profile_read()[2] == 0
     plan.launch()
