@@ -387,13 +387,15 @@ def main():
     served = None if args.no_served else run_served(dev)
     if served is not None:
         print(f"# served form done: {served['wall']:.2f} s", file=sys.stderr, flush=True)
+    # each form takes the launch shape the autotuner finds for it (or --launch): the
+    # plane-wave-fields form, with more arithmetic per byte, runs best with more waves
     fused = None if args.no_push else run_form(0, "plane_wave", args.n, args.steps, args.warmup,
-                                               dev, tuple(f64["shape"]), push=True)
+                                               dev, launch, push=True)
     if fused is not None:
         print(f"# fused push form done: {fused['wall'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
     wave = None if args.no_wave else run_form(0, "plane_wave", args.n, args.steps, args.warmup,
-                                              dev, tuple(f64["shape"]), wave=True)
+                                              dev, launch, wave=True)
     if wave is not None:
         print(f"# plane-wave fields form done: {wave['wall'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
@@ -524,6 +526,7 @@ def main():
                              "emitter_pass_ms": fused["emit_ms"],
                              "bulk_algorithmic_bytes": fb,
                              "bulk_roofline_frac": fb / (fused["bulk_ms"] * 1e-3) / HBM_PEAK,
+                             "launch_shape": fused["shape"],
                              "emitted_per_step": pf("emitted"),
                              "converted_per_step": pf("converted")}
     if wave is not None:
@@ -541,6 +544,7 @@ def main():
             "bulk_kernel_ms": wave["bulk_ms"], "emitter_pass_ms": wave["emit_ms"],
             "bulk_algorithmic_bytes": wb,
             "bulk_roofline_frac": wb / (wave["bulk_ms"] * 1e-3) / HBM_PEAK,
+            "launch_shape": wave["shape"],
             "emitted_per_step": pw("emitted"), "converted_per_step": pw("converted")}
     if const is not None:
         cc = const["counters"]
