@@ -326,3 +326,34 @@ def test_maximum_tile_count_and_overflow_rerun(dev):
     assert cf.as_dict()["overflow"] == 0 and fit.host_counts() == need
     assert same(state(a), state(c)) and same(state(b), state(c))
     assert same(product_set(fit), product_set(large))
+
+
+def test_descriptor_reuse_follows_the_tiles(dev):
+    """The handle reuses the device copy of the last uploaded tile descriptors when a step
+    passes the same ones.  Alternating tile sets (A, A, B, A), new contents in the same arrays,
+    and a new launch shape must all give what a fresh handle per step gives."""
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    a = make_tiles(dev, h, sizes=(6000, 2000))
+    b = make_tiles(dev, h, sizes=(3000, 500, 4000))
+    ra, rb = clone_tiles(a), clone_tiles(b)
+    pb_, qb_ = sfq.ProductBuffers.empty(20000, 20000, dev), sfq.ProductBuffers.empty(20000, 20000, dev)
+    seq = [("a", 0), ("a", 1), ("b", 0), ("a", 2), ("a", 3)]
+    for which, step in seq:
+        t, r = (a, ra) if which == "a" else (b, rb)
+        if step == 3:
+            # new contents in the same arrays: same descriptors, different particles
+            for x, y in zip(t, r):
+                x.px.mul_(1.5)
+                y.px.mul_(1.5)
+            h.set_launch(4, 1024)      # and a new launch shape (new chunk offsets)
+        h.step(t, seed=8, step=step, products=pb_, counters=sfq.Counters(dev),
+               zero_product_counts=True)
+        fresh = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+        fresh.step(r, seed=8, step=step, products=qb_, counters=sfq.Counters(dev),
+                   zero_product_counts=True)
+        torch.cuda.synchronize()
+        assert same(state(t), state(r)), (which, step)
+        assert pb_.host_counts() == qb_.host_counts()
+        assert same(product_set(pb_), product_set(qb_)), (which, step)
+        fresh.close()
+    h.close()
