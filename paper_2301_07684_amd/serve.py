@@ -29,7 +29,7 @@ import collections
 import math
 import time
 from dataclasses import dataclass, field
-from typing import Callable, Deque, Dict, List, Optional, Sequence
+from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
 
 from . import inputs, sfq
 
@@ -38,6 +38,10 @@ from . import inputs, sfq
 LEPTON_BYTES = 8 * 3 * 3 + 8 + 1 + 8 + 8  # p, F_perp, dF; uid; just_created; wave a, phi
 PHOTON_BYTES = 8 * 3 + 8 + 1 + 8 + 8       # p; uid; alive; wave a, phi
 PRODUCT_BYTES = 6 * 8                      # p, tau, uid, parent
+# launch shape of the lanes' steps (blocks per compute unit, particles per chunk): the best of
+# 8 x 2048, 3 x 4096, 4 x 2048 and 3 x 2048 on the served workload (batches of about 24M
+# particles in beyond-LCFA kernels of 3 waves per SIMD), by a few percent
+LANE_LAUNCH = (4, 2048)
 
 
 @dataclass
@@ -218,7 +222,8 @@ class Server:
     def __init__(self, dev=None, *, hbm_budget: int = 3 << 30, lanes: int = 2,
                  precision: int = sfq.MIXED, seed: int = 0, max_batch_particles: int = 1 << 25,
                  max_batch_tiles: int = 256, clients: int = 8,
-                 on_step: Optional[Callable[[Simulation], None]] = None):
+                 on_step: Optional[Callable[[Simulation], None]] = None,
+                 launch: Tuple[int, int] = LANE_LAUNCH):
         import torch
 
         self.dev = dev or torch.device("cuda", 0)
@@ -229,6 +234,7 @@ class Server:
         for _ in range(lanes):
             h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=self.dt, precision=precision,
                            decision=sfq.LOCAL, blcfa=True, device=self.dev.index or 0)
+            h.set_launch(*launch)
             h.reserve(max_batch_particles, max_batch_tiles)
             self.lanes.append(Lane(h, torch.cuda.Stream(device=self.dev), sfq.Counters(self.dev)))
         self.client_streams = [torch.cuda.Stream(device=self.dev) for _ in range(clients)]
