@@ -75,23 +75,25 @@ def tune(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], products: sfq.Prod
     snap = _snapshot(tiles)
     counts0 = products.counts.clone()
     cnt0 = counters.t.clone()
-    stream = torch.cuda.current_stream()
     timings = {}
+    was_profiling = getattr(handle, "profiling", False)
+    if was_profiling:
+        handle.profile_read_steps()      # the caller's pending timings are not the candidates'
+    handle.profile(True)                 # each launch timed by the library's timing-only events
     for bpc, chunk in candidates:
         handle.set_launch(bpc, chunk)
         plan = handle.plan(tiles, seed=seed, step=step, products=products, counters=counters)
         plan.launch()
         torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(repeats + 1)]
-        ev[0].record(stream)
+        handle.profile_read_steps()
         for k in range(repeats):
             plan.launch()
-            ev[k + 1].record(stream)
-        torch.cuda.synchronize()
-        ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(repeats))
+        a, b = handle.profile_read_steps()
+        ms = sorted((a + b).tolist())    # per launch: streaming kernel to emitter pass end
         timings[f"{bpc}x{chunk}"] = ms[len(ms) // 2]
         plan.close()
         _restore(tiles, snap)
+    handle.profile(was_profiling)
     best = min(timings, key=timings.get)
     bpc, chunk = (int(v) for v in best.split("x"))
     handle.set_launch(bpc, chunk)

@@ -186,6 +186,7 @@ class Handle:
         h = C.c_void_p()
         self._check(self._L.sfq_create(C.byref(cfg), C.byref(h)))
         self._h = h
+        self.profiling = False
         self.precision, self.decision, self.blcfa, self.bw_fast = precision, decision, blcfa, bw_fast
         self.device = torch.device("cuda", device)
         lc, lr = C.c_double(), C.c_double()
@@ -223,6 +224,7 @@ class Handle:
     def profile(self, enable: bool = True):
         """Start/stop timing the two step kernels of every step with HIP events."""
         self._check(self._L.sfq_profile_enable(self._h, int(enable)))
+        self.profiling = bool(enable)
 
     def profile_read(self):
         """(stream-kernel ms, emitter-kernel ms, steps) summed since the previous read."""
