@@ -10,8 +10,9 @@
 //                LDS-staged coefficient tables and the decision (or the beyond-LCFA force
 //                update); emitters are compacted with a wave ballot + popcount prefix into the
 //                block's own slice of a queue (one LDS atomic per wave, no global atomics).  It
-//                carries none of the sampling code, so its register footprint allows high
-//                occupancy.
+//                writes every slot of a chunk it updates (whole cache lines), addresses each
+//                chunk from its first element (scalar bases, one 32-bit lane offset), and
+//                carries none of the sampling code, so its register footprint stays small.
 //   scan_kernel  one block: prefix sums of the queued emitters over blocks give every block its
 //                product slots; the step's counters are written once.
 //   emit_kernel  each queue slice is sampled by a few blocks with all lanes busy: Philox draws,
