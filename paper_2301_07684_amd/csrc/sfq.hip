@@ -290,8 +290,10 @@ __device__ __forceinline__ unsigned long long keyed_reserve(const sfq_product_se
 // =============================================================================================
 constexpr int STEP_BLOCK = 256;
 // minimum waves per SIMD requested from the register allocator for the two step kernels.  The
-// streaming kernel's register budget decides how many waves hide HBM latency: the FP64 LCFA
-// form fits 93 registers (5 waves) and the mixed form 67 (6 waves).  The beyond-LCFA forms
+// streaming kernel's register budget decides how many waves can hide HBM latency: the LCFA
+// array forms, with their two-particles-per-lane loop, fit 4 waves (FP64) and 5 (mixed); the
+// launch shapes that run best use 2 per SIMD (2 blocks of 4 waves per compute unit), with two
+// independent particles per lane.  The beyond-LCFA forms
 // (which leave the emission threshold's transcendentals to the emitter pass) fit 5 waves
 // (mixed), 4 (mixed with the push, FP64) or 3 (FP64 with the push).  The kernels that take
 // plane-wave tiles (fields computed in the kernel, two particles per lane in the LCFA loop)
@@ -302,7 +304,7 @@ constexpr int bulk_waves(bool, bool, bool, bool) { return SFQ_BULK_WAVES; }
 constexpr int bulk_waves(bool mixed, bool blcfa, bool push, bool wave)
 {
     if (blcfa) return wave ? 3 : (mixed ? (push ? 4 : 5) : (push ? 3 : 4));
-    return wave ? 4 : (mixed ? 6 : 5);
+    return wave ? 4 : (mixed ? 5 : 4);
 }
 #endif
 #ifndef SFQ_EMIT_WAVES
@@ -538,6 +540,98 @@ __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_til
     }
 }
 
+typedef double dv2 __attribute__((ext_vector_type(2)));
+// LCFA chunks of array tiles (optical-depth decisions, no push), two adjacent particles per
+// lane per iteration: every array is read and the optical depths written with 16-byte accesses
+// (the caller checks the alignment), and each lane carries two independent chains of
+// arithmetic, which hides more of their latency at the same number of waves and memory
+// streams.  Whole iterations of 2 x STEP_BLOCK particles only; returns how many particles of the
+// chunk it took (the one-particle loop does the rest).  The arithmetic is bulk_kernel's.
+template <bool MIXED, typename RT>
+__device__ __forceinline__ uint32_t lcfa_array_vec2(const StepArgs& A, const sfq_tile& T, int t,
+                                                    uint64_t start, uint64_t end,
+                                                    const uint8_t* alive, uint64_t amask,
+                                                    bool photon, uint64_t qbase,
+                                                    const RT* s_rad, const RT* s_pair,
+                                                    unsigned* s_qn, unsigned long long& c_proc,
+                                                    unsigned long long& c_ood)
+{
+    const int tid = threadIdx.x;
+    const double dt = A.ph.dt;
+    const uint32_t cn = (uint32_t)(end - start);
+    const uint32_t full = cn - cn % (2u * STEP_BLOCK);
+    for (uint32_t ob0 = 0; ob0 < full; ob0 += 2u * STEP_BLOCK) {
+        const uint32_t o = ob0 + 2u * (uint32_t)tid;   // even: particles o, o + 1
+        const uint32_t ob = o * 8u;
+        uint16_t al2 = 0x0101;
+        if (amask) al2 = ld_off((const uint16_t*)(alive + start), o);
+        const dv2 px = ld_off((const dv2*)(T.px + start), ob);
+        const dv2 py = ld_off((const dv2*)(T.py + start), ob);
+        const dv2 pz = ld_off((const dv2*)(T.pz + start), ob);
+        const dv2 ex = ld_off((const dv2*)(T.ex + start), ob);
+        const dv2 ey = ld_off((const dv2*)(T.ey + start), ob);
+        const dv2 ez = ld_off((const dv2*)(T.ez + start), ob);
+        const dv2 bx = ld_off((const dv2*)(T.bx + start), ob);
+        const dv2 by = ld_off((const dv2*)(T.by + start), ob);
+        const dv2 bz = ld_off((const dv2*)(T.bz + start), ob);
+        const dv2 t0 = ld_off((const dv2*)(T.tau + start), ob);
+        __builtin_amdgcn_sched_barrier(0);
+        dv2 tout;
+        bool em[2];
+        double chiv[2], gamv[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const bool live = ((al2 >> (8 * u)) & 0xff) != 0;
+            double gamma, chi;
+            bool ood = false;
+            gamma_chi(photon, px[u], py[u], pz[u], ex[u], ey[u], ez[u], bx[u], by[u], bz[u],
+                      A.ph.lc_over_lr, gamma, chi);
+            const double W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
+                                    : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+            const double tau = t0[u] - W * dt;
+            em[u] = live && tau < 0.0;
+            tout[u] = live ? tau : t0[u];
+            chiv[u] = chi; gamv[u] = gamma;
+            if (live) {
+                ++c_proc;
+                const uint64_t i = start + o + u;
+                if (T.chi_out) T.chi_out[i] = chi;
+                if (T.rate_out) T.rate_out[i] = W;
+                c_ood += ood ? 1 : 0;
+            }
+        }
+        st_off((dv2*)(T.tau + start), ob, tout);
+        // compaction of both particles in index order (lane l holds particles 2l, 2l + 1), with
+        // one LDS atomic per wave
+        const unsigned long long m0 = __ballot(em[0]), m1 = __ballot(em[1]);
+        if (m0 | m1) {
+            const int lane = lane_id();
+            const unsigned long long below = (1ull << lane) - 1ull;
+            const unsigned total = (unsigned)(__popcll(m0) + __popcll(m1));
+            const int leader = __ffsll((long long)(m0 | m1)) - 1;
+            unsigned off = 0;
+            if (lane == leader) off = atomicAdd(&s_qn[photon ? 1 : 0], total);
+            off = __shfl(off, leader);
+            const unsigned r0 = off + (unsigned)(__popcll(m0 & below) + __popcll(m1 & below));
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (em[u]) {
+                    const unsigned rank = r0 + (u == 1 && em[0] ? 1u : 0u);
+                    const uint64_t slot = photon ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
+                    A.q_idx[slot] = (uint32_t)(start + o + u);
+                    A.q_tile[slot] = (uint32_t)t;
+                    A.q_chi[slot] = chiv[u];
+                    A.q_gamma[slot] = gamv[u];
+                    A.q_px[slot] = px[u];
+                    A.q_py[slot] = py[u];
+                    A.q_pz[slot] = pz[u];
+                }
+            }
+        }
+    }
+    return full;
+}
+
 template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE>
 __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) void bulk_kernel(StepArgs A)
 {
@@ -596,7 +690,22 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
             }
         }
         const uint32_t cn = (uint32_t)(end - start);  // chunk-relative offsets below
-        for (uint64_t base = start; base < end; base += STEP_BLOCK) {
+        uint64_t first = start;
+        if constexpr (!BLCFA && !LOCAL && !PUSH && !WAVE) {
+            // array tiles whose arrays allow 16-byte accesses at the chunk (and 2-byte ones for
+            // the alive flags): two adjacent particles per lane (not in the kernels that also
+            // take plane-wave tiles, whose register budget the plane-wave loop needs)
+            const uintptr_t a16 = (uintptr_t)(T.px + start) | (uintptr_t)(T.py + start) |
+                                  (uintptr_t)(T.pz + start) | (uintptr_t)(T.ex + start) |
+                                  (uintptr_t)(T.ey + start) | (uintptr_t)(T.ez + start) |
+                                  (uintptr_t)(T.bx + start) | (uintptr_t)(T.by + start) |
+                                  (uintptr_t)(T.bz + start) | (uintptr_t)(T.tau + start);
+            const uintptr_t a2 = amask ? (uintptr_t)(alive + start) : 0;
+            if (fmask == ~0ull && (a16 & 15) == 0 && (a2 & 1) == 0)
+                first += lcfa_array_vec2<MIXED>(A, T, t, start, end, alive, amask, photon, qbase,
+                                                s_rad, s_pair, s_qn, c_proc, c_ood);
+        }
+        for (uint64_t base = first; base < end; base += STEP_BLOCK) {
             const uint64_t i = base + tid;
             const uint64_t j = min(i, end - 1);
             const uint32_t o = (uint32_t)(base - start) + (uint32_t)tid;  // i - start
