@@ -541,13 +541,14 @@ __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_til
 }
 
 typedef double dv2 __attribute__((ext_vector_type(2)));
-// LCFA chunks of array tiles (optical-depth decisions, no push), two adjacent particles per
-// lane per iteration: every array is read and the optical depths written with 16-byte accesses
+// LCFA chunks of array tiles (optical-depth decisions), two adjacent particles per lane per
+// iteration: every array is read and the optical depths (and, with the fused push, the pushed
+// momenta) written with 16-byte accesses
 // (the caller checks the alignment), and each lane carries two independent chains of
 // arithmetic, which hides more of their latency at the same number of waves and memory
 // streams.  Whole iterations of 2 x STEP_BLOCK particles only; returns how many particles of the
 // chunk it took (the one-particle loop does the rest).  The arithmetic is bulk_kernel's.
-template <bool MIXED, typename RT>
+template <bool MIXED, bool PUSH, typename RT>
 __device__ __forceinline__ uint32_t lcfa_array_vec2(const StepArgs& A, const sfq_tile& T, int t,
                                                     uint64_t start, uint64_t end,
                                                     const uint8_t* alive, uint64_t amask,
@@ -576,15 +577,22 @@ __device__ __forceinline__ uint32_t lcfa_array_vec2(const StepArgs& A, const sfq
         const dv2 bz = ld_off((const dv2*)(T.bz + start), ob);
         const dv2 t0 = ld_off((const dv2*)(T.tau + start), ob);
         __builtin_amdgcn_sched_barrier(0);
-        dv2 tout;
+        dv2 tout, qxo, qyo, qzo;
         bool em[2];
         double chiv[2], gamv[2];
+        const bool pushed = PUSH && !photon;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const bool live = ((al2 >> (8 * u)) & 0xff) != 0;
+            double qx = px[u], qy = py[u], qz = pz[u];
+            if (pushed && live) {  // dead slots keep (and write back) their momentum
+                const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
+                boris_push(hq, ex[u], ey[u], ez[u], bx[u], by[u], bz[u], qx, qy, qz);
+            }
+            qxo[u] = qx; qyo[u] = qy; qzo[u] = qz;
             double gamma, chi;
             bool ood = false;
-            gamma_chi(photon, px[u], py[u], pz[u], ex[u], ey[u], ez[u], bx[u], by[u], bz[u],
+            gamma_chi(photon, qx, qy, qz, ex[u], ey[u], ez[u], bx[u], by[u], bz[u],
                       A.ph.lc_over_lr, gamma, chi);
             const double W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
                                     : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
@@ -599,6 +607,11 @@ __device__ __forceinline__ uint32_t lcfa_array_vec2(const StepArgs& A, const sfq
                 if (T.rate_out) T.rate_out[i] = W;
                 c_ood += ood ? 1 : 0;
             }
+        }
+        if (pushed) {
+            st_off((dv2*)(T.px + start), ob, qxo);
+            st_off((dv2*)(T.py + start), ob, qyo);
+            st_off((dv2*)(T.pz + start), ob, qzo);
         }
         st_off((dv2*)(T.tau + start), ob, tout);
         // compaction of both particles in index order (lane l holds particles 2l, 2l + 1), with
@@ -622,9 +635,9 @@ __device__ __forceinline__ uint32_t lcfa_array_vec2(const StepArgs& A, const sfq
                     A.q_tile[slot] = (uint32_t)t;
                     A.q_chi[slot] = chiv[u];
                     A.q_gamma[slot] = gamv[u];
-                    A.q_px[slot] = px[u];
-                    A.q_py[slot] = py[u];
-                    A.q_pz[slot] = pz[u];
+                    A.q_px[slot] = qxo[u];
+                    A.q_py[slot] = qyo[u];
+                    A.q_pz[slot] = qzo[u];
                 }
             }
         }
@@ -691,7 +704,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
         }
         const uint32_t cn = (uint32_t)(end - start);  // chunk-relative offsets below
         uint64_t first = start;
-        if constexpr (!BLCFA && !LOCAL && !PUSH && !WAVE) {
+        if constexpr (!BLCFA && !LOCAL && !WAVE) {
             // array tiles whose arrays allow 16-byte accesses at the chunk (and 2-byte ones for
             // the alive flags): two adjacent particles per lane (not in the kernels that also
             // take plane-wave tiles, whose register budget the plane-wave loop needs)
@@ -702,7 +715,7 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
                                   (uintptr_t)(T.bz + start) | (uintptr_t)(T.tau + start);
             const uintptr_t a2 = amask ? (uintptr_t)(alive + start) : 0;
             if (fmask == ~0ull && (a16 & 15) == 0 && (a2 & 1) == 0)
-                first += lcfa_array_vec2<MIXED>(A, T, t, start, end, alive, amask, photon, qbase,
+                first += lcfa_array_vec2<MIXED, PUSH>(A, T, t, start, end, alive, amask, photon, qbase,
                                                 s_rad, s_pair, s_qn, c_proc, c_ood);
         }
         for (uint64_t base = first; base < end; base += STEP_BLOCK) {
