@@ -388,6 +388,67 @@ def test_step_tiling_invariance_and_ragged_tiles(h64, dev):
     assert c1 == c2
 
 
+@pytest.mark.parametrize("form", ["fp64", "mixed", "fp64_push"])
+@pytest.mark.parametrize("shifted", ["all", "tau", "alive"])
+def test_step_same_on_unaligned_views(dev, form, shifted):
+    """Array tiles whose arrays all start on 16-byte boundaries (and whose alive flags start on
+    an even byte) are streamed two adjacent particles per lane with 16-byte accesses; a tile
+    with any array one element off such a boundary takes the one-particle-per-lane loop.  Both
+    give the same bits for the same particles: momenta, depths, flags, diagnostics, products
+    and counters."""
+    h = handle(precision=sfq.MIXED if form == "mixed" else sfq.FP64)
+    h.set_launch(2, 1024)   # 1024-particle chunks: two full 2 x 256 iterations each, ragged tail
+    push = form.endswith("push")
+    n = 5000
+
+    def run(shift_names):
+        tiles = []
+        for species in (sfq.ELECTRON, sfq.PHOTON):
+            w = inputs.plane_wave(1 << 24, idx=np.arange(n) * 1024, species=species, seed=21)
+            tau0 = h.init_optical_depth(T(w["uid"], dev), seed=4).cpu().numpy() * 1e-3
+            alive = (np.arange(n) % 7 != 5).astype(np.uint8)
+
+            def put(name, a):
+                t = torch.from_numpy(np.ascontiguousarray(a))
+                s = 1 if (shift_names == "all" or shift_names == name) else 0
+                buf = torch.zeros(n + 2, dtype=t.dtype, device=dev)
+                buf[s:s + n] = t.to(dev)
+                return buf[s:s + n]
+
+            p = [put("p", w["p"][i]) for i in range(3)]
+            E = [put("E", w["E"][i]) for i in range(3)]
+            B = [put("B", w["B"][i]) for i in range(3)]
+            tiles.append(sfq.TileArrays(
+                species, *p, *E, *B, tau=put("tau", tau0), uid=put("uid", w["uid"]),
+                alive=put("alive", alive),
+                chi_out=torch.zeros(n, dtype=torch.float64, device=dev),
+                rate_out=torch.zeros(n, dtype=torch.float64, device=dev)))
+        prods = sfq.ProductBuffers.empty(2 * n, n, dev)
+        cnt = sfq.Counters(dev)
+        h.step(tiles, seed=6, step=2, products=prods, counters=cnt, push=push)
+        torch.cuda.synchronize()
+        out = [torch.stack([t.px, t.py, t.pz, t.tau, t.chi_out, t.rate_out]).cpu().numpy()
+               for t in tiles]
+        flags = [t.alive.cpu().numpy() for t in tiles]
+        ptrs = [t.tau.data_ptr() % 16 for t in tiles]
+        maps = {k: products_by_parent(prods, k) for k in ("photons", "electrons", "positrons")}
+        return out, flags, maps, cnt.as_dict(), ptrs
+
+    o1, f1, m1, c1, a1 = run(None)
+    o2, f2, m2, c2, a2 = run(shifted)
+    assert a1 == [0, 0] and a2 == ([8, 8] if shifted in ("all", "tau") else [0, 0])
+    assert c1["emitted"] > 0 and c1["converted"] > 0 and c1 == c2
+    for x, y in zip(o1, o2):
+        assert np.array_equal(x.view(np.uint64), y.view(np.uint64))
+    for x, y in zip(f1, f2):
+        assert np.array_equal(x, y)
+    for k in m1:
+        assert m1[k].keys() == m2[k].keys()
+        for parent in m1[k]:
+            assert np.array_equal(m1[k][parent][0], m2[k][parent][0])
+            assert m1[k][parent][1:] == m2[k][parent][1:]
+
+
 def test_step_edge_cases(h64, dev):
     n = 3000
     w = inputs.plain_compton(n, seed=91)
