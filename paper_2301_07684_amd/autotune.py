@@ -19,7 +19,8 @@ import torch
 
 from . import sfq
 
-DEFAULT_CANDIDATES = [(2, 4096), (4, 2048), (4, 4096), (8, 1024), (8, 2048), (16, 1024)]
+DEFAULT_CANDIDATES = [(2, 1024), (2, 2048), (2, 4096), (4, 2048), (4, 4096), (8, 1024), (8, 2048),
+                      (16, 1024)]
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "autotune.json")
 
 _STATE_FIELDS = ("px", "py", "pz", "tau", "alive", "fperp", "dfperp", "just_created")
