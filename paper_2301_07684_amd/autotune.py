@@ -26,13 +26,15 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
 _STATE_FIELDS = ("px", "py", "pz", "tau", "alive", "fperp", "dfperp", "just_created")
 
 
-def signature(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays]) -> str:
+def signature(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], push: bool = False) -> str:
     total = sum(t.n for t in tiles)
     species = sorted({int(t.species) for t in tiles})
+    fields = sorted({int(t.field_mode) for t in tiles})
     props = torch.cuda.get_device_properties(handle.device)
     b = lambda v: 2 ** max(0, math.ceil(math.log2(max(v, 1))))
     return (f"{props.name}|cu{props.multi_processor_count}|prec{handle.precision}|"
-            f"blcfa{int(handle.blcfa)}|n{b(total)}|t{b(len(tiles))}|s{'-'.join(map(str, species))}")
+            f"blcfa{int(handle.blcfa)}|n{b(total)}|t{b(len(tiles))}|s{'-'.join(map(str, species))}|"
+            f"f{'-'.join(map(str, fields))}|push{int(push)}")
 
 
 def _snapshot(tiles):
@@ -65,9 +67,12 @@ def save_cache(cache, path: str = DEFAULT_CACHE):
 def tune(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], products: sfq.ProductBuffers,
          counters: sfq.Counters, *, seed: int = 0, step: int = 1,
          candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES, repeats: int = 4,
-         cache_path: str | None = DEFAULT_CACHE, force: bool = False) -> Dict:
-    """Sets the fastest launch shape on `handle` and returns {'shape', 'ms', 'timings', ...}."""
-    key = signature(handle, tiles)
+         cache_path: str | None = DEFAULT_CACHE, force: bool = False,
+         push: bool = False) -> Dict:
+    """Sets the fastest launch shape on `handle` and returns {'shape', 'ms', 'timings', ...}.
+    Each candidate is timed on the step the caller will run: with `push`, the kernels that push
+    the leptons inside the step."""
+    key = signature(handle, tiles, push)
     cache = load_cache(cache_path) if cache_path else {}
     if not force and key in cache:
         bpc, chunk = cache[key]["shape"]
@@ -83,7 +88,8 @@ def tune(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], products: sfq.Prod
     handle.profile(True)                 # each launch timed by the library's timing-only events
     for bpc, chunk in candidates:
         handle.set_launch(bpc, chunk)
-        plan = handle.plan(tiles, seed=seed, step=step, products=products, counters=counters)
+        plan = handle.plan(tiles, seed=seed, step=step, products=products, counters=counters,
+                           push=push)
         plan.launch()
         torch.cuda.synchronize()
         handle.profile_read_steps()
@@ -128,7 +134,7 @@ def select_form(handle_kwargs: Dict, tiles: Sequence[sfq.TileArrays],
                 products: sfq.ProductBuffers, counters: sfq.Counters, *, max_rel_error: float,
                 allow_bw_fast: bool = False, seed: int = 0, step: int = 1,
                 candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES,
-                repeats: int = 4) -> Dict:
+                repeats: int = 4, push: bool = False) -> Dict:
     """The accuracy/speed dial (the analogue of the paper's choice of coefficient counts, Sec. 4.5,
     and of its _fast pair functions, App. A functions 7 and 11): times every arithmetic form
     whose error bound is within `max_rel_error` (FP64 always; MIXED from 2e-5; each also with
@@ -136,7 +142,7 @@ def select_form(handle_kwargs: Dict, tiles: Sequence[sfq.TileArrays],
     returns the fastest as {'handle', 'precision', 'bw_fast', 'shape', 'ms', 'error_bound',
     'timings'}.  The other handles are closed; the particle state, product counts and counters
     are restored.  handle_kwargs are the sfq.Handle arguments other than precision and bw_fast
-    (units, dt, decision, blcfa, device)."""
+    (units, dt, decision, blcfa, device); `push` times the steps with the leptons' push."""
     forms = [p for p in (sfq.FP64, sfq.MIXED)
              if max(FORM_ERRORS[p].values()) <= max_rel_error]
     if not forms:
@@ -151,7 +157,7 @@ def select_form(handle_kwargs: Dict, tiles: Sequence[sfq.TileArrays],
                 h = sfq.Handle(**handle_kwargs, precision=prec, bw_fast=bw)
                 handles.append(h)
                 r = tune(h, tiles, products, counters, seed=seed, step=step,
-                         candidates=candidates, repeats=repeats, cache_path=None)
+                         candidates=candidates, repeats=repeats, cache_path=None, push=push)
                 _restore(tiles, snap)
                 name = ("fp64" if prec == sfq.FP64 else "mixed") + ("+bw_fast" if bw else "")
                 timings[name] = r["ms"]

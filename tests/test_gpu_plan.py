@@ -136,6 +136,14 @@ def test_autotune_restores_state_and_picks_a_candidate(dev, tmp_path):
     torch.cuda.synchronize()
     assert same(state(tuned), state(ref))  # launch shapes never change results
     assert same(product_set(pt), product_set(pr))
+    # the pushed form is tuned on its own kernels, under its own cache entry, and its
+    # momenta (which the timed steps push) come back as they were
+    pushed = clone_tiles(base)
+    res3 = autotune.tune(h, pushed, pt, ct, cache_path=cache, repeats=2, push=True)
+    assert not res3["cached"] and tuple(res3["shape"]) in autotune.DEFAULT_CANDIDATES
+    assert same(state(pushed), state(base))
+    assert autotune.signature(h, pushed, True) != autotune.signature(h, pushed, False)
+    assert len(autotune.load_cache(cache)) == 2
 
 
 def test_reserve_and_kernel_timing(dev):
