@@ -362,8 +362,9 @@ def main():
                          "instead of the autotuner (e.g. for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the QED step is independent per particle and this "
-              "build runs on a single MI355X; --gpus above 1 is not supported.", file=sys.stderr)
+        print("bench.py measures one GPU: the QED step is independent per particle and the "
+              "library runs it on a single MI355X; --gpus above 1 is not supported.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
