@@ -229,9 +229,9 @@ def constant_field_kernel_bytes(processed, emitted):
 def run_constant_field(dev, n, warmup=2, launch=None):
     """The paper's constant-field set-up at scale: n electrons of 10 GeV at chi = 1 in a uniform
     magnetic field (one field value for the tile), 1.3 fs in 130 steps of 0.01 fs with the
-    fused push and recoil, at the library's default launch shape (or `launch`): the autotuner,
-    run on the first 2^28 electrons, picked shapes that were no faster on all 2^30.  Returns
-    timings, counters and the photon count against N T R."""
+    fused push and recoil, at the library's default launch shape (or `launch`), which the
+    autotuner, run on the first 2^28 electrons, also picks.  Returns timings, counters and the
+    photon count against N T R."""
     import torch
 
     from paper_2301_07684_amd import inputs, sfq
