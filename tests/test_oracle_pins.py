@@ -565,6 +565,133 @@ def test_blcfa_acceptance_rule():
     assert not O.blcfa_accept(gbar, limit, g, chi, ratio * 1.001)
 
 
+@pytest.mark.parametrize("gamma,chi", [(1e3, 0.05), (2e4, 1.0), (5e5, 30.0), (1e2, 400.0)])
+def test_photon_pdf_energy_is_the_w_spectrum_through_the_jacobian(gamma, chi):
+    # Eq. (chang): d2W/dt dgamma_ph = d2W/dt dw * (2 + 3 w^3 chi)^2 / (18 gamma w^2 chi), with
+    # gamma_ph = 3 gamma chi w^3 / (2 + 3 chi w^3).  The w spectrum is pinned (it integrates to
+    # W~_rad, has the K_{5/3} form and the slope 9 Gamma(2/3)/2^{1/3} at 0), so the gamma-space
+    # pdf divided by the w spectrum times the printed Jacobian must be a constant in w (the
+    # oracle's pdf omits the w-independent prefactor; the constant works out to gamma chi).
+    # Tolerance: the pdf takes gamma_ph, so u = g/(gamma - g) carries a rounding error of about
+    # eps gamma/(gamma - g), which K_{2/3}(z), z = w^3, amplifies by about z.
+    ratios, tols = [], []
+    for w in [1e-3, 0.02, 0.1, 0.3, 0.6, 1.0, 1.5, 2.2, 3.0]:
+        x = 3.0 * chi * w ** 3
+        g_ph = gamma * x / (2.0 + x)
+        if not (0.0 < g_ph < gamma):
+            continue
+        pdf = O.photon_pdf_energy(g_ph, gamma, chi)
+        jac_inv = (2.0 + x) ** 2 / (18.0 * gamma * w * w * chi)
+        ratios.append(pdf / (O.photon_spectrum_w(w, chi) * jac_inv))
+        tols.append(1e-13 + 16 * 2.2e-16 * (1.0 + w ** 3) * (2.0 + x) / 2.0)
+    assert len(ratios) >= 8
+    ratios, tols = np.array(ratios), np.array(tols)
+    assert np.all(np.abs(ratios / (gamma * chi) - 1.0) < tols), ratios / (gamma * chi) - 1.0
+
+
+def test_photon_pdf_energy_soft_photon_divergence():
+    # the gamma-space LCFA spectrum diverges as gamma_ph^{-2/3} for soft photons (Sec. 5, text
+    # after Eq. (chang)): pdf * g^{2/3} tends to a constant, fixed by K_{2/3}(z) ~ Gamma(2/3)/2
+    # (2/z)^{2/3} with z = 2u/(3 chi) -> 2 g/(3 chi gamma):  2 * Gamma(2/3)/2 * (3 chi gamma/g)^{2/3}
+    gamma, chi = 1e4, 2.0
+    for g in (1e-6, 1e-5):
+        want = math.gamma(2.0 / 3.0) * (3.0 * chi * gamma / g) ** (2.0 / 3.0)
+        assert abs(O.photon_pdf_energy(g, gamma, chi) / want - 1.0) < 2e-3, g
+
+
+def _blcfa_run(F_seq, P, dt, tc):
+    """Steps of the beyond-LCFA force update where the averaged momentum is exactly P x
+    and the Lorentz force is exactly the transverse F_seq[n] (so F_perp = F_seq[n])."""
+    Fp, dF, jc = [0.0] * 3, [0.0] * 3, True
+    out = []
+    for F in F_seq:
+        h = [0.0, F[1] * dt / 2.0, F[2] * dt / 2.0]   # exact: dt is a power of two
+        p_prev = [P, -h[1], -h[2]]
+        p_push = [P, h[1], h[2]]
+        out.append(O.blcfa_update(p_prev, p_push, dt, tc, Fp, dF, jc))
+        _, _, _, _, _, Fp, dF, jc = out[-1]
+    return out
+
+
+@pytest.mark.parametrize("a,b,c", [((0, 3.0, -2.0), (0, 0.5, 0.25), (0, -0.125, 0.375)),
+                                   ((0, 40.0, 7.0), (0, -1.0, 2.0), (0, 0.0, 0.0)),
+                                   ((0, 1e9, 0.0), (0, 1.0, 0.0), (0, 0.0, 0.0))])
+def test_blcfa_delta_closed_form_for_a_quadratic_force(a, b, c):
+    # Eq. (condit) for F^(n) = a + b n + c n^2 (transverse to p_L = P x):
+    #   dF/dt = (F^(n) - F^(n-1))/dt = (b + c (2n - 1))/dt,  d2F/dt2 = 2c/dt^2,
+    #   delta = tau_C^2 [ (dF/dt)^2 + |F^(n) . d2F/dt2| ]
+    # and the flag below Eq. (condit): gamma^2 delta/zeta^2 > chi^2 F^2 and chi > zeta, with
+    # chi = tau_C gamma |F| (Eq. (chi_p)).  Evaluated here by hand from the sequence.
+    dt, tc, P = 2.0 ** -6, 3.0328e-6, 2.5e3
+    zeta = 2.220446049250313e-16
+    a, b, c = (np.array(v, dtype=float) for v in (a, b, c))
+    seq = [a + b * n + c * n * n for n in range(6)]
+    out = _blcfa_run(seq, P, dt, tc)
+    gam = math.sqrt(1.0 + P * P)
+    for n in range(2, 6):
+        flag, g, chi, delta, first, Fp, dF, jc = out[n]
+        F = seq[n]
+        d1 = (b + c * (2 * n - 1)) / dt
+        d2 = 2.0 * c / dt ** 2
+        want = tc * tc * (np.dot(d1, d1) + abs(np.dot(F, d2)))
+        F2 = np.dot(F, F)
+        assert not first
+        assert abs(g / gam - 1.0) < 1e-15
+        assert abs(chi / (tc * gam * math.sqrt(F2)) - 1.0) < 1e-14
+        assert abs(delta - want) <= 1e-12 * want
+        assert np.allclose(Fp, F, rtol=1e-15, atol=0)
+        assert np.allclose(dF, seq[n] - seq[n - 1], rtol=1e-12, atol=1e-12 * np.abs(F).max())
+        expect_flag = (gam * gam * want / zeta ** 2 > chi * chi * F2) and chi > zeta
+        assert flag == expect_flag, (n, flag)
+    # the first step after creation stores F and no difference; the second sees F^(n-2) =
+    # F^(n-1) (the paper's rule for new particles), so d2F/dt2 = (F^(1) - F^(0))/dt^2
+    flag0, _, _, delta0, first0, Fp0, dF0, _ = out[0]
+    assert first0 and not flag0 and delta0 == 0.0 and dF0 == [0.0, 0.0, 0.0]
+    _, _, _, delta1, first1, _, _, _ = out[1]
+    d = (seq[1] - seq[0]) / dt
+    want1 = tc * tc * (np.dot(d, d) + abs(np.dot(seq[1], d / dt)))
+    assert not first1 and abs(delta1 - want1) <= 1e-12 * want1
+
+
+def test_blcfa_flag_both_ways():
+    # a force of 1e9 changing by 1 per step: delta/zeta^2 stays below tau_C^2 F^4, so the
+    # fields count as constant (no flag); at 1e3 the same change raises the flag
+    dt, tc, P = 2.0 ** -6, 3.0328e-6, 2.5e3
+    for mag, want in ((1e9, False), (1e3, True)):
+        seq = [np.array([0.0, mag + n, 0.0]) for n in range(4)]
+        out = _blcfa_run(seq, P, dt, tc)
+        assert all(o[0] == want for o in out[2:]), mag
+
+
+def test_blcfa_threshold_matches_the_sinh_triple_angle_form():
+    # Eq. (gammaLCFA) with sinh(3 asinh x) = 3 x + 4 x^3:
+    #   gamma_LCFA = 0.7 gamma / (1 + 4/(3 pi chi) (3 x + 4 x^3)),  x = chi tau/(8 gamma tau_C),
+    # and tau/tau_C = 2 pi sqrt(F_perp^2/delta) (text above Eq. (gammaLCFA))
+    F = [3.0, -4.0, 12.0]  # |F| = 13
+    for gamma, chi in [(1e3, 0.01), (2e4, 1.0), (5e5, 50.0)]:
+        for x in 10.0 ** np.linspace(-3, 3, 25):
+            tau_ratio = 8.0 * gamma * x / chi
+            delta = (2.0 * math.pi * 13.0 / tau_ratio) ** 2
+            want = 0.7 * gamma / (1.0 + 4.0 / (3.0 * math.pi * chi) * (3.0 * x + 4.0 * x ** 3))
+            got = O.blcfa_threshold(F, delta, gamma, chi)
+            assert abs(got / want - 1.0) < 1e-12, (gamma, chi, x, got, want)
+
+
+def test_pair_rate_normalisation_against_the_printed_bounds():
+    # Eq. (pp_tot_real) through the rate function itself: W_pair gamma/(alpha lambda_r/lambda_C)
+    # = W~_pair/(sqrt3 pi), which the paper prints as 9.1e-6 at chi = 0.3 (Sec. 4.2, on the fast
+    # rate) and 3.5e-119 at chi = 0.01 (Sec. 4.2, after Eq. (low_chi)).  A chi/gamma for 1/gamma
+    # slip or a missing sqrt(3) or pi would change the printed digits.
+    g = json.load(open(os.path.join(GOLD, "paper_printed_values.json")))
+    lr_lc = 1.0 / 3.0328e-6
+    for key in ("pair_rate_bound_chi_0p01", "pair_rate_bound_chi_0p3"):
+        e = g[key]
+        for gam in (37.0, 4.5e3):
+            W = O.rates(O.PHOTON, [gam], [e["chi"]], lr_lc)[0]
+            val = W * gam / (O.alpha() * lr_lc)
+            assert float(f"{val:.1e}") == e["printed"], (key, gam, val)
+
+
 # ------------------------------------------------------------------------------------------------
 # Boris push (the leapfrog momentum update of the PIC cycle, paper Fig. 7), pinned by properties
 # of the scheme rather than by its formula: an exact rotation in a pure magnetic field, an exact
