@@ -23,7 +23,10 @@
  *     different streams share the handle's emitter queue: the library orders them on the
  *     device (a step waits for the previous step of the handle when it was enqueued on another
  *     stream), so they are correct but do not overlap; use one handle per stream for
- *     concurrency.  Inside a stream capture that ordering is the caller's graph's.
+ *     concurrency.
+ *   - sfq_step is not captured into graphs: on a stream that is capturing it returns
+ *     SFQ_E_STATE and enqueues nothing (a graph would keep pointers to scratch memory the handle
+ *     reuses).  Graphs of steps come from plans (sfq_plan_capture), which own theirs.
  */
 #ifndef SFQ_H
 #define SFQ_H
@@ -40,7 +43,8 @@ typedef struct sfq_ctx* sfq_handle;
 typedef enum {
     SFQ_OK = 0,
     SFQ_E_ARG = 1,      /* invalid argument (NULL pointer, bad enum, inconsistent config)      */
-    SFQ_E_STATE = 2,    /* invalid handle                                                        */
+    SFQ_E_STATE = 2,    /* invalid handle, or a call not allowed in this state (sfq_step on a
+                           capturing stream)                                                     */
     SFQ_E_NOMEM = 3,    /* device allocation failed                                              */
     SFQ_E_CAPACITY = 4, /* request exceeds a fixed limit of the library                          */
     SFQ_E_DEVICE = 5,   /* HIP runtime error                                                     */

@@ -4,8 +4,9 @@ For a given set of tiles it times each candidate launch shape (blocks per comput
 length, see sfq_set_launch) on the real data with a plan, keeps the fastest and caches the
 choice in a JSON file keyed by the device, the precision and a coarse signature of the workload
 (total particles and number of tiles rounded to powers of two, species mix).  The particle
-state is snapshotted before tuning and restored afterwards, so a tuned run gives the same
-results as an untuned one (results never depend on the launch shape).
+state, the products already in the caller's buffers and the counters are snapshotted before
+tuning and restored afterwards, so a tuned run gives the same results as an untuned one
+(results never depend on the launch shape).
 """
 from __future__ import annotations
 
@@ -48,6 +49,30 @@ def _restore(tiles, snap):
             getattr(t, f).copy_(v)
 
 
+_PRODUCT_FIELDS = ("px", "py", "pz", "tau", "uid", "parent")
+_PRODUCT_SPECIES = ("photons", "electrons", "positrons")
+
+
+def _snapshot_products(products: sfq.ProductBuffers):
+    """The products already in the buffers (the timed launches write theirs from slot 0)."""
+    counts = products.host_counts()
+    snap = []
+    for k, name in enumerate(_PRODUCT_SPECIES):
+        ps = getattr(products, name)
+        m = min(counts[k], ps.capacity)
+        snap.append({f: getattr(ps, f)[:m].clone() for f in _PRODUCT_FIELDS} if m > 0 else {})
+    return products.counts.clone(), snap
+
+
+def _restore_products(products: sfq.ProductBuffers, saved):
+    counts, snap = saved
+    for name, s in zip(_PRODUCT_SPECIES, snap):
+        ps = getattr(products, name)
+        for f, v in s.items():
+            getattr(ps, f)[:v.numel()].copy_(v)
+    products.counts.copy_(counts)
+
+
 def load_cache(path: str = DEFAULT_CACHE) -> Dict[str, List[int]]:
     try:
         with open(path) as f:
@@ -79,7 +104,7 @@ def tune(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], products: sfq.Prod
         handle.set_launch(bpc, chunk)
         return dict(cache[key], cached=True, key=key)
     snap = _snapshot(tiles)
-    counts0 = products.counts.clone()
+    prod0 = _snapshot_products(products)
     cnt0 = counters.t.clone()
     timings = {}
     was_profiling = getattr(handle, "profiling", False)
@@ -104,7 +129,7 @@ def tune(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], products: sfq.Prod
     best = min(timings, key=timings.get)
     bpc, chunk = (int(v) for v in best.split("x"))
     handle.set_launch(bpc, chunk)
-    products.counts.copy_(counts0)
+    _restore_products(products, prod0)
     counters.t.copy_(cnt0)
     torch.cuda.synchronize()
     entry = {"shape": [bpc, chunk], "ms": timings[best], "timings": timings,

@@ -2106,19 +2106,36 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     const sfq_status v = validate_desc(h, desc, off, chunk);
     if (v != SFQ_OK) return v;
     const int nt = desc->ntiles;
-    const int nchunks = (int)off[nt];
-    if (nchunks == 0) return SFQ_OK;
     HIP_TRY(h, hipSetDevice(h->device));
+    // A captured step would keep pointers to memory the handle recycles (a staging slot of the
+    // descriptors, the emitter queue, which may be reallocated): graphs are made from plans,
+    // which own both.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(h, hipStreamIsCapturing((hipStream_t)stream, &cap));
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(h, SFQ_E_STATE, "sfq_step: the stream is capturing a graph; capture a plan "
+                                    "instead (sfq_plan_create, sfq_plan_capture)");
+    const int nchunks = (int)off[nt];
+    if (nchunks == 0) {
+        // nothing to step; the product counts are still zeroed when asked
+        if (desc->zero_product_counts) {
+            if (desc->nsets > 0) {
+                for (int k = 0; k < desc->nsets; ++k)
+                    HIP_TRY(h, hipMemsetAsync(desc->product_sets[k].product_counts, 0,
+                                              3 * sizeof(unsigned long long),
+                                              (hipStream_t)stream));
+            } else {
+                HIP_TRY(h, hipMemsetAsync(desc->product_counts, 0, 3 * sizeof(unsigned long long),
+                                          (hipStream_t)stream));
+            }
+        }
+        return SFQ_OK;
+    }
     const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk);
     {
         const sfq_status q = ensure_queue(h, qs, "sfq_step");
         if (q != SFQ_OK) return q;
     }
-    // steps on different streams share the emitter queue: order them on the device (outside
-    // stream capture, where the caller's graph orders its own nodes)
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    HIP_TRY(h, hipStreamIsCapturing((hipStream_t)stream, &cap));
-    const bool order = cap == hipStreamCaptureStatusNone;
     // descriptors through a ring of pinned staging buffers and their device copies
     const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
     const size_t set_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
@@ -2130,11 +2147,11 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     memcpy(db.data() + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
     if (desc->nsets > 0)
         memcpy(db.data() + set_pos, desc->product_sets, desc->nsets * sizeof(sfq_product_set));
-    // The same descriptors as the last upload (outside capture, where steps are ordered on the
-    // device, see below): the kernels read that device copy again, with no copy from the host
-    // (a copy costs a transfer and its dispatch latency on every step).  Device copies are
-    // read-only; a slot is overwritten only after the last step that used it (its event).
-    const bool reuse = order && h->last_slot >= 0 && h->last_desc == db;
+    // The same descriptors as the last upload: the kernels read that device copy again, with
+    // no copy from the host (a copy costs a transfer and its dispatch latency on every step).
+    // Device copies are read-only; a slot is overwritten only after the last step that used it
+    // (its event).
+    const bool reuse = h->last_slot >= 0 && h->last_desc == db;
     Staging& S = h->staging[reuse ? h->last_slot : h->next_staging];
     if (!reuse) {
         const int slot = h->next_staging;
@@ -2150,17 +2167,14 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
         memcpy(S.host, db.data(), used);
         HIP_TRY(h, hipMemcpyAsync(S.dev, S.host, used, hipMemcpyHostToDevice,
                                   (hipStream_t)stream));
-        // under capture the graph copies from the host buffer when it runs, so that buffer
-        // (which the ring reuses) is not a cache for later steps
-        h->last_slot = order ? slot : -1;
-        if (order) h->last_desc.swap(db);
+        h->last_slot = slot;
+        h->last_desc.swap(db);
     }
-    if (order) {
-        if (!h->queue_free)
-            HIP_TRY(h, hipEventCreateWithFlags(&h->queue_free, hipEventDisableTiming));
-        if (h->queue_used && h->queue_stream != (hipStream_t)stream)
-            HIP_TRY(h, hipStreamWaitEvent((hipStream_t)stream, h->queue_free, 0));
-    }
+    // steps on different streams share the emitter queue: order them on the device
+    if (!h->queue_free)
+        HIP_TRY(h, hipEventCreateWithFlags(&h->queue_free, hipEventDisableTiming));
+    if (h->queue_used && h->queue_stream != (hipStream_t)stream)
+        HIP_TRY(h, hipStreamWaitEvent((hipStream_t)stream, h->queue_free, 0));
     // the queue shape must describe the allocation actually bound
     QueueShape bound = qs;
     bound.entries = h->queue_entries;
@@ -2176,11 +2190,9 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, prof_events(h));
     HIP_TRY(h, hipGetLastError());
     HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
-    if (order) {
-        HIP_TRY(h, hipEventRecord(h->queue_free, (hipStream_t)stream));
-        h->queue_stream = (hipStream_t)stream;
-        h->queue_used = true;
-    }
+    HIP_TRY(h, hipEventRecord(h->queue_free, (hipStream_t)stream));
+    h->queue_stream = (hipStream_t)stream;
+    h->queue_used = true;
     return SFQ_OK;
 }
 

@@ -110,6 +110,20 @@ def test_blcfa_steps_match_oracle(dev, precision):
         g_gpu = np.sqrt(1 + np.sum(pg ** 2, axis=0))
         g_ref = np.sqrt(1 + np.sum(ref["p"] ** 2, axis=0))
         assert np.all(np.abs(g_gpu[em] - g_ref[em]) <= tol["recoil"] * g_push[em])
+        # component by component: the recoiled momentum and the photon (along the pushed one)
+        dvec = np.linalg.norm(pg[:, em] - ref["p"][:, em], axis=0)
+        assert np.all(dvec <= tol["recoil"] * g_push[em])
+        gpush = dict(zip(uid.view(np.uint64).tolist(), g_push))
+        ph = {int(a): j for j, a in enumerate(parents)}
+        php = np.stack([t[:k].cpu().numpy() for t in (prods.photons.px, prods.photons.py,
+                                                      prods.photons.pz)])
+        compared = 0
+        for q in ref["products"]:
+            if q["parent"] in ph:
+                d = np.linalg.norm(php[:, ph[q["parent"]]] - np.array([q["px"], q["py"], q["pz"]]))
+                assert d <= tol["recoil"] * gpush[q["parent"]], q["parent"]
+                compared += 1
+        assert compared == em.sum()
         assert np.array_equal(pg[:, ~emit_gpu], p_push[:, ~emit_gpu])  # others untouched
         tot_emit += c["emitted"]
         tot_rej += c["blcfa_rejected"]

@@ -146,6 +146,29 @@ def test_autotune_restores_state_and_picks_a_candidate(dev, tmp_path):
     assert len(autotune.load_cache(cache)) == 2
 
 
+def test_autotune_keeps_products_already_in_the_buffers(dev, tmp_path):
+    # the timed launches write their products from slot 0; the caller's products come back
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    tiles = make_tiles(dev, h, sizes=(20000, 6000))
+    pb, cnt = sfq.ProductBuffers.empty(60000, 60000, dev), sfq.Counters(dev)
+    h.step(clone_tiles(tiles), seed=7, step=1, products=pb, counters=cnt)
+    torch.cuda.synchronize()
+    before = product_set(pb)
+    counts = pb.host_counts()
+    assert counts[0] > 100 and counts[1] > 0
+    raw = [getattr(getattr(pb, sp), f)[:counts[k]].clone()
+           for k, sp in enumerate(("photons", "electrons", "positrons"))
+           for f in ("px", "py", "pz", "tau", "uid", "parent")]
+    autotune.tune(h, tiles, pb, cnt, cache_path=str(tmp_path / "t.json"), repeats=1,
+                  candidates=[(2, 1024), (8, 2048)])
+    assert pb.host_counts() == counts
+    assert same(product_set(pb), before)
+    raw2 = [getattr(getattr(pb, sp), f)[:counts[k]]
+            for k, sp in enumerate(("photons", "electrons", "positrons"))
+            for f in ("px", "py", "pz", "tau", "uid", "parent")]
+    assert all(torch.equal(a, b) for a, b in zip(raw, raw2))  # in place, in the same order
+
+
 def test_reserve_and_kernel_timing(dev):
     h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
     h.reserve(50000, 4)
