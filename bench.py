@@ -49,20 +49,30 @@ HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_kernel_plane_wave_fp64.md")
 
 
-def stream_kernel_bytes(n_total, processed, emitted, converted):
+def stream_kernel_bytes(n_flags, processed, emitted, converted):
     """Algorithmic bytes of the streaming kernel for one step (optical-depth decisions).  Every
-    particle slot: its alive flag (1 B).  Every live particle: p (24), E and B (48) and the
-    optical depth (8) read.  Every live particle that does not emit: the optical depth written
-    back (8); emitters get a fresh depth in the emitter kernel.  The particle id is not needed
-    here: only emitters use it (emitter kernel)."""
-    return n_total + 80 * processed + 8 * (processed - emitted - converted)
+    particle slot of a tile with alive flags (photons; leptons never die in the step and have
+    none): its flag (1 B).  Every live particle: p (24), E and B (48) and the optical depth (8)
+    read.  Every live particle that does not emit: the optical depth written back (8); emitters
+    get a fresh depth in the emitter kernel.  The particle id is not needed here: only emitters
+    use it (emitter kernel)."""
+    return n_flags + 80 * processed + 8 * (processed - emitted - converted)
 
 
-def pushed_stream_kernel_bytes(n_total, processed, emitted, converted, leptons):
+def survey_step_bytes(processed, emitted, converted):
+    """The whole step's bytes as the scope table counts them (a fixed yardstick for the step's
+    roofline fraction): 96 B per particle update (p, E, B, optical depth and id read, optical
+    depth written), plus per Compton emission the emitter's momentum (24 B) and a photon
+    product (48 B), per conversion two lepton products (96 B), and 8 B of queue traffic per
+    event."""
+    return 96 * processed + (24 + 48 + 8) * emitted + (96 + 8) * converted
+
+
+def pushed_stream_kernel_bytes(n_flags, processed, emitted, converted, leptons):
     """The streaming kernel with the fused momentum push: as above, plus the pushed momentum
     (24 B) written back for every live lepton that does not emit (emitters' momenta are written
     after the recoil by the emitter kernel, as without the push)."""
-    return stream_kernel_bytes(n_total, processed, emitted, converted) + 24 * (leptons - emitted)
+    return stream_kernel_bytes(n_flags, processed, emitted, converted) + 24 * (leptons - emitted)
 
 
 def emit_kernel_bytes(emitted, converted):
@@ -73,11 +83,11 @@ def emit_kernel_bytes(emitted, converted):
     return 88 * emitted + 105 * converted
 
 
-def wave_stream_kernel_bytes(n_total, processed, emitted, converted):
+def wave_stream_kernel_bytes(n_flags, processed, emitted, converted):
     """The streaming kernel with plane-wave tiles (fields computed in the kernel): as
     stream_kernel_bytes, with the wave's amplitude and phase (16 B) read instead of E and B
     (48 B)."""
-    return n_total + 48 * processed + 8 * (processed - emitted - converted)
+    return n_flags + 48 * processed + 8 * (processed - emitted - converted)
 
 
 def device_tiles(dev, sfq, h, workloads, wave=False):
@@ -95,18 +105,46 @@ def device_tiles(dev, sfq, h, workloads, wave=False):
         else:
             fields = dict(ex=t(w["E"][0]), ey=t(w["E"][1]), ez=t(w["E"][2]), bx=t(w["B"][0]),
                           by=t(w["B"][1]), bz=t(w["B"][2]))
+        # photons convert and die; leptons never die in the step and carry no alive flags
+        alive = (torch.ones(n, dtype=torch.uint8, device=dev)
+                 if int(w["species"]) == sfq.PHOTON else None)
         tiles.append(sfq.TileArrays(int(w["species"]), *[t(w["p"][k]) for k in range(3)],
                                     **fields, tau=h.init_optical_depth(uid, seed=0), uid=uid,
-                                    alive=torch.ones(n, dtype=torch.uint8, device=dev)))
+                                    alive=alive))
     return tiles
 
 
-def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False, wave=False):
+class StateReset:
+    """The tiles' evolving state (momenta, optical depths, alive flags) as it was when made, put
+    back by a device copy before every timed step, outside the step's timed events, so that each
+    repeat steps the same ensemble (no converted photons pile up as dead slots).  A copy through
+    an unrelated buffer after it leaves the caches as a step of its own would find them."""
+
+    def __init__(self, tiles, dev, flush_bytes=512 << 20):
+        import torch
+
+        self.pairs = []
+        for t in tiles:
+            for f in ("px", "py", "pz", "tau", "alive"):
+                v = getattr(t, f)
+                if v is not None:
+                    self.pairs.append((v, v.clone()))
+        self.flush_src = torch.empty(flush_bytes // 8, dtype=torch.float64, device=dev)
+        self.flush_dst = torch.empty_like(self.flush_src)
+
+    def __call__(self):
+        for dst, src in self.pairs:
+            dst.copy_(src)
+        self.flush_dst.copy_(self.flush_src)
+
+
+def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False, wave=False,
+             approx=0):
     import torch
 
     from paper_2301_07684_amd import autotune, inputs, sfq
 
-    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=precision)
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=precision, approx=approx)
     tiles = []
     for species in (sfq.ELECTRON, sfq.PHOTON):
         if workload == "plane_wave":
@@ -115,7 +153,8 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False
             w = inputs.plane_wave(n, seed=inputs.SEED_SKEW, species=species, chi_range=(1e-4, 1e3))
         tiles += device_tiles(dev, sfq, h, [w], wave=wave)
         del w
-    prods = sfq.ProductBuffers.empty(n // 4, n // 16, dev)
+    n_flags = sum(t.n for t in tiles if t.alive is not None)
+    prods = sfq.ProductBuffers.empty(n // 2, n // 8, dev)
     cnt = sfq.Counters(dev)
     if launch is None:
         tuned = autotune.tune(h, tiles, prods, cnt, seed=0, step=1, repeats=3, cache_path=None,
@@ -124,18 +163,22 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False
         h.set_launch(*launch)
         tuned = {"shape": list(launch)}
     h.reserve(2 * n, 2)
+    reset = StateReset(tiles, dev)
     for s in range(warmup):
+        reset()
         h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt, push=push,
                zero_product_counts=True)
     torch.cuda.synchronize()
     cnt.reset()
     # the library's timing events (before the streaming kernel, between it and the emitter
-    # pass, after that; no system-scope fence) time every step's kernels on the step's stream
+    # pass, after that; no system-scope fence) time every step's kernels on the step's stream;
+    # the state reset runs between them
     h.profile(True)
     h.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(steps):
+        reset()
         # the step zeroes the product counts itself: the buffers hold this step's products
         h.step(tiles, seed=0, step=warmup + s + 1, products=prods, counters=cnt, push=push,
                zero_product_counts=True)
@@ -150,11 +193,13 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False
     c = cnt.as_dict()
     if c["overflow"]:
         raise RuntimeError("product buffers overflowed during the benchmark")
+    qbytes = h.queue_bytes()
     h.close()
-    del tiles, prods
+    del tiles, prods, reset
     torch.cuda.empty_cache()
-    return dict(wall=wall, step_ms=step_ms, counters=c, n_total=2 * n,
-                bulk_ms=bulk_ms / nprof, emit_ms=emit_ms / nprof, shape=tuned["shape"])
+    return dict(wall=wall, device_s=float(step_ms.sum()) * 1e-3, step_ms=step_ms, counters=c,
+                n_total=2 * n, n_flags=n_flags, bulk_ms=bulk_ms / nprof, emit_ms=emit_ms / nprof,
+                shape=tuned["shape"], queue_bytes=qbytes)
 
 
 def run_batched(steps, warmup, dev):
@@ -175,7 +220,9 @@ def run_batched(steps, warmup, dev):
     plan = h.plan(tiles, seed=0, step=1, products=prods, counters=cnt)
     plan.capture(1)
     stream = torch.cuda.current_stream()
+    reset = StateReset(tiles, dev)
     for _ in range(warmup):
+        reset()
         plan.replay()
     torch.cuda.synchronize()
     cnt.reset()
@@ -183,6 +230,7 @@ def run_batched(steps, warmup, dev):
           for _ in range(steps)]
     t0 = time.perf_counter()
     for s in range(steps):
+        reset()
         ev[s][0].record(stream)
         plan.replay()
         ev[s][1].record(stream)
@@ -192,11 +240,23 @@ def run_batched(steps, warmup, dev):
     c = cnt.as_dict()
     if c["overflow"]:
         raise RuntimeError("product buffers overflowed during the batched benchmark")
+    # the streaming / emitter split, from plan launches (the graph's kernels, outside the
+    # graph) timed with the library's events
+    h.profile(True)
+    h.profile_read()
+    for s in range(min(steps, 10)):
+        reset()
+        plan.launch()
+    bulk, emit = h.profile_read_steps()
+    h.profile(False)
     plan.close()
     h.close()
-    del tiles, prods
+    n_flags = sum(t.n for t in tiles if t.alive is not None)
+    del tiles, prods, reset
     torch.cuda.empty_cache()
-    return dict(wall=wall, step_ms=step_ms, counters=c, n_total=n_total, tuned=tuned)
+    return dict(wall=wall, device_s=float(step_ms.sum()) * 1e-3, step_ms=step_ms, counters=c,
+                n_total=n_total, n_flags=n_flags, tuned=tuned, bulk_ms=float(np.mean(bulk)),
+                emit_ms=float(np.mean(emit)))
 
 
 def run_served(dev, jobs_per_client=16, steps=40):
@@ -285,27 +345,51 @@ def run_constant_field(dev, n, warmup=2, launch=None):
                 bulk_ms=float(bulk.mean()), emit_ms=float(emit.mean()), shape=shape)
 
 
-def cpu_baseline(n_sample=24576):
-    """The oracle as it stands on a bounded sample of the FP64 workload (all host cores)."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_sample=16384):
+    """The oracle as it stands on a bounded sample of the FP64 workload (all host cores): the
+    full step of every sampled particle (the workload's own emission mix), and, on the same
+    sample, chi and the rate alone (a particle that does not emit) and, from the difference,
+    the cost of each emitter's sampling, recoil and products."""
     from oracle import oracle as O
     from paper_2301_07684_amd import inputs
 
     O.build()
     rng_idx = np.random.default_rng(0).choice(1 << 24, n_sample // 2, replace=False)
-    t0 = time.perf_counter()
-    done = 0
-    for species in (O.ELECTRON, O.PHOTON):
-        w = inputs.plane_wave(1 << 24, idx=rng_idx, species=species)
+    ws = [inputs.plane_wave(1 << 24, idx=rng_idx, species=sp) for sp in (O.ELECTRON, O.PHOTON)]
+    t_rate = t_step = 0.0
+    done = emitters = 0
+    for species, w in zip((O.ELECTRON, O.PHOTON), ws):
         uid = w["uid"].view(np.uint64)
         tau0 = O.init_optical_depth(0, uid)
-        O.step(species, w["p"], w["E"], w["B"], tau0, uid, dt=inputs.DT,
-               lc_over_lr=inputs.LC_OVER_LR, seed=0, step=1)
+        t0 = time.perf_counter()
+        g, c = O.chi(species, w["p"], w["E"], w["B"], inputs.LC_OVER_LR)
+        O.rates(species, g, c, 1.0 / inputs.LC_OVER_LR)
+        t1 = time.perf_counter()
+        ref = O.step(species, w["p"], w["E"], w["B"], tau0, uid, dt=inputs.DT,
+                     lc_over_lr=inputs.LC_OVER_LR, seed=0, step=1)
+        t2 = time.perf_counter()
+        t_rate += t1 - t0
+        t_step += t2 - t1
         done += uid.size
-    dt = time.perf_counter() - t0
-    return dict(value=done / dt, unit="particle-updates/s", cores=O.num_threads(), kind="oracle",
+        emitters += int(np.sum(ref["emitted"]))
+    per_emitter = max(0.0, t_step - t_rate) / max(1, emitters)
+    return dict(value=done / t_step, unit="particle-updates/s", cores=O.num_threads(),
+                kind="oracle", cpu_model=cpu_model(),
+                rate_only_updates_per_s=done / t_rate,
+                seconds_per_emitter=per_emitter, emitters_in_sample=emitters,
                 sample=f"{done} particles ({n_sample // 2} electrons + {n_sample // 2} photons, "
                        f"seeded random indices) of the FP64 plane-wave workload, one full step "
-                       f"each, {dt:.1f} s")
+                       f"each ({t_step:.1f} s; chi and rate alone {t_rate:.1f} s)")
 
 
 def measured_traffic():
@@ -354,6 +438,8 @@ def main():
     ap.add_argument("--no-constant-field", action="store_true")
     ap.add_argument("--no-wave", action="store_true")
     ap.add_argument("--no-mixed-same", action="store_true")
+    ap.add_argument("--no-dial", action="store_true",
+                    help="skip the truncated-table forms of the accuracy/speed dial")
     ap.add_argument("--constant-field-n", type=int, default=1 << 30,
                     help="electrons of the constant-field run")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -406,6 +492,14 @@ def main():
     if wave is not None:
         print(f"# plane-wave fields form done: {wave['wall'] / args.steps * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
+    dial = {}
+    if not args.no_dial:
+        # the accuracy/speed dial's truncated forms on the headline workload
+        for prec, name in ((0, "fp64_trunc"), (1, "mixed_trunc")):
+            dial[name] = run_form(prec, "plane_wave", args.n, args.steps, args.warmup, dev,
+                                  launch, approx=1)
+            print(f"# {name} form done: {dial[name]['wall'] / args.steps * 1e3:.3f} ms/step",
+                  file=sys.stderr, flush=True)
     const = None if args.no_constant_field else run_constant_field(dev, args.constant_field_n,
                                                                    launch=launch)
     if const is not None:
@@ -414,9 +508,9 @@ def main():
 
     c = f64["counters"]
     K = args.steps
-    value = c["processed"] / f64["wall"]
+    value = c["processed"] / f64["device_s"]
     per = lambda k: c[k] / K
-    bulk_bytes = stream_kernel_bytes(f64["n_total"], per("processed"), per("emitted"),
+    bulk_bytes = stream_kernel_bytes(f64["n_flags"], per("processed"), per("emitted"),
                                      per("converted"))
     emit_bytes = emit_kernel_bytes(per("emitted"), per("converted"))
     bulk_s, emit_s = f64["bulk_ms"] * 1e-3, f64["emit_ms"] * 1e-3
@@ -428,7 +522,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": f64["wall"] / K * 1e3,
+        "ms_per_step": f64["device_s"] / K * 1e3,
         "p50_step_ms": float(np.percentile(f64["step_ms"], 50)),
         "p99_step_ms": float(np.percentile(f64["step_ms"], 99)),
         "higher_is_better": True,
@@ -443,23 +537,40 @@ def main():
         "converted_per_step": per("converted"),
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": measured_traffic(),
-                     "kernel": "bulk_kernel<false, false, false, false, false> (streaming pass)",
+                     "kernel": "bulk_kernel<false, false, false, false, false> (the streaming "
+                               "kernel alone; the whole step is step_roofline)",
                      "kernel_ms": f64["bulk_ms"], "algorithmic_bytes_per_launch": bulk_bytes},
-        "emitter_pass": {"kernels": "scan_kernel + emit_kernel<false, false, false>",
+        "emitter_pass": {"kernels": "scan_kernel + emit_kernel<false, false, false> + "
+                                    "defer_kernel (returns at once when nothing was deferred)",
                          "ms": f64["emit_ms"], "algorithmic_bytes_per_launch": emit_bytes,
                          "achieved_GB_per_s": emit_bytes / emit_s / 1e9},
         "launch_shape": f64["shape"],
+        # the whole step (streaming kernel, scan, emitter pass) against the HBM peak: with the
+        # kernels' algorithmic bytes, and with the scope table's per-update yardstick
         "step_roofline_frac": (bulk_bytes + emit_bytes) / (float(np.mean(f64["step_ms"])) * 1e-3)
                               / HBM_PEAK,
+        "step_roofline": {"bytes_per_step": survey_step_bytes(per("processed"), per("emitted"),
+                                                              per("converted")),
+                          "frac": survey_step_bytes(per("processed"), per("emitted"),
+                                                    per("converted"))
+                                  / (f64["device_s"] / K) / HBM_PEAK,
+                          "counting": "96 B per particle update + 80 B per emission + 104 B per "
+                                      "conversion"},
+        "timing": "each step's kernels between the library's timing-only HIP events on the "
+                  "step's stream; before every timed step the particle state is put back by an "
+                  "untimed device copy (and a 512 MiB copy evicts it from the caches), so each "
+                  "repeat steps the same ensemble",
+        "wall_ms_per_step_incl_reset": f64["wall"] / K * 1e3,
+        "emitter_queue_bytes": f64["queue_bytes"],
     }
     if mixed is not None:
         cm = mixed["counters"]
         pm = lambda k: cm[k] / K
-        bb = stream_kernel_bytes(mixed["n_total"], pm("processed"), pm("emitted"), pm("converted"))
-        out["mixed"] = {"value": cm["processed"] / mixed["wall"], "unit": "particle-updates/s",
+        bb = stream_kernel_bytes(mixed["n_flags"], pm("processed"), pm("emitted"), pm("converted"))
+        out["mixed"] = {"value": cm["processed"] / mixed["device_s"], "unit": "particle-updates/s",
                         "dtype": "f32 (f64 chi, optical depth and tails)",
                         "workload": "plane-wave skewed chi log-uniform [1e-4, 1e3], 2^24 + 2^24",
-                        "ms_per_step": mixed["wall"] / K * 1e3,
+                        "ms_per_step": mixed["device_s"] / K * 1e3,
                         "p50_step_ms": float(np.percentile(mixed["step_ms"], 50)),
                         "p99_step_ms": float(np.percentile(mixed["step_ms"], 99)),
                         "bulk_kernel_ms": mixed["bulk_ms"], "emitter_pass_ms": mixed["emit_ms"],
@@ -470,36 +581,39 @@ def main():
     if mixed_same is not None:
         cs_ = mixed_same["counters"]
         ps_ = lambda k: cs_[k] / K
-        bs_ = stream_kernel_bytes(mixed_same["n_total"], ps_("processed"), ps_("emitted"),
+        bs_ = stream_kernel_bytes(mixed_same["n_flags"], ps_("processed"), ps_("emitted"),
                                   ps_("converted"))
         out["mixed_headline_workload"] = {
-            "value": cs_["processed"] / mixed_same["wall"], "unit": "particle-updates/s",
+            "value": cs_["processed"] / mixed_same["device_s"], "unit": "particle-updates/s",
             "dtype": "f32 (f64 chi, optical depth and tails)",
             "workload": "the headline workload (plane wave, 2^24 + 2^24) in the MIXED form",
-            "ms_per_step": mixed_same["wall"] / K * 1e3,
+            "ms_per_step": mixed_same["device_s"] / K * 1e3,
             "p50_step_ms": float(np.percentile(mixed_same["step_ms"], 50)),
             "p99_step_ms": float(np.percentile(mixed_same["step_ms"], 99)),
             "bulk_kernel_ms": mixed_same["bulk_ms"], "emitter_pass_ms": mixed_same["emit_ms"],
             "bulk_roofline_frac": bs_ / (mixed_same["bulk_ms"] * 1e-3) / HBM_PEAK,
-            "speedup_over_fp64": (cs_["processed"] / mixed_same["wall"]) / value,
+            "speedup_over_fp64": (cs_["processed"] / mixed_same["device_s"]) / value,
             "emitted_per_step": ps_("emitted"), "converted_per_step": ps_("converted")}
     if batched is not None:
         cb = batched["counters"]
         pb = lambda k: cb[k] / K
-        sb = stream_kernel_bytes(batched["n_total"], pb("processed"), pb("emitted"),
+        sb = stream_kernel_bytes(batched["n_flags"], pb("processed"), pb("emitted"),
                                  pb("converted")) + emit_kernel_bytes(pb("emitted"),
                                                                       pb("converted"))
-        out["batched"] = {"value": cb["processed"] / batched["wall"], "unit": "particle-updates/s",
+        out["batched"] = {"value": cb["processed"] / batched["device_s"], "unit": "particle-updates/s",
                           "dtype": "f32 (f64 chi, optical depth and tails)",
                           "workload": f"64 uneven tiles, {batched['n_total']} particles, "
                                       "e-/e+/photon, static B, chi log-uniform [1e-3, 1e2]",
-                          "ms_per_step": batched["wall"] / K * 1e3,
+                          "ms_per_step": batched["device_s"] / K * 1e3,
                           "p50_step_ms": float(np.percentile(batched["step_ms"], 50)),
                           "p99_step_ms": float(np.percentile(batched["step_ms"], 99)),
                           "launch_shape": batched["tuned"]["shape"],
                           "autotune_ms": batched["tuned"].get("timings"),
                           "step_roofline_frac": sb / (float(np.mean(batched["step_ms"])) * 1e-3)
                                                 / HBM_PEAK,
+                          "bulk_kernel_ms": batched["bulk_ms"],
+                          "emitter_pass_ms": batched["emit_ms"],
+                          "split_from": "plan launches with the library's timing events",
                           "emitted_per_step": pb("emitted"),
                           "converted_per_step": pb("converted")}
     if served is not None:
@@ -521,13 +635,13 @@ def main():
     if fused is not None:
         cf = fused["counters"]
         pf = lambda k: cf[k] / K
-        fb = pushed_stream_kernel_bytes(fused["n_total"], pf("processed"), pf("emitted"),
+        fb = pushed_stream_kernel_bytes(fused["n_flags"], pf("processed"), pf("emitted"),
                                         pf("converted"), fused["n_total"] // 2)
-        out["fused_push"] = {"value": cf["processed"] / fused["wall"],
+        out["fused_push"] = {"value": cf["processed"] / fused["device_s"],
                              "unit": "particle-updates/s", "dtype": "f64",
                              "workload": "the headline workload, electrons pushed (Boris) "
                                          "through their fields inside the streaming kernel",
-                             "ms_per_step": fused["wall"] / K * 1e3,
+                             "ms_per_step": fused["device_s"] / K * 1e3,
                              "p50_step_ms": float(np.percentile(fused["step_ms"], 50)),
                              "p99_step_ms": float(np.percentile(fused["step_ms"], 99)),
                              "bulk_kernel_ms": fused["bulk_ms"],
@@ -540,13 +654,13 @@ def main():
     if wave is not None:
         cw = wave["counters"]
         pw = lambda k: cw[k] / K
-        wb = wave_stream_kernel_bytes(wave["n_total"], pw("processed"), pw("emitted"),
+        wb = wave_stream_kernel_bytes(wave["n_flags"], pw("processed"), pw("emitted"),
                                       pw("converted"))
         out["plane_wave_fields"] = {
-            "value": cw["processed"] / wave["wall"], "unit": "particle-updates/s", "dtype": "f64",
+            "value": cw["processed"] / wave["device_s"], "unit": "particle-updates/s", "dtype": "f64",
             "workload": "the headline workload with its fields given as the plane wave they come "
                         "from (per-particle amplitude and phase, E and B computed in the kernel)",
-            "ms_per_step": wave["wall"] / K * 1e3,
+            "ms_per_step": wave["device_s"] / K * 1e3,
             "p50_step_ms": float(np.percentile(wave["step_ms"], 50)),
             "p99_step_ms": float(np.percentile(wave["step_ms"], 99)),
             "bulk_kernel_ms": wave["bulk_ms"], "emitter_pass_ms": wave["emit_ms"],
@@ -554,6 +668,22 @@ def main():
             "bulk_roofline_frac": wb / (wave["bulk_ms"] * 1e-3) / HBM_PEAK,
             "launch_shape": wave["shape"],
             "emitted_per_step": pw("emitted"), "converted_per_step": pw("converted")}
+    if dial:
+        from paper_2301_07684_amd import autotune
+
+        errs = autotune.form_errors()
+        out["dial"] = {"reported_error_bounds": {
+            autotune.FORM_NAMES[k]: {"rate": v["rate"], "sample": v["sample"]}
+            for k, v in errs.items()}, "forms": {}}
+        for name, r in dial.items():
+            cd = r["counters"]
+            out["dial"]["forms"][name] = {
+                "value": cd["processed"] / r["device_s"], "unit": "particle-updates/s",
+                "workload": "the headline workload (plane wave, 2^24 + 2^24)",
+                "ms_per_step": r["device_s"] / K * 1e3,
+                "bulk_kernel_ms": r["bulk_ms"], "emitter_pass_ms": r["emit_ms"],
+                "launch_shape": r["shape"], "speedup_over_fp64": (cd["processed"] / r["device_s"])
+                                                                 / value}
     if const is not None:
         cc = const["counters"]
         kb = constant_field_kernel_bytes(cc["processed"] / const["K"], cc["emitted"] / const["K"])

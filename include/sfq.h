@@ -68,6 +68,14 @@ typedef enum { SFQ_OPTICAL_DEPTH = 0, SFQ_LOCAL = 1 } sfq_decision;
  * the field traffic is that of a_i and phi_i (16 B per particle instead of 48). */
 typedef enum { SFQ_FIELDS_ARRAYS = 0, SFQ_FIELDS_UNIFORM = 1, SFQ_FIELDS_PLANE_WAVE = 2 } sfq_field_mode;
 
+/* Evaluation form of the approximation tables (sfq_config.approx), the accuracy/speed dial in
+ * the spirit of the paper's choice of coefficient counts (Sec. 4.5): FULL evaluates all 16
+ * Chebyshev terms of each rate segment and all 8 x 8 coefficients of each inverse-CDF patch;
+ * TRUNCATED only the leading 10 terms and 5 x 5 coefficients of the same tables (less work,
+ * less accuracy).  The table generator measures each form's error (its report, data/
+ * sfq_tables_report.json, "forms"). */
+typedef enum { SFQ_APPROX_FULL = 0, SFQ_APPROX_TRUNCATED = 1 } sfq_approx;
+
 /* Philox draw purposes (counter word 3).  See sfq_philox. */
 enum { SFQ_P_INIT = 0, SFQ_P_EMIT = 1, SFQ_P_CHILD = 2, SFQ_P_CHILD2 = 3, SFQ_P_LOCAL = 4 };
 
@@ -82,7 +90,7 @@ typedef struct {
                                 requires decision == SFQ_LOCAL (Sec. 2, App. A)                   */
     int32_t bw_fast;         /* 1: pair rate is zero for chi < 0.3 (App. A function 7)           */
     int32_t device;          /* HIP device ordinal the handle's tables live on                   */
-    int32_t reserved;        /* must be 0                                                          */
+    int32_t approx;          /* sfq_approx: full or truncated evaluation of the tables           */
     const char* tables_path; /* approximation table file; NULL = data/sfq_tables.bin next to
                                 the shared library                                                */
 } sfq_config;
@@ -206,7 +214,9 @@ typedef struct {
     unsigned long long out_of_domain;   /* chi above the tables (2^16): asymptotic forms used    */
     unsigned long long clamped;         /* leptons left with gamma <= 1 and put at rest          */
     unsigned long long overflow;        /* products that did not fit their buffer                */
-    unsigned long long reserved;
+    unsigned long long deferred;        /* particles whose step the deferred-share pass did (the
+                                           emitter queue was too small for their share of a
+                                           chunk; results are the same, only slower)            */
 } sfq_counters;
 
 /* Product buffers and their append counters, one set per owner (e.g. per simulation when one
@@ -302,11 +312,31 @@ sfq_status sfq_plan_replay(sfq_plan p, void* stream);
 /* ------------------------------------------------------------------------------------------ */
 /* Scratch sizing and kernel timing                                                            */
 /* ------------------------------------------------------------------------------------------ */
-/* Pre-sizes the handle's emitter queue (device scratch owned by the handle) for sfq_step calls
- * of up to `max_particles` particles in up to `max_tiles` tiles with the current launch shape,
- * so that such calls allocate nothing.  A larger step, or one after a change of launch shape,
- * still grows the queue, which waits for the device.  SFQ_E_NOMEM if the allocation fails. */
+/* The emitter queue (device scratch owned by the handle) holds the particles that emit in a
+ * step between the streaming pass and the emitter pass.  Each wave of the streaming pass owns a
+ * slice of it, sized for the expected emitters, not for the worst case: a wave whose slice could
+ * not take every particle of its next share of a chunk (chunk / 4 particles) leaves that share
+ * untouched, and a further kernel of the same step steps it afterwards with the same arithmetic.
+ * So the queue size never changes results, only speed (sfq_counters.deferred counts the
+ * particles of such shares).  A slice holds one share plus `2 * expected_fraction` of the
+ * particles of the wave's shares (at most all of them, which makes deferral impossible).
+ *
+ * Pre-sizes the queue for sfq_step calls of up to `max_particles` particles in up to
+ * `max_tiles` tiles with the current launch shape and queue fraction, so that such calls
+ * allocate nothing.  A larger step, one after a change of launch shape, or one after the queue
+ * fraction grew still grows the queue, which waits for the device.  SFQ_E_NOMEM if the
+ * allocation fails. */
 sfq_status sfq_reserve(sfq_handle h, uint64_t max_particles, int max_tiles);
+
+/* Sizing of the emitter queue: `expected_fraction` in [0, 1] is the fraction of a step's
+ * particles expected to emit (the slices hold twice that, plus one share; the default is 1/16,
+ * adaptive); with adaptive = 1 the library raises it to twice the largest emitter fraction of
+ * a wave's shares that the completed steps report (faster after deferrals), with adaptive = 0
+ * it stays.  Takes effect from the next sfq_step, sfq_reserve or sfq_plan_create. */
+sfq_status sfq_set_queue(sfq_handle h, double expected_fraction, int adaptive);
+
+/* Bytes of device memory the handle's emitter queue holds now (0 before the first step). */
+sfq_status sfq_queue_bytes(sfq_handle h, uint64_t* bytes);
 
 /* Kernel timing (instrumentation).  With enable = 1, every sfq_step and sfq_plan_launch on this
  * handle records HIP events on its stream before the streaming kernel, between it and the

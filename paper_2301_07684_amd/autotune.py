@@ -143,13 +143,38 @@ def tune(handle: sfq.Handle, tiles: Sequence[sfq.TileArrays], products: sfq.Prod
 # ------------------------------------------------------------------------------------------------
 # Accuracy/speed dial
 # ------------------------------------------------------------------------------------------------
-# Relative error bound of each arithmetic form, per quantity: the bars its parity tests hold it
-# to (rates against the quadrature of Eqs. (wtilde), (wtilde_pair); sampled energy fractions
-# against the exact inversion of Eqs. (again), (again_pp)).
-FORM_ERRORS = {
-    sfq.FP64: {"rate": 1e-12, "sample": 1e-9},
-    sfq.MIXED: {"rate": 2e-5, "sample": 2e-5},
-}
+FORM_NAMES = {(sfq.FP64, sfq.APPROX_FULL): "fp64", (sfq.FP64, sfq.APPROX_TRUNCATED): "fp64_trunc",
+              (sfq.MIXED, sfq.APPROX_FULL): "mixed", (sfq.MIXED, sfq.APPROX_TRUNCATED): "mixed_trunc"}
+# rounding of the kernels' own arithmetic after the table evaluation (products, powers, the
+# energy fractions), per form: a few units in the last place of the evaluation precision
+_FINAL_ULPS = {sfq.FP64: 8 * 2.0 ** -53, sfq.MIXED: 8 * 2.0 ** -24}
+
+
+def tables_report_path() -> str:
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "sfq_tables_report.json")
+
+
+def form_errors(report_path: str | None = None) -> Dict[Tuple[int, int], Dict[str, float]]:
+    """Relative error bound of each arithmetic form (precision x table evaluation), from the
+    table generator's measured report for the tables the library loads: twice the largest
+    error it measured on its check points for the rates (against the quadrature of Eqs. (wtilde),
+    (wtilde_pair)) and for the samples (against the exact inversion of Eqs. (again),
+    (again_pp)), plus the rounding of the kernels' final arithmetic."""
+    with open(report_path or tables_report_path()) as f:
+        forms = json.load(f)["forms"]
+    out = {}
+    for (prec, approx), name in FORM_NAMES.items():
+        m = forms[name]
+        a = _FINAL_ULPS[prec]
+        out[(prec, approx)] = {"rate": 2.0 * m["rate"] + a, "sample": 2.0 * m["sample"] + a,
+                               # per process: photon emission by leptons, pair creation by photons
+                               "emission_rate": 2.0 * m["photon_rate"] + a,
+                               "pair_rate": 2.0 * m["pair_rate"] + a,
+                               "measured_rate": m["rate"], "measured_sample": m["sample"],
+                               "rate_terms": m["rate_terms"], "patch_terms": m["patch_terms"]}
+    return out
+
+
 # bw_fast (App. A function 7) is not a relative error: pair creation is dropped below chi = 0.3,
 # where the pair rate is below 9.1e-6 alpha lambda_r / (lambda_C gamma) (Sec. 4.2).
 BW_FAST_BOUND = "pair creation dropped for chi < 0.3, where W_pair < 9.1e-6 alpha lambda_r/(lambda_C gamma)"
@@ -161,40 +186,43 @@ def select_form(handle_kwargs: Dict, tiles: Sequence[sfq.TileArrays],
                 candidates: Sequence[Tuple[int, int]] = DEFAULT_CANDIDATES,
                 repeats: int = 4, push: bool = False) -> Dict:
     """The accuracy/speed dial (the analogue of the paper's choice of coefficient counts, Sec. 4.5,
-    and of its _fast pair functions, App. A functions 7 and 11): times every arithmetic form
-    whose error bound is within `max_rel_error` (FP64 always; MIXED from 2e-5; each also with
-    bw_fast when `allow_bw_fast`), each at its own best launch shape, on the caller's tiles, and
-    returns the fastest as {'handle', 'precision', 'bw_fast', 'shape', 'ms', 'error_bound',
-    'timings'}.  The other handles are closed; the particle state, product counts and counters
-    are restored.  handle_kwargs are the sfq.Handle arguments other than precision and bw_fast
-    (units, dt, decision, blcfa, device); `push` times the steps with the leptons' push."""
-    forms = [p for p in (sfq.FP64, sfq.MIXED)
-             if max(FORM_ERRORS[p].values()) <= max_rel_error]
+    and of its _fast pair functions, App. A functions 7 and 11): times every arithmetic form --
+    FP64 or MIXED, with the full or the truncated tables -- whose measured error bound
+    (form_errors) is within `max_rel_error`, each also with bw_fast when `allow_bw_fast`, each at
+    its own best launch shape, on the caller's tiles, and returns the fastest as {'handle',
+    'precision', 'approx', 'bw_fast', 'name', 'shape', 'ms', 'error_bound', 'timings'}.  The
+    other handles are closed; the particle state, products and counters are restored.
+    handle_kwargs are the sfq.Handle arguments other than precision, approx and bw_fast (units,
+    dt, decision, blcfa, device); `push` times the steps with the leptons' push."""
+    errors = form_errors()
+    forms = [f for f in FORM_NAMES if max(errors[f]["rate"], errors[f]["sample"]) <= max_rel_error]
     if not forms:
+        best = errors[(sfq.FP64, sfq.APPROX_FULL)]
         raise ValueError(f"no form meets a relative error of {max_rel_error:g} "
-                         f"(FP64: {max(FORM_ERRORS[sfq.FP64].values()):g})")
+                         f"(FP64: {max(best['rate'], best['sample']):g})")
     fast = (False, True) if allow_bw_fast else (False,)
     snap = _snapshot(tiles)
     timings, best, handles = {}, None, []
     try:
-        for prec in forms:
+        for prec, approx in forms:
             for bw in fast:
-                h = sfq.Handle(**handle_kwargs, precision=prec, bw_fast=bw)
+                h = sfq.Handle(**handle_kwargs, precision=prec, approx=approx, bw_fast=bw)
                 handles.append(h)
                 r = tune(h, tiles, products, counters, seed=seed, step=step,
                          candidates=candidates, repeats=repeats, cache_path=None, push=push)
                 _restore(tiles, snap)
-                name = ("fp64" if prec == sfq.FP64 else "mixed") + ("+bw_fast" if bw else "")
+                name = FORM_NAMES[(prec, approx)] + ("+bw_fast" if bw else "")
                 timings[name] = r["ms"]
                 if best is None or r["ms"] < best["ms"]:
-                    best = dict(handle=h, precision=prec, bw_fast=bw, shape=r["shape"],
-                                ms=r["ms"], name=name)
+                    best = dict(handle=h, precision=prec, approx=approx, bw_fast=bw,
+                                shape=r["shape"], ms=r["ms"], name=name)
     finally:
         for h in handles:
             if best is None or h is not best["handle"]:
                 h.close()
     torch.cuda.synchronize()
-    bound = dict(FORM_ERRORS[best["precision"]])
+    e = errors[(best["precision"], best["approx"])]
+    bound = {"rate": e["rate"], "sample": e["sample"]}
     if best["bw_fast"]:
         bound["bw_fast"] = BW_FAST_BOUND
     best.update(error_bound=bound, timings=timings)

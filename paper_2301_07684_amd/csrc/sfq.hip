@@ -43,6 +43,7 @@ using namespace sfq;
 struct Tables {
     const double *rad, *pair, *ka, *kb, *phinv, *ppinv;
     const float *rad32, *pair32, *phinv32, *ppinv32;
+    int trunc;           // evaluate the truncated form of the inverse patches (sfq_config.approx)
 };
 
 struct Physics {
@@ -50,6 +51,7 @@ struct Physics {
     double lc_over_lr;   // lambda_C/lambda_r: chi = gamma lc |...|, tau_C in units of 1/omega_r
     double k_rate;       // alpha/(sqrt3 pi) lambda_r/lambda_C
     double chi_min_pair; // 0.01, or 0.3 with bw_fast
+    int trunc;           // evaluate the truncated form of the rate segments (sfq_config.approx)
 };
 
 struct StepArgs {
@@ -65,8 +67,9 @@ struct StepArgs {
     uint32_t step;
     const unsigned long long* step_ptr;  // if set, the step index is read from device memory
     uint64_t seed;
-    // emitter queue (SoA).  Block b owns entries [b cap, (b+1) cap): leptons from the start of
-    // the slice upwards, photons from its end downwards.
+    // emitter queue (SoA).  Wave w of streaming block b owns the slice s = STEP_WAVES b + w,
+    // entries [s cap, (s+1) cap): leptons from the start of the slice upwards, photons from its
+    // end downwards.
     uint32_t* q_idx;
     uint32_t* q_tile;
     double* q_chi;
@@ -77,12 +80,21 @@ struct StepArgs {
     uint64_t* q_uid;
     double* q_aux;              // beyond-LCFA tau/tau_C for the threshold (negative: LCFA)
     double* q_aux2;             // beyond-LCFA: gamma of the pushed momentum minus gamma^{(n)}
-    uint32_t* q_count;          // [2 grid]: lepton and photon emitters queued by each block
+    uint32_t* q_count;          // [2 slices]: lepton and photon emitters queued in each slice
     unsigned long long* q_proc; // [grid]: particles processed by each block of the streaming pass
-    unsigned long long* q_base; // [3 grid]: first product slot of each block (photons, e-, e+)
-    uint64_t q_cap_per_block;
-    int grid;                   // blocks of the streaming kernel (= queue slices)
-    int emit_split;             // emitter blocks per queue slice
+    unsigned long long* q_base; // [3 slices]: first product slot of each slice (photons, e-, e+)
+    uint64_t q_cap_per_wave;    // entries of one slice
+    // Shares that did not fit: a wave whose slice could not take every particle of its share of
+    // a chunk (STEP_BLOCK/64 waves share a chunk) leaves that share untouched and appends
+    // chunk * STEP_WAVES + wave here; the emitter kernel steps those shares afterwards.
+    uint32_t* d_list;
+    unsigned* d_ctl;            // [4]: shares deferred, next share to step, emitter blocks done
+    unsigned* obs;              // nullable, host-mapped: [0] the largest emitter fraction of a
+                                // wave's share (float bits), [1] shares deferred (for sizing)
+    int grid;                   // blocks of the streaming kernel (STEP_WAVES slices each)
+    int emit_split;             // emitter blocks per streaming block's slices
+    int may_defer;              // the slices are smaller than the step's worst case (host side:
+                                // the deferred-share kernel is enqueued)
     sfq_products prod[3];       // photons, electrons, positrons
     unsigned long long* prod_counts;
     sfq_counters* counters;
@@ -95,7 +107,7 @@ struct StepArgs {
 };
 
 enum { CNT_PROCESSED, CNT_EMITTED, CNT_CONVERTED, CNT_REJECTED, CNT_OOD, CNT_CLAMPED, CNT_OVERFLOW,
-       CNT_N };
+       CNT_DEFERRED, CNT_N };
 
 // =============================================================================================
 // Device helpers shared by the step and the batched calls
@@ -106,10 +118,10 @@ __device__ __forceinline__ double rate_lepton(const void* rad, const Physics& ph
 {
     if (!(chi > 0.0) || !(gamma > 0.0)) return 0.0;
     if (MIXED) {
-        const float wt = wtilde_rad((const float*)rad, (float)chi, ood);
+        const float wt = wtilde_rad((const float*)rad, (float)chi, ood, ph.trunc != 0);
         return (double)((float)ph.k_rate * (float)chi / (float)gamma * wt);
     }
-    const double wt = wtilde_rad((const double*)rad, chi, ood);
+    const double wt = wtilde_rad((const double*)rad, chi, ood, ph.trunc != 0);
     return ph.k_rate * chi * rcp_nr(gamma) * wt;
 }
 
@@ -119,10 +131,10 @@ __device__ __forceinline__ double rate_photon(const void* pair, const Physics& p
 {
     if (!(chi >= ph.chi_min_pair) || !(gamma > 0.0)) return 0.0;
     if (MIXED) {
-        const float wt = wtilde_pair((const float*)pair, (float)chi, ood);
+        const float wt = wtilde_pair((const float*)pair, (float)chi, ood, ph.trunc != 0);
         return (double)((float)ph.k_rate / (float)gamma * wt);
     }
-    const double wt = wtilde_pair((const double*)pair, chi, ood);
+    const double wt = wtilde_pair((const double*)pair, chi, ood, ph.trunc != 0);
     return ph.k_rate * rcp_nr(gamma) * wt;
 }
 
@@ -147,7 +159,8 @@ __device__ __forceinline__ void sample_coop(const Tables& tb, bool valid, bool p
     const int patch = q.patch + (pair ? N_INV_CHI * N_R_SEG : 0);  // pair patches follow
     bool need64 = true;
     if (MIXED) {
-        const float f = coop_patch_eval<float>(tb.phinv32, patch, (float)q.Xr, (float)q.Xc, valid);
+        const float f = coop_patch_eval<float>(tb.phinv32, patch, (float)q.Xr, (float)q.Xc, valid,
+                                               tb.trunc != 0);
         const float uf = (float)u;
         if (!pair) {
             const float xbar = q.upper ? expf(f) : (f * uf) * (f * uf) * (f * uf);
@@ -167,7 +180,7 @@ __device__ __forceinline__ void sample_coop(const Tables& tb, bool valid, bool p
         if (__ballot(need64) == 0) return;
     }
     need64 = need64 && valid;
-    const double f = coop_patch_eval<double>(tb.phinv, patch, q.Xr, q.Xc, need64);
+    const double f = coop_patch_eval<double>(tb.phinv, patch, q.Xr, q.Xc, need64, tb.trunc != 0);
     if (!need64) return;
     if (!pair) {
         const double w = f * u;
@@ -435,27 +448,289 @@ __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
         atomicAdd(&global->processed + threadIdx.x, s_cnt[threadIdx.x]);
 }
 
-// Streaming pass: per alive particle gamma, chi (or the beyond-LCFA force update), the rate
-// from LDS-staged tables and the decision; emitters go to the block's queue slice through a
-// wave ballot + popcount prefix and one LDS atomic per wave.
+// =============================================================================================
+// Emitter work of one lane (wave-cooperative: every lane of the wave calls it; lanes with
+// valid == false pass through): Philox draws, the energy sample, recoil written in place and
+// the products.  Product slots come from the scan (k_ph, k_el, k_po: this lane's slots), or,
+// with atomic_slots (and always for beyond-LCFA photons and per-set products), from one atomic
+// per wave and buffer.
+// =============================================================================================
+struct EmitCounts {
+    unsigned long long emit = 0, conv = 0, rej = 0, clamp = 0, over = 0, ood = 0;
+};
+
+template <bool MIXED, bool BLCFA, bool LOCAL>
+__device__ __forceinline__ void emit_one(const StepArgs& A, bool valid, bool pair, uint32_t i,
+                                         int t, double chi, double gamma, double px, double py,
+                                         double pz, uint64_t quid, double tau_ratio,
+                                         double dgamma_push, uint32_t base_step,
+                                         bool atomic_slots, unsigned long long k_ph,
+                                         unsigned long long k_el, unsigned long long k_po,
+                                         EmitCounts& C)
+{
+    static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
+    const bool multi = A.nsets > 0;
+    bool want_ph = false, want_pair = false;
+    double pgx = 0, pgy = 0, pgz = 0, tau_a = 0, pbx = 0, pby = 0, pbz = 0, tau_b = 0;
+    uint64_t uid_a = 0, uid_b = 0, parent = 0;
+    pair = valid && pair;
+    uint64_t uid = 0;
+    uint32_t step = base_step;
+    int pset = 0;
+    double r = 0.5;
+    if (!valid) { chi = 1.0; gamma = 1.0; px = py = pz = 0.0; }
+    Draw d1{0, 0}, d2{0, 0};
+    if (valid) {
+        // with optical-depth decisions the streaming pass did not read the id
+        uid = LOCAL ? quid : A.tiles[t].uid[i];
+        step = base_step + (uint32_t)A.tiles[t].step_offset;
+        d1 = philox_draw(A.seed, uid, step, SFQ_P_EMIT);
+        d2 = philox_draw(A.seed, uid, step, SFQ_P_CHILD);
+        r = uniform53(d1.a);
+    }
+    double s = 0.0, v = 0.0, omv = 1.0;
+    bool ood = false;
+    sample_coop<MIXED>(A.tb, valid, pair, chi, r, s, v, omv, ood);
+    if (valid) {
+        const sfq_tile& T = A.tiles[t];
+        if (multi) pset = T.product_set;
+        parent = uid;
+        const double pn = sqrt(fma(px, px, fma(py, py, pz * pz)));
+        if (!pair) {
+            const double gph = gamma * (s / (1.0 + s));
+            bool accept = true, none = false;
+            double gem = gamma / (1.0 + s);
+            if (BLCFA) {
+                // the threshold gamma_{gamma,LCFA} (Eq. gammaLCFA) from the queued tau/tau_C
+                double limit = 0.0;
+                if (tau_ratio >= 0.0) {
+                    const double arg = chi / (8.0 * gamma) * tau_ratio;
+                    limit = 0.7 * gamma /
+                            (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
+                }
+                // no emission at all when the threshold reaches 0.75 gamma (Sec. 5; it
+                // cannot for finite input, as the threshold is at most 0.7 gamma)
+                none = !(limit < 0.75 * gamma);
+                if (none) {
+                    accept = false;
+                } else if (!(gph > limit)) {  // Eq. (rej_cond)
+                    const Draw dl = philox_draw(A.seed, uid, step, SFQ_P_LOCAL);
+                    const double r2 = uniform53(dl.b);
+                    const double lp_s = log_photon_pdf(A.tb.ka, A.tb.kb, gph, gamma, chi);
+                    const double lp_l = log_photon_pdf(A.tb.ka, A.tb.kb, limit, gamma, chi);
+                    accept = log(r2) + lp_s <= lp_l;
+                }
+                // the pushed momentum recoils by the photon energy
+                gem += dgamma_push;
+            }
+            if (accept) {
+                bool cl;
+                const double f = lepton_momentum_factor(gem, pn, cl);
+                C.clamp += cl ? 1 : 0;
+                T.px[i] = px * f; T.py[i] = py * f; T.pz[i] = pz * f;
+                if (A.decision == SFQ_OPTICAL_DEPTH) T.tau[i] = optical_depth(d1.b);
+                const double fg = pn > 0.0 ? gph / pn : 0.0;
+                pgx = px * fg; pgy = py * fg; pgz = pz * fg;
+                tau_a = optical_depth(d2.a);
+                uid_a = d2.b;
+                want_ph = true;
+                ++C.emit;
+            } else {
+                // rejected: the lepton keeps the pushed momentum, which the streaming pass
+                // has already written to the tile with the fused push
+                if (!none) ++C.rej;
+            }
+        } else {
+            const Draw d3 = philox_draw(A.seed, uid, step, SFQ_P_CHILD2);
+            double ge, gp;
+            pair_energies(gamma, r, v, omv, ge, gp);
+            bool c1, c2;
+            const double fe = lepton_momentum_factor(ge, pn, c1);
+            const double fp = lepton_momentum_factor(gp, pn, c2);
+            C.clamp += (c1 ? 1 : 0) + (c2 ? 1 : 0);
+            pgx = px * fe; pgy = py * fe; pgz = pz * fe;   // electron
+            pbx = px * fp; pby = py * fp; pbz = pz * fp;   // positron
+            tau_a = optical_depth(d1.b);
+            uid_a = d2.b;
+            tau_b = optical_depth(d2.a);
+            uid_b = d3.a;
+            if (T.alive) T.alive[i] = 0;
+            want_pair = true;
+            ++C.conv;
+        }
+        C.ood += ood ? 1 : 0;
+    }
+    {
+        unsigned long long k;
+        if (multi) k = keyed_reserve(A.sets, 0, pset, want_ph);
+        else k = (BLCFA || atomic_slots) ? wave_reserve(&A.prod_counts[0], want_ph) : k_ph;
+        if (want_ph) {
+            const sfq_products P = multi ? A.sets[pset].photons : A.prod[0];
+            if (k < P.capacity) {
+                P.px[k] = pgx; P.py[k] = pgy; P.pz[k] = pgz; P.tau[k] = tau_a;
+                P.uid[k] = uid_a; P.parent[k] = parent;
+            } else {
+                ++C.over;
+            }
+        }
+    }
+    unsigned long long ke = k_el, kp = k_po;
+    if (multi) {
+        ke = keyed_reserve(A.sets, 1, pset, want_pair);
+        kp = keyed_reserve(A.sets, 2, pset, want_pair);
+    } else if (atomic_slots) {
+        ke = wave_reserve(&A.prod_counts[1], want_pair);
+        kp = wave_reserve(&A.prod_counts[2], want_pair);
+    }
+    if (want_pair) {
+        const sfq_products E = multi ? A.sets[pset].electrons : A.prod[1];
+        if (ke < E.capacity) {
+            E.px[ke] = pgx; E.py[ke] = pgy; E.pz[ke] = pgz; E.tau[ke] = tau_a;
+            E.uid[ke] = uid_a; E.parent[ke] = parent;
+        } else {
+            ++C.over;
+        }
+        const sfq_products P = multi ? A.sets[pset].positrons : A.prod[2];
+        if (kp < P.capacity) {
+            P.px[kp] = pbx; P.py[kp] = pby; P.pz[kp] = pbz; P.tau[kp] = tau_b;
+            P.uid[kp] = uid_b; P.parent[kp] = parent;
+        } else {
+            ++C.over;
+        }
+    }
+}
+
+// =============================================================================================
+// Where the streaming pass puts the emitters it finds
+// =============================================================================================
+// One lane's emitter: what the emitter work needs (the uid only with local decisions, the two
+// beyond-LCFA values only for beyond-LCFA leptons).
+struct EmitRec {
+    uint32_t i;
+    double chi, gamma, px, py, pz;
+    uint64_t uid;
+    double aux, aux2;
+};
+
+__device__ __forceinline__ unsigned long long lanes_below() { return (1ull << lane_id()) - 1ull; }
+
+// The streaming kernel's sink: the wave's own slice of the emitter queue, its counts in scalar
+// registers (wave-uniform; no atomics).  The caller makes sure, before each chunk, that the
+// slice can take every particle of the wave's share of it.
+struct QueueSink {
+    uint64_t base;   // first entry of the wave's slice
+    uint32_t nl, np; // leptons and photons queued so far
+
+    __device__ __forceinline__ void write(const StepArgs& A, uint64_t slot, int t,
+                                          const EmitRec& e, bool local, bool aux) const
+    {
+        A.q_idx[slot] = e.i;
+        A.q_tile[slot] = (uint32_t)t;
+        A.q_chi[slot] = e.chi;
+        A.q_gamma[slot] = e.gamma;
+        A.q_px[slot] = e.px;
+        A.q_py[slot] = e.py;
+        A.q_pz[slot] = e.pz;
+        if (local) A.q_uid[slot] = e.uid;
+        if (aux) {
+            A.q_aux[slot] = e.aux;
+            A.q_aux2[slot] = e.aux2;
+        }
+    }
+
+    template <bool LOCAL>
+    __device__ __forceinline__ void put(const StepArgs& A, bool emit, bool photon, bool aux,
+                                        int t, const EmitRec& e)
+    {
+        const unsigned long long mask = __ballot(emit);
+        if (!mask) return;
+        const unsigned first = photon ? np : nl;
+        if (emit) {
+            const unsigned rank = first + (unsigned)__popcll(mask & lanes_below());
+            const uint64_t slot = photon ? base + A.q_cap_per_wave - 1 - rank : base + rank;
+            write(A, slot, t, e, LOCAL, aux);
+        }
+        if (photon) np += (unsigned)__popcll(mask); else nl += (unsigned)__popcll(mask);
+    }
+
+    // two particles per lane (lane l holds particles 2l, 2l + 1), queued in index order
+    __device__ __forceinline__ void put2(const StepArgs& A, const bool (&em)[2], bool photon,
+                                         int t, const EmitRec (&e)[2])
+    {
+        const unsigned long long m0 = __ballot(em[0]), m1 = __ballot(em[1]);
+        if (!(m0 | m1)) return;
+        const unsigned long long below = lanes_below();
+        const unsigned r0 = (photon ? np : nl) +
+                            (unsigned)(__popcll(m0 & below) + __popcll(m1 & below));
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (em[u]) {
+                const unsigned rank = r0 + (u == 1 && em[0] ? 1u : 0u);
+                const uint64_t slot = photon ? base + A.q_cap_per_wave - 1 - rank : base + rank;
+                write(A, slot, t, e[u], false, false);
+            }
+        }
+        const unsigned total = (unsigned)(__popcll(m0) + __popcll(m1));
+        if (photon) np += total; else nl += total;
+    }
+};
+
+// The sink of the deferred shares (stepped inside the emitter kernel): each emitter's work is
+// done at once by the wave, with product slots taken by atomics.
+template <bool MIXED, bool BLCFA, bool LOCAL>
+struct InlineSink {
+    EmitCounts* cnt;
+    uint32_t base_step;
+
+    template <bool LOCAL_>
+    __device__ __forceinline__ void put(const StepArgs& A, bool emit, bool photon, bool aux,
+                                        int t, const EmitRec& e)
+    {
+        (void)aux;
+        if (__ballot(emit) == 0) return;
+        emit_one<MIXED, BLCFA, LOCAL>(A, emit, photon, e.i, t, e.chi, e.gamma, e.px, e.py, e.pz,
+                                      e.uid, e.aux, e.aux2, base_step, true, 0, 0, 0, *cnt);
+    }
+
+    __device__ __forceinline__ void put2(const StepArgs& A, const bool (&em)[2], bool photon,
+                                         int t, const EmitRec (&e)[2])
+    {
+#pragma unroll 1
+        for (int u = 0; u < 2; ++u) {
+            const bool m = u ? em[1] : em[0];
+            const EmitRec& r = u ? e[1] : e[0];
+            put<false>(A, m, photon, false, t, r);
+        }
+    }
+};
+
+// =============================================================================================
+// The streaming pass: per alive particle gamma, chi (or the beyond-LCFA force update), the rate
+// from LDS-staged tables and the decision; emitters go to a sink (the wave's queue slice, or,
+// for deferred shares, the emitter work itself) through a wave ballot and popcount prefix.
 //
 // Memory pattern: each iteration issues all loads of a particle as one group (the alive flag
-// was fetched one iteration earlier), so an iteration costs one memory round trip.  With
-// optical-depth decisions the particle id is not read here: only emitters need it, and the
-// emitter pass fetches it.
+// included), so an iteration costs one memory round trip.  With optical-depth decisions the
+// particle id is not read here: only emitters need it, and the emitter pass fetches it.
+//
+// Each wave works on its own share of a chunk: lanes are addressed by `tid` (the thread index
+// of a 256-thread block: wave w takes tid = 64 w .. 64 w + 63), so any wave can step any
+// wave's share of any chunk with the same arithmetic.
+// =============================================================================================
+constexpr int STEP_WAVES = STEP_BLOCK / 64;
+
 // The LCFA particle loop of a plane-wave chunk, two particles per lane per iteration (see
-// bulk_kernel for the one-particle loop and its comments; the arithmetic is the same).
-template <bool MIXED, bool LOCAL, bool PUSH, typename RT>
+// stream_chunk for the one-particle loop and its comments; the arithmetic is the same).
+template <bool MIXED, bool LOCAL, bool PUSH, typename SINK, typename RT>
 __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_tile& T,
                                                 const Wave& WV, int t, uint64_t start,
                                                 uint64_t end, const uint8_t* alive,
                                                 uint64_t amask, uint32_t step, bool photon,
-                                                uint64_t qbase, const RT* s_rad,
-                                                const RT* s_pair, unsigned* s_qn,
+                                                int tid, const RT* s_rad,
+                                                const RT* s_pair, SINK& sink,
                                                 unsigned long long& c_proc,
                                                 unsigned long long& c_ood)
 {
-    const int tid = threadIdx.x;
     const double dt = A.ph.dt;
     const uint32_t cn = (uint32_t)(end - start);  // chunk-relative offsets, as in bulk_kernel
     for (uint64_t base = start; base < end; base += 2 * STEP_BLOCK) {
@@ -516,26 +791,13 @@ __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_til
                 if (T.rate_out) T.rate_out[i] = W;
                 c_ood += ood ? 1 : 0;
             }
-            const unsigned long long mask = __ballot(emit);
-            if (mask) {
-                const int lane = lane_id();
-                const int leader = __ffsll((long long)mask) - 1;
-                unsigned off = 0;
-                if (lane == leader) off = atomicAdd(&s_qn[photon ? 1 : 0], (unsigned)__popcll(mask));
-                off = __shfl(off, leader);
-                if (emit) {
-                    const unsigned rank = off + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-                    const uint64_t slot = photon ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
-                    A.q_idx[slot] = (uint32_t)i;
-                    A.q_tile[slot] = (uint32_t)t;
-                    A.q_chi[slot] = chi;
-                    A.q_gamma[slot] = gamma;
-                    A.q_px[slot] = qx;
-                    A.q_py[slot] = qy;
-                    A.q_pz[slot] = qz;
-                    if (LOCAL) A.q_uid[slot] = quid[u];
-                }
-            }
+            EmitRec er;
+            er.i = (uint32_t)i;
+            er.chi = chi; er.gamma = gamma;
+            er.px = qx; er.py = qy; er.pz = qz;
+            er.uid = quid[u];
+            er.aux = 0.0; er.aux2 = 0.0;
+            sink.template put<LOCAL>(A, emit, photon, false, t, er);
         }
     }
 }
@@ -548,16 +810,15 @@ typedef double dv2 __attribute__((ext_vector_type(2)));
 // arithmetic, which hides more of their latency at the same number of waves and memory
 // streams.  Whole iterations of 2 x STEP_BLOCK particles only; returns how many particles of the
 // chunk it took (the one-particle loop does the rest).  The arithmetic is bulk_kernel's.
-template <bool MIXED, bool PUSH, typename RT>
+template <bool MIXED, bool PUSH, typename SINK, typename RT>
 __device__ __forceinline__ uint32_t lcfa_array_vec2(const StepArgs& A, const sfq_tile& T, int t,
                                                     uint64_t start, uint64_t end,
                                                     const uint8_t* alive, uint64_t amask,
-                                                    bool photon, uint64_t qbase,
+                                                    bool photon, int tid,
                                                     const RT* s_rad, const RT* s_pair,
-                                                    unsigned* s_qn, unsigned long long& c_proc,
+                                                    SINK& sink, unsigned long long& c_proc,
                                                     unsigned long long& c_ood)
 {
-    const int tid = threadIdx.x;
     const double dt = A.ph.dt;
     const uint32_t cn = (uint32_t)(end - start);
     const uint32_t full = cn - cn % (2u * STEP_BLOCK);
@@ -614,35 +875,281 @@ __device__ __forceinline__ uint32_t lcfa_array_vec2(const StepArgs& A, const sfq
             st_off((dv2*)(T.pz + start), ob, qzo);
         }
         st_off((dv2*)(T.tau + start), ob, tout);
-        // compaction of both particles in index order (lane l holds particles 2l, 2l + 1), with
-        // one LDS atomic per wave
-        const unsigned long long m0 = __ballot(em[0]), m1 = __ballot(em[1]);
-        if (m0 | m1) {
-            const int lane = lane_id();
-            const unsigned long long below = (1ull << lane) - 1ull;
-            const unsigned total = (unsigned)(__popcll(m0) + __popcll(m1));
-            const int leader = __ffsll((long long)(m0 | m1)) - 1;
-            unsigned off = 0;
-            if (lane == leader) off = atomicAdd(&s_qn[photon ? 1 : 0], total);
-            off = __shfl(off, leader);
-            const unsigned r0 = off + (unsigned)(__popcll(m0 & below) + __popcll(m1 & below));
+        // compaction of both particles in index order (lane l holds particles 2l, 2l + 1)
+        EmitRec er[2];
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (em[u]) {
-                    const unsigned rank = r0 + (u == 1 && em[0] ? 1u : 0u);
-                    const uint64_t slot = photon ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
-                    A.q_idx[slot] = (uint32_t)(start + o + u);
-                    A.q_tile[slot] = (uint32_t)t;
-                    A.q_chi[slot] = chiv[u];
-                    A.q_gamma[slot] = gamv[u];
-                    A.q_px[slot] = qxo[u];
-                    A.q_py[slot] = qyo[u];
-                    A.q_pz[slot] = qzo[u];
-                }
-            }
+        for (int u = 0; u < 2; ++u) {
+            er[u].i = (uint32_t)(start + o + u);
+            er[u].chi = chiv[u]; er[u].gamma = gamv[u];
+            er[u].px = qxo[u]; er[u].py = qyo[u]; er[u].pz = qzo[u];
+            er[u].uid = 0; er[u].aux = 0.0; er[u].aux2 = 0.0;
         }
+        sink.put2(A, em, photon, t, er);
     }
     return full;
+}
+
+// One wave's share of chunk c (lanes tid = 64 w .. 64 w + 63 of the 256-thread layout).
+template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE, typename SINK, typename RT>
+__device__ __forceinline__ void stream_chunk(const StepArgs& A, int c, int tid, const RT* s_rad,
+                                             const RT* s_pair, SINK& sink,
+                                             unsigned long long& c_proc,
+                                             unsigned long long& c_ood, uint32_t base_step)
+{
+    static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
+    const double dt = A.ph.dt;
+    const double idt = 1.0 / dt, idt2 = idt * idt;  // beyond-LCFA finite differences
+    const int t = __builtin_amdgcn_readfirstlane(find_tile(A.chunk_off, A.ntiles, c));
+    const sfq_tile T = uniform_tile(A.tiles[t]);
+    const uint32_t step = base_step + (uint32_t)T.step_offset;
+    const uint64_t start = (uint64_t)(c - (int)A.chunk_off[t]) * (uint64_t)A.chunk;
+    const uint64_t end = min(start + (uint64_t)A.chunk, T.n);
+    const bool photon = (T.species == SFQ_PHOTON);
+    const bool blcfa = BLCFA && !photon;
+    // tiles without an alive array read a constant 1 instead (no branch)
+    const uint8_t* alive = T.alive ? T.alive : k_alive_one;
+    const uint64_t amask = T.alive ? ~0ull : 0ull;
+    // uniform fields: every lane reads element 0 (one cache line for the wave); a plane
+    // wave: the fields are computed from two loaded values per particle
+    const uint64_t fmask = T.field_mode == SFQ_FIELDS_UNIFORM ? 0ull : ~0ull;
+    const bool wave = WAVE && T.field_mode == SFQ_FIELDS_PLANE_WAVE;
+    Wave WV{};
+    if (WAVE) WV = uniform_wave(A.tiles[t]);
+    // Every lane issues every load of an iteration in one group, the alive flag included
+    // (lanes past the end of the chunk read its last particle and drop the result): one
+    // memory round trip per iteration, with no load behind a data-dependent branch.  The
+    // price is reading the fields of dead particles.
+    if constexpr (!BLCFA && WAVE) {
+        // LCFA chunks of plane-wave tiles read 16 B of fields per particle instead of 48,
+        // so one particle per lane leaves too few bytes in flight to cover HBM latency:
+        // every lane takes two particles per iteration, all loads in one group.
+        if (wave) {
+            lcfa_wave_pairs<MIXED, LOCAL, PUSH>(A, T, WV, t, start, end, alive, amask, step,
+                                                photon, tid, s_rad, s_pair, sink, c_proc,
+                                                c_ood);
+            return;
+        }
+    }
+    const uint32_t cn = (uint32_t)(end - start);  // chunk-relative offsets below
+    uint64_t first = start;
+    if constexpr (!BLCFA && !LOCAL && !WAVE) {
+        // array tiles whose arrays allow 16-byte accesses at the chunk (and 2-byte ones for
+        // the alive flags): two adjacent particles per lane (not in the kernels that also
+        // take plane-wave tiles, whose register budget the plane-wave loop needs)
+        const uintptr_t a16 = (uintptr_t)(T.px + start) | (uintptr_t)(T.py + start) |
+                              (uintptr_t)(T.pz + start) | (uintptr_t)(T.ex + start) |
+                              (uintptr_t)(T.ey + start) | (uintptr_t)(T.ez + start) |
+                              (uintptr_t)(T.bx + start) | (uintptr_t)(T.by + start) |
+                              (uintptr_t)(T.bz + start) | (uintptr_t)(T.tau + start);
+        const uintptr_t a2 = amask ? (uintptr_t)(alive + start) : 0;
+        if (fmask == ~0ull && (a16 & 15) == 0 && (a2 & 1) == 0)
+            first += lcfa_array_vec2<MIXED, PUSH>(A, T, t, start, end, alive, amask, photon, tid,
+                                                  s_rad, s_pair, sink, c_proc, c_ood);
+    }
+    for (uint64_t base = first; base < end; base += STEP_BLOCK) {
+        const uint64_t i = base + tid;
+        const uint64_t j = min(i, end - 1);
+        const uint32_t o = (uint32_t)(base - start) + (uint32_t)tid;  // i - start
+        const uint32_t oj = min(o, cn - 1u), ob = oj * 8u;               // j - start, bytes
+        const uint8_t al = ld_off(alive + (start & amask), oj & (uint32_t)amask);
+        bool live = false, emit = false;
+        double chi = 0.0, gamma = 0.0, aux = 0.0, aux2 = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+        uint64_t quid = 0;
+        bool ood = false;
+        double W = 0.0;
+        if (BLCFA) {
+            // One load group for both species of a beyond-LCFA step.  Without the push, six
+            // slots hold E and B on photon chunks and p^{(n-1/2)}, F_perp on lepton chunks;
+            // the lepton-only Delta F and flag slots re-read the momentum and alive flag on
+            // photon chunks.  With the push every chunk reads E and B, the tile's momentum
+            // is p^{(n-1/2)}, and lepton chunks read F_perp and Delta F in six more slots.
+            // (chunk-relative: each slot's array is addressed from the chunk's first element)
+            const uint64_t n = T.n;
+            const uint64_t m05 = (blcfa && !PUSH) ? ~0ull : fmask;  // slots 0..5
+            const uint64_t s05 = start & m05;
+            const uint32_t ob05 = ob & (uint32_t)m05;
+            const bool wave_f = wave && !(blcfa && !PUSH);  // slots 0..5 hold a plane wave
+            const double* q0 = (blcfa && !PUSH) ? T.px_prev : T.ex;
+            const double* q1 = (blcfa && !PUSH) ? T.py_prev : T.ey;
+            const double* q2 = (blcfa && !PUSH) ? T.pz_prev : T.ez;
+            const double* q3 = (blcfa && !PUSH) ? T.fperp : T.bx;
+            const double* q4 = (blcfa && !PUSH) ? T.fperp + n : T.by;
+            const double* q5 = (blcfa && !PUSH) ? T.fperp + 2 * n : T.bz;
+            const double* q6 = blcfa ? T.dfperp : T.px;
+            const double* q7 = blcfa ? T.dfperp + n : T.py;
+            const double* q8 = blcfa ? T.dfperp + 2 * n : T.pz;
+            const uint8_t* q9 = blcfa ? T.just_created + start : alive + (start & amask);
+            const uint32_t o9 = blcfa ? oj : (oj & (uint32_t)amask);
+            const double* q10 = blcfa ? T.fperp : T.px;
+            const double* q11 = blcfa ? T.fperp + n : T.py;
+            const double* q12 = blcfa ? T.fperp + 2 * n : T.pz;
+            double ux = ld_off(T.px + start, ob), uy = ld_off(T.py + start, ob),
+                   uz = ld_off(T.pz + start, ob);
+            double a0, a1, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0;
+            if (wave_f) {
+                a0 = ld_off(WV.amp + start, ob);
+                a1 = ld_off(WV.phase + start, ob);
+            } else {
+                a0 = ld_off(q0 + s05, ob05); a1 = ld_off(q1 + s05, ob05);
+                a2 = ld_off(q2 + s05, ob05); a3 = ld_off(q3 + s05, ob05);
+                a4 = ld_off(q4 + s05, ob05); a5 = ld_off(q5 + s05, ob05);
+            }
+            const double rx = ld_off(q6 + start, ob), ry = ld_off(q7 + start, ob),
+                         rz = ld_off(q8 + start, ob);
+            double o0 = 0.0, o1 = 0.0, o2 = 0.0;
+            if (PUSH) {
+                o0 = ld_off(q10 + start, ob);
+                o1 = ld_off(q11 + start, ob);
+                o2 = ld_off(q12 + start, ob);
+            }
+            const bool fresh = ld_off(q9, o9) != 0;
+            quid = ld_off(T.uid + start, ob);
+            __builtin_amdgcn_sched_barrier(0);
+            live = i < end && al != 0;
+            if (wave_f) plane_wave_fields(WV, a0, a1, a0, a1, a2, a3, a4, a5);
+            // p^{(n-1/2)} and F_perp^{(n-1)}: loaded, or (with the push) the tile's momentum
+            // before the push and the six extra slots
+            double vx, vy, vz, ox, oy, oz;
+            if (PUSH) {
+                vx = ux; vy = uy; vz = uz;
+                ox = o0; oy = o1; oz = o2;
+                if (blcfa && live) {  // dead slots keep (and write back) their momentum
+                    const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
+                    boris_push(hq, a0, a1, a2, a3, a4, a5, ux, uy, uz);
+                }
+            } else {
+                vx = a0; vy = a1; vz = a2;
+                ox = a3; oy = a4; oz = a5;
+            }
+            qx = ux; qy = uy; qz = uz;
+            if (!blcfa) {
+                gamma_chi(true, ux, uy, uz, a0, a1, a2, a3, a4, a5, A.ph.lc_over_lr, gamma, chi);
+                W = rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood);
+                const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
+                emit = live && W * dt > uniform53(d.a);
+            } else {
+                // beyond-LCFA force update, Sec. 5 Eqs. (fl)-(condit)
+                const double flx = (ux - vx) * idt, fly = (uy - vy) * idt, flz = (uz - vz) * idt;
+                const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
+                const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
+                gamma = sqrt_nr(g2);
+                const double fp = (flx * plx + fly * ply + flz * plz) * rcp_nr(g2);
+                const double Fx = flx - fp * plx, Fy = fly - fp * ply, Fz = flz - fp * plz;
+                const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
+                const double tc = A.ph.lc_over_lr;
+                chi = tc * gamma * sqrt(F2);
+                W = rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+                if (live) {
+                    st_off(T.fperp + start, o * 8u, Fx); st_off(T.fperp + n + start, o * 8u, Fy);
+                    st_off(T.fperp + 2 * n + start, o * 8u, Fz);
+                }
+                if (live && fresh) {
+                    st_off(T.dfperp + start, o * 8u, 0.0);
+                    st_off(T.dfperp + n + start, o * 8u, 0.0);
+                    st_off(T.dfperp + 2 * n + start, o * 8u, 0.0);
+                    st_off(T.just_created + start, o, (uint8_t)0);
+                } else if (live) {
+                    const double ax = Fx - ox, ay = Fy - oy, az = Fz - oz;
+                    const double d1x = ax * idt, d1y = ay * idt, d1z = az * idt;
+                    const double d2x = (ax - rx) * idt2, d2y = (ay - ry) * idt2, d2z = (az - rz) * idt2;
+                    const double delta = tc * tc * ((d1x * d1x + d1y * d1y + d1z * d1z) +
+                                                    fabs(Fx * d2x + Fy * d2y + Fz * d2z));
+                    st_off(T.dfperp + start, o * 8u, ax);
+                    st_off(T.dfperp + n + start, o * 8u, ay);
+                    st_off(T.dfperp + 2 * n + start, o * 8u, az);
+                    const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
+                    const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
+                    emit = W * dt > uniform53(d.a);
+                    if (emit) {
+                        // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
+                        const double pu2 = ux * ux + uy * uy + uz * uz;
+                        aux2 = (pu2 - (g2 - 1.0)) / (sqrt(1.0 + pu2) + gamma);
+                        // tau / tau_C of Sec. 5 for the threshold gamma_{gamma,LCFA}, which
+                        // the emitter pass evaluates (only emitting lanes pay for its
+                        // transcendentals there); a negative value: LCFA throughout
+                        if (flag) {
+                            aux = 2.0 * PI * sqrt(F2 / delta);
+                        } else if (chi > ZETA) {
+                            aux = -1.0;  // fields effectively constant
+                        } else {
+                            emit = false;
+                        }
+                    }
+                }
+                // the pushed momentum of every slot of the chunk, so that whole cache lines
+                // are written (emitters get theirs again in the emitter pass, after the
+                // recoil or the rejection; dead slots write back their own)
+                if (PUSH && i < end) {
+                    st_off(T.px + start, o * 8u, ux); st_off(T.py + start, o * 8u, uy);
+                    st_off(T.pz + start, o * 8u, uz);
+                }
+            }
+        } else {
+            qx = ld_off(T.px + start, ob); qy = ld_off(T.py + start, ob);
+            qz = ld_off(T.pz + start, ob);
+            const uint64_t fs = start & fmask;         // uniform fields: element 0
+            const uint32_t obf = ob & (uint32_t)fmask;
+            double ex, ey, ez = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+            if (wave) {
+                ex = ld_off(WV.amp + start, ob);
+                ey = ld_off(WV.phase + start, ob);
+            } else {
+                ex = ld_off(T.ex + fs, obf); ey = ld_off(T.ey + fs, obf);
+                ez = ld_off(T.ez + fs, obf); bx = ld_off(T.bx + fs, obf);
+                by = ld_off(T.by + fs, obf); bz = ld_off(T.bz + fs, obf);
+            }
+            double tau0 = 0.0;
+            if (LOCAL) quid = ld_off(T.uid + start, ob);
+            else tau0 = ld_off(T.tau + start, ob);
+            // keep the whole load group ahead of the arithmetic: the first use of a loaded
+            // value waits for every outstanding memory operation (loads and stores share
+            // one counter here), so a use scheduled between the loads would split the group
+            __builtin_amdgcn_sched_barrier(0);
+            live = i < end && al != 0;
+            if (wave) plane_wave_fields(WV, ex, ey, ex, ey, ez, bx, by, bz);
+            const bool pushed = PUSH && !photon;
+            if (pushed && live) {  // dead slots keep (and write back) their momentum
+                const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
+                boris_push(hq, ex, ey, ez, bx, by, bz, qx, qy, qz);
+            }
+            gamma_chi(photon, qx, qy, qz, ex, ey, ez, bx, by, bz, A.ph.lc_over_lr, gamma, chi);
+            W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
+                       : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
+            if (!LOCAL) {
+                const double tau = tau0 - W * dt;
+                emit = live && tau < 0.0;
+                // Every slot of the chunk is written, dead ones with their own value: a
+                // partly written cache line costs the memory a read-modify-write.  Emitters
+                // get a fresh depth in the emitter pass; a converting photon keeps the
+                // decremented one.
+                if (o < cn) st_off(T.tau + start, o * 8u, live ? tau : tau0);
+            } else {
+                const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
+                emit = live && W * dt > uniform53(d.a);
+            }
+            // the pushed momentum of every slot (whole cache lines, as for tau): emitters
+            // recoil from the queued, pushed momentum in the emitter pass, which then
+            // overwrites it
+            if (pushed && o < cn) {
+                st_off(T.px + start, o * 8u, qx); st_off(T.py + start, o * 8u, qy);
+                st_off(T.pz + start, o * 8u, qz);
+            }
+        }
+        if (live) {
+            ++c_proc;
+            if (T.chi_out) T.chi_out[i] = chi;
+            if (T.rate_out) T.rate_out[i] = W;
+            c_ood += ood ? 1 : 0;
+        }
+        // compaction: the whole iteration is one tile, hence one species
+        EmitRec er;
+        er.i = (uint32_t)i;
+        er.chi = chi; er.gamma = gamma;
+        er.px = qx; er.py = qy; er.pz = qz;
+        er.uid = quid;
+        er.aux = aux; er.aux2 = aux2;
+        sink.template put<LOCAL>(A, emit, photon, blcfa, t, er);
+    }
 }
 
 template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE>
@@ -652,7 +1159,6 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
     using RT = typename std::conditional<MIXED, float, double>::type;
     __shared__ RT s_rad[RAD_SIZE];
     __shared__ RT s_pair[PAIR_SIZE];
-    __shared__ unsigned s_qn[2];  // lepton, photon emitters of this block
     __shared__ unsigned long long s_cnt[CNT_N];
 
     const int tid = threadIdx.x;
@@ -660,302 +1166,48 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
     const RT* g_pair = MIXED ? (const RT*)A.tb.pair32 : (const RT*)A.tb.pair;
     for (int k = tid; k < RAD_SIZE; k += STEP_BLOCK) s_rad[k] = g_rad[k];
     for (int k = tid; k < PAIR_SIZE; k += STEP_BLOCK) s_pair[k] = g_pair[k];
-    if (tid < 2) s_qn[tid] = 0;
     if (tid < CNT_N) s_cnt[tid] = 0;
     __syncthreads();
 
     unsigned long long c_proc = 0, c_ood = 0;
-    const uint64_t qbase = (uint64_t)blockIdx.x * A.q_cap_per_block;
-    const double dt = A.ph.dt;
-    const double idt = 1.0 / dt, idt2 = idt * idt;  // beyond-LCFA finite differences
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const uint64_t slice = (uint64_t)blockIdx.x * STEP_WAVES + (uint64_t)wv;
+    QueueSink sink{slice * A.q_cap_per_wave, 0u, 0u};
+    const uint32_t share = (uint32_t)(A.chunk / STEP_WAVES);  // most particles of a wave's share
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
 
     for (int c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
-        const int t = __builtin_amdgcn_readfirstlane(find_tile(A.chunk_off, A.ntiles, c));
-        const sfq_tile T = uniform_tile(A.tiles[t]);
-        const uint32_t step = base_step + (uint32_t)T.step_offset;
-        const uint64_t start = (uint64_t)(c - (int)A.chunk_off[t]) * (uint64_t)A.chunk;
-        const uint64_t end = min(start + (uint64_t)A.chunk, T.n);
-        const bool photon = (T.species == SFQ_PHOTON);
-        const bool blcfa = BLCFA && !photon;
-        // tiles without an alive array read a constant 1 instead (no branch)
-        const uint8_t* alive = T.alive ? T.alive : k_alive_one;
-        const uint64_t amask = T.alive ? ~0ull : 0ull;
-        // uniform fields: every lane reads element 0 (one cache line for the wave); a plane
-        // wave: the fields are computed from two loaded values per particle
-        const uint64_t fmask = T.field_mode == SFQ_FIELDS_UNIFORM ? 0ull : ~0ull;
-        const bool wave = WAVE && T.field_mode == SFQ_FIELDS_PLANE_WAVE;
-        Wave WV{};
-        if (WAVE) WV = uniform_wave(A.tiles[t]);
-        // Every lane issues every load of an iteration in one group, the alive flag included
-        // (lanes past the end of the chunk read its last particle and drop the result): one
-        // memory round trip per iteration, with no load behind a data-dependent branch.  The
-        // price is reading the fields of dead particles.
-        if constexpr (!BLCFA && WAVE) {
-            // LCFA chunks of plane-wave tiles read 16 B of fields per particle instead of 48,
-            // so one particle per lane leaves too few bytes in flight to cover HBM latency:
-            // every lane takes two particles per iteration, all loads in one group.
-            if (wave) {
-                lcfa_wave_pairs<MIXED, LOCAL, PUSH>(A, T, WV, t, start, end, alive, amask, step,
-                                                    photon, qbase, s_rad, s_pair, s_qn, c_proc,
-                                                    c_ood);
-                continue;
+        // a share whose every particle might emit must fit the slice; otherwise it is left
+        // untouched for the emitter kernel to step (no result depends on which wave steps it)
+        if (A.q_cap_per_wave - (uint64_t)(sink.nl + sink.np) < (uint64_t)share) {
+            if (lane_id() == 0) {
+                const unsigned k = atomicAdd(&A.d_ctl[0], 1u);
+                A.d_list[k] = (uint32_t)c * STEP_WAVES + (uint32_t)wv;
             }
+            continue;
         }
-        const uint32_t cn = (uint32_t)(end - start);  // chunk-relative offsets below
-        uint64_t first = start;
-        if constexpr (!BLCFA && !LOCAL && !WAVE) {
-            // array tiles whose arrays allow 16-byte accesses at the chunk (and 2-byte ones for
-            // the alive flags): two adjacent particles per lane (not in the kernels that also
-            // take plane-wave tiles, whose register budget the plane-wave loop needs)
-            const uintptr_t a16 = (uintptr_t)(T.px + start) | (uintptr_t)(T.py + start) |
-                                  (uintptr_t)(T.pz + start) | (uintptr_t)(T.ex + start) |
-                                  (uintptr_t)(T.ey + start) | (uintptr_t)(T.ez + start) |
-                                  (uintptr_t)(T.bx + start) | (uintptr_t)(T.by + start) |
-                                  (uintptr_t)(T.bz + start) | (uintptr_t)(T.tau + start);
-            const uintptr_t a2 = amask ? (uintptr_t)(alive + start) : 0;
-            if (fmask == ~0ull && (a16 & 15) == 0 && (a2 & 1) == 0)
-                first += lcfa_array_vec2<MIXED, PUSH>(A, T, t, start, end, alive, amask, photon, qbase,
-                                                s_rad, s_pair, s_qn, c_proc, c_ood);
-        }
-        for (uint64_t base = first; base < end; base += STEP_BLOCK) {
-            const uint64_t i = base + tid;
-            const uint64_t j = min(i, end - 1);
-            const uint32_t o = (uint32_t)(base - start) + (uint32_t)tid;  // i - start
-            const uint32_t oj = min(o, cn - 1u), ob = oj * 8u;               // j - start, bytes
-            const uint8_t al = ld_off(alive + (start & amask), oj & (uint32_t)amask);
-            bool live = false, emit = false;
-            double chi = 0.0, gamma = 0.0, aux = 0.0, aux2 = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
-            uint64_t quid = 0;
-            bool ood = false;
-            double W = 0.0;
-            if (BLCFA) {
-                // One load group for both species of a beyond-LCFA step.  Without the push, six
-                // slots hold E and B on photon chunks and p^{(n-1/2)}, F_perp on lepton chunks;
-                // the lepton-only Delta F and flag slots re-read the momentum and alive flag on
-                // photon chunks.  With the push every chunk reads E and B, the tile's momentum
-                // is p^{(n-1/2)}, and lepton chunks read F_perp and Delta F in six more slots.
-                // (chunk-relative: each slot's array is addressed from the chunk's first element)
-                const uint64_t n = T.n;
-                const uint64_t m05 = (blcfa && !PUSH) ? ~0ull : fmask;  // slots 0..5
-                const uint64_t s05 = start & m05;
-                const uint32_t ob05 = ob & (uint32_t)m05;
-                const bool wave_f = wave && !(blcfa && !PUSH);  // slots 0..5 hold a plane wave
-                const double* q0 = (blcfa && !PUSH) ? T.px_prev : T.ex;
-                const double* q1 = (blcfa && !PUSH) ? T.py_prev : T.ey;
-                const double* q2 = (blcfa && !PUSH) ? T.pz_prev : T.ez;
-                const double* q3 = (blcfa && !PUSH) ? T.fperp : T.bx;
-                const double* q4 = (blcfa && !PUSH) ? T.fperp + n : T.by;
-                const double* q5 = (blcfa && !PUSH) ? T.fperp + 2 * n : T.bz;
-                const double* q6 = blcfa ? T.dfperp : T.px;
-                const double* q7 = blcfa ? T.dfperp + n : T.py;
-                const double* q8 = blcfa ? T.dfperp + 2 * n : T.pz;
-                const uint8_t* q9 = blcfa ? T.just_created + start : alive + (start & amask);
-                const uint32_t o9 = blcfa ? oj : (oj & (uint32_t)amask);
-                const double* q10 = blcfa ? T.fperp : T.px;
-                const double* q11 = blcfa ? T.fperp + n : T.py;
-                const double* q12 = blcfa ? T.fperp + 2 * n : T.pz;
-                double ux = ld_off(T.px + start, ob), uy = ld_off(T.py + start, ob),
-                       uz = ld_off(T.pz + start, ob);
-                double a0, a1, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0;
-                if (wave_f) {
-                    a0 = ld_off(WV.amp + start, ob);
-                    a1 = ld_off(WV.phase + start, ob);
-                } else {
-                    a0 = ld_off(q0 + s05, ob05); a1 = ld_off(q1 + s05, ob05);
-                    a2 = ld_off(q2 + s05, ob05); a3 = ld_off(q3 + s05, ob05);
-                    a4 = ld_off(q4 + s05, ob05); a5 = ld_off(q5 + s05, ob05);
-                }
-                const double rx = ld_off(q6 + start, ob), ry = ld_off(q7 + start, ob),
-                             rz = ld_off(q8 + start, ob);
-                double o0 = 0.0, o1 = 0.0, o2 = 0.0;
-                if (PUSH) {
-                    o0 = ld_off(q10 + start, ob);
-                    o1 = ld_off(q11 + start, ob);
-                    o2 = ld_off(q12 + start, ob);
-                }
-                const bool fresh = ld_off(q9, o9) != 0;
-                quid = ld_off(T.uid + start, ob);
-                __builtin_amdgcn_sched_barrier(0);
-                live = i < end && al != 0;
-                if (wave_f) plane_wave_fields(WV, a0, a1, a0, a1, a2, a3, a4, a5);
-                // p^{(n-1/2)} and F_perp^{(n-1)}: loaded, or (with the push) the tile's momentum
-                // before the push and the six extra slots
-                double vx, vy, vz, ox, oy, oz;
-                if (PUSH) {
-                    vx = ux; vy = uy; vz = uz;
-                    ox = o0; oy = o1; oz = o2;
-                    if (blcfa && live) {  // dead slots keep (and write back) their momentum
-                        const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
-                        boris_push(hq, a0, a1, a2, a3, a4, a5, ux, uy, uz);
-                    }
-                } else {
-                    vx = a0; vy = a1; vz = a2;
-                    ox = a3; oy = a4; oz = a5;
-                }
-                qx = ux; qy = uy; qz = uz;
-                if (!blcfa) {
-                    gamma_chi(true, ux, uy, uz, a0, a1, a2, a3, a4, a5, A.ph.lc_over_lr, gamma, chi);
-                    W = rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood);
-                    const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
-                    emit = live && W * dt > uniform53(d.a);
-                } else {
-                    // beyond-LCFA force update, Sec. 5 Eqs. (fl)-(condit)
-                    const double flx = (ux - vx) * idt, fly = (uy - vy) * idt, flz = (uz - vz) * idt;
-                    const double plx = 0.5 * (ux + vx), ply = 0.5 * (uy + vy), plz = 0.5 * (uz + vz);
-                    const double g2 = 1.0 + (plx * plx + ply * ply + plz * plz);
-                    gamma = sqrt_nr(g2);
-                    const double fp = (flx * plx + fly * ply + flz * plz) * rcp_nr(g2);
-                    const double Fx = flx - fp * plx, Fy = fly - fp * ply, Fz = flz - fp * plz;
-                    const double F2 = Fx * Fx + Fy * Fy + Fz * Fz;
-                    const double tc = A.ph.lc_over_lr;
-                    chi = tc * gamma * sqrt(F2);
-                    W = rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
-                    if (live) {
-                        st_off(T.fperp + start, o * 8u, Fx); st_off(T.fperp + n + start, o * 8u, Fy);
-                        st_off(T.fperp + 2 * n + start, o * 8u, Fz);
-                    }
-                    if (live && fresh) {
-                        st_off(T.dfperp + start, o * 8u, 0.0);
-                        st_off(T.dfperp + n + start, o * 8u, 0.0);
-                        st_off(T.dfperp + 2 * n + start, o * 8u, 0.0);
-                        st_off(T.just_created + start, o, (uint8_t)0);
-                    } else if (live) {
-                        const double ax = Fx - ox, ay = Fy - oy, az = Fz - oz;
-                        const double d1x = ax * idt, d1y = ay * idt, d1z = az * idt;
-                        const double d2x = (ax - rx) * idt2, d2y = (ay - ry) * idt2, d2z = (az - rz) * idt2;
-                        const double delta = tc * tc * ((d1x * d1x + d1y * d1y + d1z * d1z) +
-                                                        fabs(Fx * d2x + Fy * d2y + Fz * d2z));
-                        st_off(T.dfperp + start, o * 8u, ax);
-                        st_off(T.dfperp + n + start, o * 8u, ay);
-                        st_off(T.dfperp + 2 * n + start, o * 8u, az);
-                        const bool flag = (g2 * delta / (ZETA * ZETA) > chi * chi * F2) && (chi > ZETA);
-                        const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
-                        emit = W * dt > uniform53(d.a);
-                        if (emit) {
-                            // energy of the pushed momentum minus gamma^{(n)} (for the recoil)
-                            const double pu2 = ux * ux + uy * uy + uz * uz;
-                            aux2 = (pu2 - (g2 - 1.0)) / (sqrt(1.0 + pu2) + gamma);
-                            // tau / tau_C of Sec. 5 for the threshold gamma_{gamma,LCFA}, which
-                            // the emitter pass evaluates (only emitting lanes pay for its
-                            // transcendentals there); a negative value: LCFA throughout
-                            if (flag) {
-                                aux = 2.0 * PI * sqrt(F2 / delta);
-                            } else if (chi > ZETA) {
-                                aux = -1.0;  // fields effectively constant
-                            } else {
-                                emit = false;
-                            }
-                        }
-                    }
-                    // the pushed momentum of every slot of the chunk, so that whole cache lines
-                    // are written (emitters get theirs again in the emitter pass, after the
-                    // recoil or the rejection; dead slots write back their own)
-                    if (PUSH && i < end) {
-                        st_off(T.px + start, o * 8u, ux); st_off(T.py + start, o * 8u, uy);
-                        st_off(T.pz + start, o * 8u, uz);
-                    }
-                }
-            } else {
-                qx = ld_off(T.px + start, ob); qy = ld_off(T.py + start, ob);
-                qz = ld_off(T.pz + start, ob);
-                const uint64_t fs = start & fmask;         // uniform fields: element 0
-                const uint32_t obf = ob & (uint32_t)fmask;
-                double ex, ey, ez = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
-                if (wave) {
-                    ex = ld_off(WV.amp + start, ob);
-                    ey = ld_off(WV.phase + start, ob);
-                } else {
-                    ex = ld_off(T.ex + fs, obf); ey = ld_off(T.ey + fs, obf);
-                    ez = ld_off(T.ez + fs, obf); bx = ld_off(T.bx + fs, obf);
-                    by = ld_off(T.by + fs, obf); bz = ld_off(T.bz + fs, obf);
-                }
-                double tau0 = 0.0;
-                if (LOCAL) quid = ld_off(T.uid + start, ob);
-                else tau0 = ld_off(T.tau + start, ob);
-                // keep the whole load group ahead of the arithmetic: the first use of a loaded
-                // value waits for every outstanding memory operation (loads and stores share
-                // one counter here), so a use scheduled between the loads would split the group
-                __builtin_amdgcn_sched_barrier(0);
-                live = i < end && al != 0;
-                if (wave) plane_wave_fields(WV, ex, ey, ex, ey, ez, bx, by, bz);
-                const bool pushed = PUSH && !photon;
-                if (pushed && live) {  // dead slots keep (and write back) their momentum
-                    const double hq = (T.species == SFQ_POSITRON ? 0.5 : -0.5) * dt;
-                    boris_push(hq, ex, ey, ez, bx, by, bz, qx, qy, qz);
-                }
-                gamma_chi(photon, qx, qy, qz, ex, ey, ez, bx, by, bz, A.ph.lc_over_lr, gamma, chi);
-                W = photon ? rate_photon<MIXED>(s_pair, A.ph, gamma, chi, &ood)
-                           : rate_lepton<MIXED>(s_rad, A.ph, gamma, chi, &ood);
-                if (!LOCAL) {
-                    const double tau = tau0 - W * dt;
-                    emit = live && tau < 0.0;
-                    // Every slot of the chunk is written, dead ones with their own value: a
-                    // partly written cache line costs the memory a read-modify-write.  Emitters
-                    // get a fresh depth in the emitter pass; a converting photon keeps the
-                    // decremented one.
-                    if (o < cn) st_off(T.tau + start, o * 8u, live ? tau : tau0);
-                } else {
-                    const Draw d = philox_draw(A.seed, quid, step, SFQ_P_LOCAL);
-                    emit = live && W * dt > uniform53(d.a);
-                }
-                // the pushed momentum of every slot (whole cache lines, as for tau): emitters
-                // recoil from the queued, pushed momentum in the emitter pass, which then
-                // overwrites it
-                if (pushed && o < cn) {
-                    st_off(T.px + start, o * 8u, qx); st_off(T.py + start, o * 8u, qy);
-                    st_off(T.pz + start, o * 8u, qz);
-                }
-            }
-            if (live) {
-                ++c_proc;
-                if (T.chi_out) T.chi_out[i] = chi;
-                if (T.rate_out) T.rate_out[i] = W;
-                c_ood += ood ? 1 : 0;
-            }
-            // compaction: the whole iteration is one tile, hence one species
-            const unsigned long long mask = __ballot(emit);
-            if (mask) {
-                const int lane = lane_id();
-                const int leader = __ffsll((long long)mask) - 1;
-                unsigned off = 0;
-                if (lane == leader) off = atomicAdd(&s_qn[photon ? 1 : 0], (unsigned)__popcll(mask));
-                off = __shfl(off, leader);
-                if (emit) {
-                    const unsigned rank = off + (unsigned)__popcll(mask & ((1ull << lane) - 1ull));
-                    const uint64_t slot = photon ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
-                    A.q_idx[slot] = (uint32_t)i;
-                    A.q_tile[slot] = (uint32_t)t;
-                    A.q_chi[slot] = chi;
-                    A.q_gamma[slot] = gamma;
-                    A.q_px[slot] = qx;
-                    A.q_py[slot] = qy;
-                    A.q_pz[slot] = qz;
-                    if (LOCAL) A.q_uid[slot] = quid;
-                    if (blcfa) {
-                        A.q_aux[slot] = aux;
-                        A.q_aux2[slot] = aux2;
-                    }
-                }
-            }
-        }
+        stream_chunk<MIXED, BLCFA, LOCAL, PUSH, WAVE>(A, c, tid, s_rad, s_pair, sink, c_proc,
+                                                       c_ood, base_step);
     }
-    __syncthreads();
-    if (tid < 2) A.q_count[2 * blockIdx.x + tid] = s_qn[tid];
+    if (lane_id() == 0) {
+        A.q_count[2 * slice] = sink.nl;
+        A.q_count[2 * slice + 1] = sink.np;
+    }
     // the block's processed count goes to the queue for the scan kernel (no global atomic:
     // thousands of blocks adding to one word serialise); the rare out-of-domain count is added
     __shared__ unsigned long long s_tmp[1];
     const unsigned long long proc = block_sum(s_tmp, c_proc);
     if (tid == 0) A.q_proc[blockIdx.x] = proc;
-    const unsigned long long vals[CNT_N] = {0, 0, 0, 0, c_ood, 0, 0};
+    const unsigned long long vals[CNT_N] = {0, 0, 0, 0, c_ood, 0, 0, 0};
     block_add_counters(s_cnt, A.counters, vals);
 }
 
-// Between the two passes, one block: each streaming block's first product slot (exclusive
-// prefix sums of the queued emitters over blocks, from the current product counts), the new
+// Between the two passes, one block: each queue slice's first product slot (exclusive prefix
+// sums of the queued emitters over the slices, from the current product counts), the new
 // product counts, and the step's processed / emitted / converted counters, each written once.
 // Every queued lepton emits and every queued photon converts, except that beyond-LCFA
 // rejections are only known in the emitter pass, which then reserves photon slots itself.
+// The largest emitter fraction of a wave's share goes to A.obs (when set) for queue sizing.
 constexpr int SCAN_BLOCK = 256;
 
 // inclusive prefix sum over the 64 lanes of a wave
@@ -974,15 +1226,26 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
 {
     constexpr int NW = SCAN_BLOCK / 64;
     __shared__ unsigned long long s_w[3][NW];
-    const int tid = threadIdx.x, w = tid >> 6, G = A.grid;
-    const int per = (G + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    const int lo = min(tid * per, G), hi = min(lo + per, G);
+    __shared__ unsigned s_fmax;
+    const int tid = threadIdx.x, w = tid >> 6, G = A.grid, S = A.grid * STEP_WAVES;
+    if (tid == 0) s_fmax = 0;
+    const int per = (S + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    const int lo = min(tid * per, S), hi = min(lo + per, S);
     unsigned long long nl = 0, np = 0, proc = 0;
+    float fmax = 0.0f;
     for (int b = lo; b < hi; ++b) {
-        nl += A.q_count[2 * b];
-        np += A.q_count[2 * b + 1];
-        proc += A.q_proc[b];
+        const unsigned a = A.q_count[2 * b], c = A.q_count[2 * b + 1];
+        nl += a;
+        np += c;
+        if (A.obs) {
+            // particles of the wave's shares: its block's chunks times a share
+            const int blk = b / STEP_WAVES;
+            const int chunks = (A.nchunks - blk + G - 1) / G;
+            const float room = (float)chunks * (float)(A.chunk / STEP_WAVES);
+            if (room > 0.0f) fmax = fmaxf(fmax, (float)(a + c) / room);
+        }
     }
+    for (int b = tid; b < G; b += SCAN_BLOCK) proc += A.q_proc[b];
     // block-wide inclusive scans: within each wave, then over the wave totals
     unsigned long long il = wave_inclusive_scan(nl), ip = wave_inclusive_scan(np);
     const unsigned long long in = wave_inclusive_scan(proc);
@@ -1008,6 +1271,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
         run_l += A.q_count[2 * b];
         run_p += A.q_count[2 * b + 1];
     }
+    if (A.obs && fmax > 0.0f) atomicMax(&s_fmax, __float_as_uint(fmax));  // fmax >= 0
     __syncthreads();  // every read of the product counts happens before they are advanced
     if (tid == 0) {
         if (!multi) {
@@ -1020,52 +1284,70 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
         atomicAdd(&A.counters->processed, tn);
         if (!A.blcfa) atomicAdd(&A.counters->emitted, tl);
         atomicAdd(&A.counters->converted, tp);
+        if (A.obs) {
+            // observations for sizing the queue (plain stores to host memory, which the host
+            // reads at a later step; a late or overwritten value only delays a resize)
+            A.obs[0] = s_fmax;
+            A.obs[1] = A.d_ctl[0];
+        }
     }
 }
 
-// Emitter pass: block b samples the queue slice written by block b of the streaming pass, with
-// every lane busy: Philox draws, inverse-CDF tables, recoil and products (one global atomic per
-// wave and product buffer).
+// Emitter pass: the slices of streaming block qb are sampled by emit_split blocks with every
+// lane busy, each taking a contiguous range of their entries: Philox draws, inverse-CDF tables,
+// recoil and products at the scanned slots.
 template <bool MIXED, bool BLCFA, bool LOCAL>
 __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepArgs A)
 {
     static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
     __shared__ unsigned long long s_cnt[CNT_N];
-    __shared__ unsigned long long s_base[3];
+    __shared__ unsigned s_cum[2 * STEP_WAVES + 1];
+    __shared__ unsigned long long s_base[3 * STEP_WAVES];
     const int tid = threadIdx.x;
     if (tid < CNT_N) s_cnt[tid] = 0;
-    // emitter block -> (queue slice, part of it): a slice is shared by emit_split blocks, each
-    // taking a contiguous range of its entries
     const int qb = blockIdx.x / A.emit_split, part = blockIdx.x % A.emit_split;
-    const uint64_t qbase = (uint64_t)qb * A.q_cap_per_block;
-    const unsigned nl = A.q_count[2 * qb], np = A.q_count[2 * qb + 1];
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
-    // product slots of the whole block, from the scan kernel: one photon per lepton emitter and
-    // one electron-positron pair per converting photon (beyond-LCFA rejections leave no
+    const bool multi = A.nsets > 0;
+    // the block's slices in order: leptons then photons of slice 0, of slice 1, ...
+    if (tid == 0) {
+        unsigned acc = 0;
+        for (int w = 0; w < STEP_WAVES; ++w) {
+            const uint64_t sl = (uint64_t)qb * STEP_WAVES + w;
+            s_cum[2 * w] = acc;
+            acc += A.q_count[2 * sl];
+            s_cum[2 * w + 1] = acc;
+            acc += A.q_count[2 * sl + 1];
+        }
+        s_cum[2 * STEP_WAVES] = acc;
+    }
+    // product slots of the block's slices, from the scan kernel: one photon per lepton emitter
+    // and one electron-positron pair per converting photon (beyond-LCFA rejections leave no
     // product, so that mode reserves photon slots per wave instead, and steps with per-tile
     // product sets reserve per wave and set)
-    const bool multi = A.nsets > 0;
-    if (tid < 3) s_base[tid] = multi ? 0ull : A.q_base[3 * qb + tid];
+    if (tid < 3 * STEP_WAVES)
+        s_base[tid] = multi ? 0ull : A.q_base[(uint64_t)3 * STEP_WAVES * qb + tid];
     __syncthreads();
-    const unsigned total = nl + np;
-    unsigned long long c_emit = 0, c_conv = 0, c_rej = 0, c_clamp = 0, c_over = 0, c_ood = 0;
+    const unsigned total = s_cum[2 * STEP_WAVES];
+    EmitCounts C;
     const unsigned per = (total + A.emit_split - 1) / A.emit_split;
     const unsigned e_lo = min(total, per * (unsigned)part), e_hi = min(total, e_lo + per);
     for (unsigned b0 = e_lo; b0 < e_hi; b0 += STEP_BLOCK) {
         const unsigned e = b0 + tid;
         const bool valid = e < e_hi;
-        bool want_ph = false, want_pair = false;
-        double pgx = 0, pgy = 0, pgz = 0, tau_a = 0, pbx = 0, pby = 0, pbz = 0, tau_b = 0;
-        uint64_t uid_a = 0, uid_b = 0, parent = 0;
-        // gather this lane's emitter from the queue (contiguous reads)
-        const bool pair = valid && e >= nl;
-        const unsigned rank = pair ? e - nl : e;
-        const uint64_t slot = pair ? qbase + A.q_cap_per_block - 1 - rank : qbase + rank;
-        uint64_t i = 0, uid = 0;
-        uint32_t step = base_step;
-        int t = 0, pset = 0;
-        double chi = 1.0, gamma = 1.0, r = 0.5, px = 0, py = 0, pz = 0;
-        Draw d1{0, 0}, d2{0, 0};
+        // this lane's entry: the segment (slice, species) that holds entry e
+        int k = 0;
+#pragma unroll
+        for (int j = 1; j < 2 * STEP_WAVES; ++j)
+            if (e >= s_cum[j]) k = j;
+        const int w = k >> 1;
+        const bool pair = valid && (k & 1);
+        const unsigned rank = e - s_cum[k];
+        const uint64_t sbase = ((uint64_t)qb * STEP_WAVES + w) * A.q_cap_per_wave;
+        const uint64_t slot = pair ? sbase + A.q_cap_per_wave - 1 - rank : sbase + rank;
+        uint32_t i = 0;
+        int t = 0;
+        double chi = 1.0, gamma = 1.0, px = 0, py = 0, pz = 0, aux = -1.0, aux2 = 0.0;
+        uint64_t quid = 0;
         if (valid) {
             i = A.q_idx[slot];
             t = (int)A.q_tile[slot];
@@ -1074,127 +1356,69 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
             px = A.q_px[slot];
             py = A.q_py[slot];
             pz = A.q_pz[slot];
-            // with optical-depth decisions the streaming pass did not read the id
-            uid = LOCAL ? A.q_uid[slot] : A.tiles[t].uid[i];
-            step = base_step + (uint32_t)A.tiles[t].step_offset;
-            d1 = philox_draw(A.seed, uid, step, SFQ_P_EMIT);
-            d2 = philox_draw(A.seed, uid, step, SFQ_P_CHILD);
-            r = uniform53(d1.a);
-        }
-        double s = 0.0, v = 0.0, omv = 1.0;
-        bool ood = false;
-        sample_coop<MIXED>(A.tb, valid, pair, chi, r, s, v, omv, ood);
-        if (valid) {
-            const sfq_tile& T = A.tiles[t];
-            if (multi) pset = T.product_set;
-            parent = uid;
-            const double pn = sqrt(fma(px, px, fma(py, py, pz * pz)));
-            if (!pair) {
-                const double gph = gamma * (s / (1.0 + s));
-                bool accept = true, none = false;
-                double gem = gamma / (1.0 + s);
-                if (BLCFA) {
-                    // the threshold gamma_{gamma,LCFA} (Eq. gammaLCFA) from the queued tau/tau_C
-                    const double tau_ratio = A.q_aux[slot];
-                    double limit = 0.0;
-                    if (tau_ratio >= 0.0) {
-                        const double arg = chi / (8.0 * gamma) * tau_ratio;
-                        limit = 0.7 * gamma /
-                                (1.0 + 4.0 / (3.0 * PI * chi) * sinh(3.0 * asinh(arg)));
-                    }
-                    // no emission at all when the threshold reaches 0.75 gamma (Sec. 5; it
-                    // cannot for finite input, as the threshold is at most 0.7 gamma)
-                    none = !(limit < 0.75 * gamma);
-                    if (none) {
-                        accept = false;
-                    } else if (!(gph > limit)) {  // Eq. (rej_cond)
-                        const Draw dl = philox_draw(A.seed, uid, step, SFQ_P_LOCAL);
-                        const double r2 = uniform53(dl.b);
-                        const double lp_s = log_photon_pdf(A.tb.ka, A.tb.kb, gph, gamma, chi);
-                        const double lp_l = log_photon_pdf(A.tb.ka, A.tb.kb, limit, gamma, chi);
-                        accept = log(r2) + lp_s <= lp_l;
-                    }
-                    // the pushed momentum recoils by the photon energy
-                    gem += A.q_aux2[slot];
-                }
-                if (accept) {
-                    bool cl;
-                    const double f = lepton_momentum_factor(gem, pn, cl);
-                    c_clamp += cl ? 1 : 0;
-                    T.px[i] = px * f; T.py[i] = py * f; T.pz[i] = pz * f;
-                    if (A.decision == SFQ_OPTICAL_DEPTH) T.tau[i] = optical_depth(d1.b);
-                    const double fg = pn > 0.0 ? gph / pn : 0.0;
-                    pgx = px * fg; pgy = py * fg; pgz = pz * fg;
-                    tau_a = optical_depth(d2.a);
-                    uid_a = d2.b;
-                    want_ph = true;
-                    ++c_emit;
-                } else {
-                    // rejected: the lepton keeps the pushed momentum, which the streaming pass
-                    // has already written to the tile with the fused push
-                    if (!none) ++c_rej;
-                }
-            } else {
-                const Draw d3 = philox_draw(A.seed, uid, step, SFQ_P_CHILD2);
-                double ge, gp;
-                pair_energies(gamma, r, v, omv, ge, gp);
-                bool c1, c2;
-                const double fe = lepton_momentum_factor(ge, pn, c1);
-                const double fp = lepton_momentum_factor(gp, pn, c2);
-                c_clamp += (c1 ? 1 : 0) + (c2 ? 1 : 0);
-                pgx = px * fe; pgy = py * fe; pgz = pz * fe;   // electron
-                pbx = px * fp; pby = py * fp; pbz = pz * fp;   // positron
-                tau_a = optical_depth(d1.b);
-                uid_a = d2.b;
-                tau_b = optical_depth(d2.a);
-                uid_b = d3.a;
-                if (T.alive) T.alive[i] = 0;
-                want_pair = true;
-                ++c_conv;
-            }
-            c_ood += ood ? 1 : 0;
-        }
-        {
-            unsigned long long k;
-            if (multi) k = keyed_reserve(A.sets, 0, pset, want_ph);
-            else k = BLCFA ? wave_reserve(&A.prod_counts[0], want_ph) : s_base[0] + rank;
-            if (want_ph) {
-                const sfq_products P = multi ? A.sets[pset].photons : A.prod[0];
-                if (k < P.capacity) {
-                    P.px[k] = pgx; P.py[k] = pgy; P.pz[k] = pgz; P.tau[k] = tau_a;
-                    P.uid[k] = uid_a; P.parent[k] = parent;
-                } else {
-                    ++c_over;
-                }
+            if (LOCAL) quid = A.q_uid[slot];
+            if (BLCFA && !pair) {
+                aux = A.q_aux[slot];
+                aux2 = A.q_aux2[slot];
             }
         }
-        unsigned long long ke = s_base[1] + rank, kp = s_base[2] + rank;
-        if (multi) {
-            ke = keyed_reserve(A.sets, 1, pset, want_pair);
-            kp = keyed_reserve(A.sets, 2, pset, want_pair);
-        }
-        if (want_pair) {
-            const sfq_products E = multi ? A.sets[pset].electrons : A.prod[1];
-            if (ke < E.capacity) {
-                E.px[ke] = pgx; E.py[ke] = pgy; E.pz[ke] = pgz; E.tau[ke] = tau_a;
-                E.uid[ke] = uid_a; E.parent[ke] = parent;
-            } else {
-                ++c_over;
-            }
-            const sfq_products P = multi ? A.sets[pset].positrons : A.prod[2];
-            if (kp < P.capacity) {
-                P.px[kp] = pbx; P.py[kp] = pby; P.pz[kp] = pbz; P.tau[kp] = tau_b;
-                P.uid[kp] = uid_b; P.parent[kp] = parent;
-            } else {
-                ++c_over;
-            }
-        }
+        emit_one<MIXED, BLCFA, LOCAL>(A, valid, pair, i, t, chi, gamma, px, py, pz, quid, aux,
+                                      aux2, base_step, false, s_base[3 * w] + rank,
+                                      s_base[3 * w + 1] + rank, s_base[3 * w + 2] + rank, C);
     }
     __syncthreads();
     // emissions and conversions were counted by the scan kernel, except beyond-LCFA emissions
-    (void)c_conv;
-    const unsigned long long vals[CNT_N] = {0, BLCFA ? c_emit : 0ull, 0, c_rej, c_ood, c_clamp, c_over};
+    const unsigned long long vals[CNT_N] = {0, BLCFA ? C.emit : 0ull, 0, C.rej, C.ood, C.clamp,
+                                            C.over, 0};
     block_add_counters(s_cnt, A.counters, vals);
+}
+
+// The shares the streaming pass deferred (enqueued after the emitter kernel whenever the
+// queue is smaller than a step's worst case; it returns at once when nothing was deferred).
+// Each wave takes one share at a time and steps it whole: the streaming pass's arithmetic on
+// the same inputs (the rate tables read from global memory), each emitter's work done at once
+// with product slots taken by atomics.  The last block out clears the deferral words.
+template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE>
+__global__ __launch_bounds__(STEP_BLOCK, 1) void defer_kernel(StepArgs A)
+{
+    static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
+    using RT = typename std::conditional<MIXED, float, double>::type;
+    __shared__ unsigned long long s_cnt[CNT_N];
+    const unsigned ndef = A.d_ctl[0];
+    if (ndef == 0) return;  // the same for every block: nothing to step, nothing to clear
+    const int tid = threadIdx.x;
+    if (tid < CNT_N) s_cnt[tid] = 0;
+    __syncthreads();
+    const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
+    const RT* g_rad = MIXED ? (const RT*)A.tb.rad32 : (const RT*)A.tb.rad;
+    const RT* g_pair = MIXED ? (const RT*)A.tb.pair32 : (const RT*)A.tb.pair;
+    EmitCounts C;
+    InlineSink<MIXED, BLCFA, LOCAL> sink{&C, base_step};
+    unsigned long long c_proc = 0, c_ood = 0;
+    for (;;) {
+        unsigned u = 0;
+        if (lane_id() == 0) u = atomicAdd(&A.d_ctl[1], 1u);
+        u = __shfl(u, 0);
+        if (u >= ndef) break;
+        const uint32_t unit = A.d_list[u];
+        const int c = (int)(unit / STEP_WAVES), wu = (int)(unit % STEP_WAVES);
+        stream_chunk<MIXED, BLCFA, LOCAL, PUSH, WAVE>(A, c, wu * 64 + lane_id(), g_rad, g_pair,
+                                                       sink, c_proc, c_ood, base_step);
+    }
+    __syncthreads();
+    const unsigned long long vals[CNT_N] = {c_proc, C.emit, C.conv, C.rej, C.ood + c_ood,
+                                            C.clamp, C.over, c_proc};
+    block_add_counters(s_cnt, A.counters, vals);
+    if (tid == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&A.d_ctl[2], 1u);
+        if (done == gridDim.x - 1) {
+            A.d_ctl[0] = 0;
+            A.d_ctl[1] = 0;
+            A.d_ctl[2] = 0;
+            __threadfence();
+        }
+    }
 }
 
 // step helpers: zero the product counts of product sets (a kernel, not a memset, so graphs
@@ -1346,21 +1570,32 @@ struct ProfEvents {
 struct sfq_ctx {
     int device = 0;
     int precision = SFQ_FP64, decision = SFQ_OPTICAL_DEPTH, blcfa = 0, bw_fast = 0;
+    int approx = SFQ_APPROX_FULL;
     double lc_over_lr = 0, lr_over_lc = 0, dt = 0;
     Physics ph{};
     Tables tb{};
     void* d_tab64 = nullptr;
     void* d_tab32 = nullptr;
     int num_cus = 256;
-    // step scratch
+    // step scratch: the emitter queue and its capacities (entries, slices, blocks, deferrable
+    // shares), and its sizing: room for q_frac of a wave's particles beyond one share, grown
+    // from what the steps observe when q_adaptive
     std::mutex mu;
     void* d_queue = nullptr;
-    size_t queue_entries = 0;
-    int queue_blocks = 0;
-    // the queue's last user: a step on another stream waits for this event before using it
-    hipEvent_t queue_free = nullptr;
-    hipStream_t queue_stream = nullptr;
-    bool queue_used = false;
+    uint64_t q_cap_entries = 0, q_cap_slices = 0, q_cap_grid = 0, q_cap_deferrable = 0;
+    double q_frac = 0.125;
+    int q_adaptive = 1;
+    unsigned* obs_host = nullptr;  // pinned, mapped: the scan kernel's observations
+    unsigned* obs_dev = nullptr;
+    // The end of the handle's last step (its own step_done event, or the step's timing event
+    // when timing is on): a step on another stream waits for it, since steps share the queue.
+    // One event record per step: a staging slot's event is recorded only when the descriptors
+    // move on to another slot (on the stream of the step that moves on, after that wait, so it
+    // marks the end of every step that read the slot).
+    hipEvent_t step_done = nullptr;
+    hipEvent_t last_end = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool any_step = false;
     Staging staging[N_STAGING];
     int next_staging = 0;
     // the descriptor bytes last uploaded and the staging slot whose device copy holds them: a
@@ -1430,16 +1665,17 @@ static sfq_status load_tables(sfq_ctx* h, const char* path_in)
     memcpy(&hash, &buf[pos + 8], 8);
     pos += 16;
     (void)hash;
-    const int expect_geom[22] = {RATE_DEG, CHI_OCT_LO, CHI_OCT_HI, N_CHI_SEG, PAIR_OCT_LO,
+    const int expect_geom[24] = {RATE_DEG, CHI_OCT_LO, CHI_OCT_HI, N_CHI_SEG, PAIR_OCT_LO,
                                  N_PAIR_SEG, KA_DEG, N_KA, KB_DEG, KB_OCT_LO, KB_OCT_HI, INV_NC,
                                  INV_NR, N_LO_SEG, T_OCT_LO, T_OCT_HI, N_HI_SEG, N_R_SEG, SUB,
-                                 INV_CHI_OCT_LO, N_INV_CHI, N_PAIR_INV_CHI};
+                                 INV_CHI_OCT_LO, N_INV_CHI, N_PAIR_INV_CHI, RATE_DEG_TRUNC,
+                                 INV_TRUNC};
     if (version != 3 || narr != 6 || !need(sizeof(expect_geom)))
         return fail(h, SFQ_E_TABLES, "unsupported table file version in " + path);
-    int geom[22];
+    int geom[24];
     memcpy(geom, &buf[pos], sizeof(geom));
     pos += sizeof(geom);
-    for (int k = 0; k < 22; ++k)
+    for (int k = 0; k < 24; ++k)
         if (geom[k] != expect_geom[k])
             return fail(h, SFQ_E_TABLES, "table geometry mismatch (field " + std::to_string(k) +
                                              ") in " + path + ": rebuild the tables");
@@ -1498,11 +1734,12 @@ static void release(sfq_ctx* h)
     for (auto* v : {&h->prof_used, &h->prof_free})
         for (auto& pe : *v)
             for (auto& e : pe.e) (void)hipEventDestroy(e);
-    if (h->queue_free) {
-        (void)hipEventSynchronize(h->queue_free);
-        (void)hipEventDestroy(h->queue_free);
+    if (h->step_done) {
+        (void)hipEventSynchronize(h->step_done);
+        (void)hipEventDestroy(h->step_done);
     }
     if (h->d_queue) (void)hipFree(h->d_queue);
+    if (h->obs_host) (void)hipHostFree(h->obs_host);
     if (h->d_tab64) (void)hipFree(h->d_tab64);
     if (h->d_tab32) (void)hipFree(h->d_tab32);
     delete h;
@@ -1532,7 +1769,8 @@ sfq_status sfq_create(const sfq_config* cfg, sfq_handle* out)
         return fail(nullptr, SFQ_E_ARG, "sfq_create: bad decision");
     if (cfg->blcfa && cfg->decision != SFQ_LOCAL)
         return fail(nullptr, SFQ_E_ARG, "sfq_create: beyond-LCFA emission requires the local decision");
-    if (cfg->reserved != 0) return fail(nullptr, SFQ_E_ARG, "sfq_create: reserved field must be 0");
+    if (cfg->approx != SFQ_APPROX_FULL && cfg->approx != SFQ_APPROX_TRUNCATED)
+        return fail(nullptr, SFQ_E_ARG, "sfq_create: bad approx");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
         return fail(nullptr, SFQ_E_DEVICE, "sfq_create: no HIP device");
@@ -1566,6 +1804,22 @@ sfq_status sfq_create(const sfq_config* cfg, sfq_handle* out)
         tl_error = msg;
         return st;
     }
+    h->approx = cfg->approx;
+    h->ph.trunc = h->tb.trunc = (cfg->approx == SFQ_APPROX_TRUNCATED) ? 1 : 0;
+    // the scan kernel's observations for sizing the emitter queue: pinned host memory the
+    // kernel writes directly (without it the queue keeps its initial size)
+    void* obs = nullptr;
+    if (hipHostMalloc(&obs, 256, hipHostMallocMapped) == hipSuccess) {
+        void* dptr = nullptr;
+        if (hipHostGetDevicePointer(&dptr, obs, 0) == hipSuccess) {
+            h->obs_host = (unsigned*)obs;
+            h->obs_dev = (unsigned*)dptr;
+            memset(obs, 0, 256);
+        } else {
+            (void)hipHostFree(obs);
+        }
+    }
+    (void)hipGetLastError();
     *out = h;
     return SFQ_OK;
 }
@@ -1779,8 +2033,9 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
                 return fail(h, SFQ_E_ARG, "sfq_step: beyond-LCFA state missing" + tn);
         }
         const uint64_t nch = (T.n + chunk - 1) / chunk;
-        if ((uint64_t)off[t] + nch >= (1ull << 31))
-            return fail(h, SFQ_E_CAPACITY, "sfq_step: too many particles in one step");
+        if ((uint64_t)off[t] + nch >= (1ull << 29))
+            return fail(h, SFQ_E_CAPACITY, "sfq_step: too many particles in one step (at most "
+                                           "2^29 - 1 chunks)");
         off[t + 1] = off[t] + (uint32_t)nch;
     }
     auto bad = [](const sfq_products& P) {
@@ -1800,35 +2055,64 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
 }
 
 struct QueueShape {
-    int grid;
-    uint64_t cap_per_block, entries;
+    int grid;                // streaming blocks
+    uint64_t slices;         // grid * STEP_WAVES: one per wave
+    uint64_t cap_per_wave;   // entries of a slice
+    uint64_t entries;        // slices * cap_per_wave
+    uint64_t deferrable;     // STEP_WAVES * chunks: the most shares a step can defer
+    int may_defer;           // cap_per_wave is below the worst case (every particle emitting)
 };
 
-static QueueShape queue_shape(const sfq_ctx* h, int nchunks, int blocks_per_cu, int chunk)
+// The queue of a step of nchunks chunks.  A wave's slice holds one share of a chunk (what one
+// chunk can add to it) plus the fraction `frac` of every particle of the wave's shares (the
+// expected emitters with headroom), at most all of them: then no share is ever deferred.
+static QueueShape queue_shape(const sfq_ctx* h, int nchunks, int blocks_per_cu, int chunk,
+                              double frac)
 {
     QueueShape q;
     q.grid = std::max(1, std::min(nchunks, h->num_cus * blocks_per_cu));
+    q.slices = (uint64_t)q.grid * STEP_WAVES;
     const uint64_t chunks_per_block = (uint64_t)((nchunks + q.grid - 1) / q.grid);
-    q.cap_per_block = chunks_per_block * (uint64_t)chunk;
-    q.entries = q.cap_per_block * (uint64_t)q.grid;
+    const uint64_t share = (uint64_t)chunk / STEP_WAVES;
+    const uint64_t worst = chunks_per_block * share;
+    const double want = (double)share + std::ceil(std::max(0.0, frac) * (double)worst);
+    q.cap_per_wave = std::max<uint64_t>(1, std::min<uint64_t>(worst, (uint64_t)want));
+    q.may_defer = q.cap_per_wave < worst ? 1 : 0;
+    q.entries = q.slices * q.cap_per_wave;
+    q.deferrable = (uint64_t)STEP_WAVES * (uint64_t)std::max(nchunks, 1);
     return q;
 }
 
 // Bytes per queue entry for the handle's form: chi, gamma, p (5 doubles) and index and tile
-// (2 uint32), plus the uid with local decisions and the two beyond-LCFA values.  Per block:
-// 2 uint32 counts, the processed count and 3 product bases.
+// (2 uint32), plus the uid with local decisions and the two beyond-LCFA values.
 static size_t queue_entry_bytes(const sfq_ctx* h)
 {
     return 48 + (h->decision == SFQ_LOCAL ? 8 : 0) + (h->blcfa ? 16 : 0);
 }
 
-static size_t queue_bytes(const sfq_ctx* h, const QueueShape& q)
+// Queue memory: the deferral words (d_ctl, the first 256 bytes), per slice 2 counts and 3
+// product bases, per block the processed count, the deferred-share list, then the entries.
+struct QueueLayout {
+    size_t count, proc, base, dlist, soa, total;
+};
+
+static QueueLayout queue_layout(const sfq_ctx* h, const QueueShape& q)
 {
-    return q.entries * queue_entry_bytes(h) + 40 * (size_t)q.grid + 256;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    QueueLayout L;
+    L.count = 256;
+    L.proc = al(L.count + 8 * q.slices);
+    L.base = al(L.proc + 8 * (size_t)q.grid);
+    L.dlist = al(L.base + 24 * q.slices);
+    L.soa = al(L.dlist + 4 * q.deferrable);
+    L.total = L.soa + q.entries * queue_entry_bytes(h);
+    return L;
 }
 
-// Emitter blocks per queue slice: enough emitter blocks to keep every compute unit busy with
-// the latency-bound emitter pass even when the streaming pass runs few, large blocks.
+static size_t queue_bytes(const sfq_ctx* h, const QueueShape& q) { return queue_layout(h, q).total; }
+
+// Emitter blocks per streaming block's slices: enough emitter blocks to keep every compute unit
+// busy with the latency-bound emitter pass even when the streaming pass runs few, large blocks.
 #ifndef SFQ_EMIT_BPC
 #define SFQ_EMIT_BPC 6
 #endif
@@ -1837,13 +2121,16 @@ static int emit_split_for(const sfq_ctx* h, int grid)
     return std::max(1, std::min(16, (h->num_cus * SFQ_EMIT_BPC) / std::max(1, grid)));
 }
 
-// The arrays of a queue of qs.entries entries at `mem` (layout of queue_entry_bytes): the
-// fields a form does not use are not allocated, and their pointers are null (the kernels
-// touch them only in the forms that use them).
-static void bind_queue(const sfq_ctx* h, StepArgs& A, void* mem, const QueueShape& qs)
+// The arrays of a queue allocated with the capacities `cap` at `mem`, bound for a step of shape
+// qs (qs fits cap): the fields a form does not use are not allocated, and their pointers are
+// null (the kernels touch them only in the forms that use them).
+static void bind_queue(const sfq_ctx* h, StepArgs& A, void* mem, const QueueShape& cap,
+                       const QueueShape& qs)
 {
-    char* q = (char*)mem;
-    const size_t E = qs.entries;
+    const QueueLayout L = queue_layout(h, cap);
+    char* base = (char*)mem;
+    char* q = base + L.soa;
+    const size_t E = cap.entries;
     A.q_chi = (double*)q;
     A.q_gamma = (double*)(q + 8 * E);
     A.q_px = (double*)(q + 16 * E);
@@ -1863,12 +2150,21 @@ static void bind_queue(const sfq_ctx* h, StepArgs& A, void* mem, const QueueShap
     }
     A.q_idx = (uint32_t*)(q + pos);
     A.q_tile = (uint32_t*)(q + pos + 4 * E);
-    pos += 8 * E;
-    A.q_count = (uint32_t*)(q + pos);
-    A.q_proc = (unsigned long long*)(q + pos + 8 * (size_t)qs.grid);
-    A.q_base = (unsigned long long*)(q + pos + 16 * (size_t)qs.grid);
-    A.q_cap_per_block = qs.cap_per_block;
+    A.d_ctl = (unsigned*)base;
+    A.q_count = (uint32_t*)(base + L.count);
+    A.q_proc = (unsigned long long*)(base + L.proc);
+    A.q_base = (unsigned long long*)(base + L.base);
+    A.d_list = (uint32_t*)(base + L.dlist);
+    A.q_cap_per_wave = qs.cap_per_wave;
     A.grid = qs.grid;
+    A.obs = nullptr;
+    A.may_defer = qs.may_defer;
+}
+
+static bool queue_fits(const QueueShape& cap, const QueueShape& qs)
+{
+    return qs.entries <= cap.entries && qs.slices <= cap.slices && qs.grid <= cap.grid &&
+           qs.deferrable <= cap.deferrable;
 }
 
 static void fill_args(const sfq_ctx* h, const sfq_step_desc* desc, StepArgs& A, int nchunks,
@@ -1923,7 +2219,31 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
     const dim3 g(grid), b(STEP_BLOCK);
     if (pe) (void)hipEventRecord(pe->e[0], st);
     const bool mixed = h->precision == SFQ_MIXED, local = h->decision == SFQ_LOCAL;
-#define SFQ_LAUNCH_PAIR(K, G)                                                                  \
+    const dim3 ge(grid * A.emit_split);
+#define SFQ_LAUNCH_FORM(K, G, M, BL, L)                                                        \
+    do {                                                                                       \
+        if (A.push) {                                                                          \
+            if (A.wave) hipLaunchKernelGGL((K<M, BL, L, true, true>), G, b, 0, st, A);         \
+            else hipLaunchKernelGGL((K<M, BL, L, true, false>), G, b, 0, st, A);               \
+        } else {                                                                               \
+            if (A.wave) hipLaunchKernelGGL((K<M, BL, L, false, true>), G, b, 0, st, A);        \
+            else hipLaunchKernelGGL((K<M, BL, L, false, false>), G, b, 0, st, A);              \
+        }                                                                                      \
+    } while (0)
+#define SFQ_LAUNCH(K, G)                                                                       \
+    do {                                                                                       \
+        if (h->blcfa) {                                                                        \
+            if (mixed) SFQ_LAUNCH_FORM(K, G, true, true, true);                                \
+            else SFQ_LAUNCH_FORM(K, G, false, true, true);                                     \
+        } else if (mixed) {                                                                    \
+            if (local) SFQ_LAUNCH_FORM(K, G, true, false, true);                               \
+            else SFQ_LAUNCH_FORM(K, G, true, false, false);                                    \
+        } else {                                                                               \
+            if (local) SFQ_LAUNCH_FORM(K, G, false, false, true);                              \
+            else SFQ_LAUNCH_FORM(K, G, false, false, false);                                   \
+        }                                                                                      \
+    } while (0)
+#define SFQ_LAUNCH_EMIT(K, G)                                                                  \
     do {                                                                                       \
         if (mixed) {                                                                           \
             if (h->blcfa) hipLaunchKernelGGL((K<true, true, true>), G, b, 0, st, A);           \
@@ -1935,33 +2255,16 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
             else hipLaunchKernelGGL((K<false, false, false>), G, b, 0, st, A);                 \
         }                                                                                      \
     } while (0)
-#define SFQ_LAUNCH_BULK(M, BL, L)                                                              \
-    do {                                                                                       \
-        if (A.push) {                                                                          \
-            if (A.wave) hipLaunchKernelGGL((bulk_kernel<M, BL, L, true, true>), g, b, 0, st, A); \
-            else hipLaunchKernelGGL((bulk_kernel<M, BL, L, true, false>), g, b, 0, st, A);     \
-        } else {                                                                               \
-            if (A.wave) hipLaunchKernelGGL((bulk_kernel<M, BL, L, false, true>), g, b, 0, st, A); \
-            else hipLaunchKernelGGL((bulk_kernel<M, BL, L, false, false>), g, b, 0, st, A);    \
-        }                                                                                      \
-    } while (0)
-    if (h->blcfa) {
-        if (mixed) SFQ_LAUNCH_BULK(true, true, true);
-        else SFQ_LAUNCH_BULK(false, true, true);
-    } else {
-        if (mixed) {
-            if (local) SFQ_LAUNCH_BULK(true, false, true);
-            else SFQ_LAUNCH_BULK(true, false, false);
-        } else {
-            if (local) SFQ_LAUNCH_BULK(false, false, true);
-            else SFQ_LAUNCH_BULK(false, false, false);
-        }
-    }
-#undef SFQ_LAUNCH_BULK
+    SFQ_LAUNCH(bulk_kernel, g);
     if (pe) (void)hipEventRecord(pe->e[1], st);
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, A);
-    SFQ_LAUNCH_PAIR(emit_kernel, dim3(grid * A.emit_split));
-#undef SFQ_LAUNCH_PAIR
+    SFQ_LAUNCH_EMIT(emit_kernel, ge);
+    // the deferred shares, when the queue may have been too small for some
+    const dim3 gd(2 * h->num_cus);
+    if (A.may_defer) SFQ_LAUNCH(defer_kernel, gd);
+#undef SFQ_LAUNCH_EMIT
+#undef SFQ_LAUNCH
+#undef SFQ_LAUNCH_FORM
     if (pe) (void)hipEventRecord(pe->e[2], st);
 }
 
@@ -2006,27 +2309,69 @@ static void plan_enqueue(sfq_plan_t* p, hipStream_t st, const ProfEvents* pe = n
 }
 
 // Grows the handle's emitter queue to hold a step of shape qs (caller holds h->mu).  Growing
-// waits for the device, since in-flight steps may still use the old queue.
+// waits for the device, since in-flight steps may still use the old queue; a new queue starts
+// with its deferral words cleared.
 static sfq_status ensure_queue(sfq_ctx* h, const QueueShape& qs, const char* who)
 {
-    if (qs.entries <= h->queue_entries && qs.grid <= h->queue_blocks) return SFQ_OK;
+    QueueShape cap;
+    cap.may_defer = 0;
+    cap.grid = (int)h->q_cap_grid;
+    cap.slices = h->q_cap_slices;
+    cap.entries = h->q_cap_entries;
+    cap.deferrable = h->q_cap_deferrable;
+    cap.cap_per_wave = 0;
+    if (h->d_queue && queue_fits(cap, qs)) return SFQ_OK;
     QueueShape want = qs;
-    want.entries = std::max<uint64_t>(qs.entries, h->queue_entries);
-    want.grid = std::max(qs.grid, h->queue_blocks);
     if (h->d_queue) {
+        want.grid = std::max(qs.grid, cap.grid);
+        want.slices = std::max(qs.slices, cap.slices);
+        want.entries = std::max(qs.entries, cap.entries);
+        want.deferrable = std::max(qs.deferrable, cap.deferrable);
         HIP_TRY(h, hipDeviceSynchronize());
         HIP_TRY(h, hipFree(h->d_queue));
         h->d_queue = nullptr;
-        h->queue_entries = 0;
-        h->queue_blocks = 0;
+        h->q_cap_grid = h->q_cap_slices = h->q_cap_entries = h->q_cap_deferrable = 0;
     }
     if (hipMalloc(&h->d_queue, queue_bytes(h, want)) != hipSuccess) {
         h->d_queue = nullptr;
         return fail(h, SFQ_E_NOMEM, std::string(who) + ": cannot allocate the emitter queue");
     }
-    h->queue_entries = want.entries;
-    h->queue_blocks = want.grid;
+    HIP_TRY(h, hipMemset(h->d_queue, 0, 256));
+    h->q_cap_grid = (uint64_t)want.grid;
+    h->q_cap_slices = want.slices;
+    h->q_cap_entries = want.entries;
+    h->q_cap_deferrable = want.deferrable;
     return SFQ_OK;
+}
+
+static QueueShape queue_capacity(const sfq_ctx* h)
+{
+    QueueShape cap;
+    cap.may_defer = 0;
+    cap.grid = (int)h->q_cap_grid;
+    cap.slices = h->q_cap_slices;
+    cap.entries = h->q_cap_entries;
+    cap.deferrable = h->q_cap_deferrable;
+    cap.cap_per_wave = 0;
+    return cap;
+}
+
+// What the last completed steps observed (the largest emitter fraction of a wave's share,
+// shares deferred): the queue grows to twice the observed fraction, faster after deferrals
+// (caller holds h->mu).  The observation may be a step or two old; sizing never changes results.
+static void adapt_queue(sfq_ctx* h)
+{
+    if (!h->q_adaptive || !h->obs_host) return;
+    volatile unsigned* o = h->obs_host;
+    const unsigned fb = o[0], nd = o[1];
+    if (!(fb | nd)) return;
+    float f;
+    memcpy(&f, &fb, sizeof f);
+    double want = 2.0 * (double)f;
+    if (nd) want = std::max(4.0 * (double)f, 2.0 * h->q_frac);
+    if (want > h->q_frac) h->q_frac = std::min(1.0, want);
+    o[0] = 0;
+    o[1] = 0;
 }
 
 extern "C" {
@@ -2038,9 +2383,34 @@ sfq_status sfq_reserve(sfq_handle h, uint64_t max_particles, int max_tiles)
         return fail(h, SFQ_E_ARG, "sfq_reserve: max_tiles in [1, SFQ_MAX_TILES]");
     std::lock_guard<std::mutex> lock(h->mu);
     const uint64_t nch = (max_particles + h->chunk - 1) / h->chunk + (uint64_t)max_tiles;
-    if (nch >= (1ull << 31)) return fail(h, SFQ_E_CAPACITY, "sfq_reserve: too many particles");
+    if (nch >= (1ull << 29)) return fail(h, SFQ_E_CAPACITY, "sfq_reserve: too many particles");
     HIP_TRY(h, hipSetDevice(h->device));
-    return ensure_queue(h, queue_shape(h, (int)nch, h->blocks_per_cu, h->chunk), "sfq_reserve");
+    return ensure_queue(h, queue_shape(h, (int)nch, h->blocks_per_cu, h->chunk, h->q_frac),
+                        "sfq_reserve");
+}
+
+sfq_status sfq_set_queue(sfq_handle h, double expected_fraction, int adaptive)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_set_queue: NULL handle");
+    if (!(expected_fraction >= 0.0 && expected_fraction <= 1.0) || (adaptive != 0 && adaptive != 1))
+        return fail(h, SFQ_E_ARG, "sfq_set_queue: expected_fraction in [0, 1], adaptive 0 or 1");
+    std::lock_guard<std::mutex> lock(h->mu);
+    h->q_frac = std::min(1.0, 2.0 * expected_fraction);
+    h->q_adaptive = adaptive;
+    if (h->obs_host) {
+        h->obs_host[0] = 0;
+        h->obs_host[1] = 0;
+    }
+    return SFQ_OK;
+}
+
+sfq_status sfq_queue_bytes(sfq_handle h, uint64_t* bytes)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_queue_bytes: NULL handle");
+    if (!bytes) return fail(h, SFQ_E_ARG, "sfq_queue_bytes: NULL output");
+    std::lock_guard<std::mutex> lock(h->mu);
+    *bytes = h->d_queue ? (uint64_t)queue_bytes(h, queue_capacity(h)) : 0;
+    return SFQ_OK;
 }
 
 sfq_status sfq_profile_enable(sfq_handle h, int enable)
@@ -2131,7 +2501,8 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
         }
         return SFQ_OK;
     }
-    const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk);
+    adapt_queue(h);
+    const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk, h->q_frac);
     {
         const sfq_status q = ensure_queue(h, qs, "sfq_step");
         if (q != SFQ_OK) return q;
@@ -2147,13 +2518,18 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     memcpy(db.data() + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
     if (desc->nsets > 0)
         memcpy(db.data() + set_pos, desc->product_sets, desc->nsets * sizeof(sfq_product_set));
+    // steps on different streams share the emitter queue: order them on the device
+    if (h->any_step && h->last_stream != (hipStream_t)stream)
+        HIP_TRY(h, hipStreamWaitEvent((hipStream_t)stream, h->last_end, 0));
     // The same descriptors as the last upload: the kernels read that device copy again, with
     // no copy from the host (a copy costs a transfer and its dispatch latency on every step).
-    // Device copies are read-only; a slot is overwritten only after the last step that used it
-    // (its event).
+    // Device copies are read-only; a slot is overwritten only after the last step that used it.
     const bool reuse = h->last_slot >= 0 && h->last_desc == db;
     Staging& S = h->staging[reuse ? h->last_slot : h->next_staging];
     if (!reuse) {
+        // the slot left behind: every step that read it ends before this point of the stream
+        if (h->last_slot >= 0)
+            HIP_TRY(h, hipEventRecord(h->staging[h->last_slot].done, (hipStream_t)stream));
         const int slot = h->next_staging;
         h->next_staging = (h->next_staging + 1) % N_STAGING;
         if (!S.host) {
@@ -2170,29 +2546,31 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
         h->last_slot = slot;
         h->last_desc.swap(db);
     }
-    // steps on different streams share the emitter queue: order them on the device
-    if (!h->queue_free)
-        HIP_TRY(h, hipEventCreateWithFlags(&h->queue_free, hipEventDisableTiming));
-    if (h->queue_used && h->queue_stream != (hipStream_t)stream)
-        HIP_TRY(h, hipStreamWaitEvent((hipStream_t)stream, h->queue_free, 0));
-    // the queue shape must describe the allocation actually bound
-    QueueShape bound = qs;
-    bound.entries = h->queue_entries;
+    if (!h->step_done)
+        HIP_TRY(h, hipEventCreateWithFlags(&h->step_done, hipEventDisableTiming));
     StepArgs A;
     fill_args(h, desc, A, nchunks, chunk);
     A.tiles = (const sfq_tile*)S.dev;
     A.chunk_off = (const uint32_t*)((char*)S.dev + off_pos);
     if (desc->nsets > 0) A.sets = (const sfq_product_set*)((char*)S.dev + set_pos);
-    bind_queue(h, A, h->d_queue, bound);
-    A.q_cap_per_block = qs.cap_per_block;
+    bind_queue(h, A, h->d_queue, queue_capacity(h), qs);
+    A.obs = h->obs_dev;
     A.emit_split = emit_split_for(h, qs.grid);
     if (desc->zero_product_counts) enqueue_zero_counts(A, (hipStream_t)stream);
-    launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, prof_events(h));
+    const ProfEvents* pe = prof_events(h);
+    launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, pe);
     HIP_TRY(h, hipGetLastError());
-    HIP_TRY(h, hipEventRecord(S.done, (hipStream_t)stream));
-    HIP_TRY(h, hipEventRecord(h->queue_free, (hipStream_t)stream));
-    h->queue_stream = (hipStream_t)stream;
-    h->queue_used = true;
+    // the step's end: its timing event when it is timed (recorded by the launch), else step_done
+    // (a timing event recycled after sfq_profile_read and recorded again by a later step then
+    // marks a later point of the same handle's ordered steps: waiting for it stays correct)
+    if (pe) {
+        h->last_end = pe->e[2];
+    } else {
+        HIP_TRY(h, hipEventRecord(h->step_done, (hipStream_t)stream));
+        h->last_end = h->step_done;
+    }
+    h->last_stream = (hipStream_t)stream;
+    h->any_step = true;
     return SFQ_OK;
 }
 
@@ -2211,7 +2589,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     const int nchunks = (int)off[nt];
     if (nchunks == 0) return fail(h, SFQ_E_ARG, "sfq_plan_create: no particles");
     HIP_TRY(h, hipSetDevice(h->device));
-    const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk);
+    const QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk, h->q_frac);
     const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
     const size_t set_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
     const size_t step_pos =
@@ -2233,6 +2611,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     const unsigned long long step0 = desc->step;
     memcpy(hostbuf.data() + step_pos, &step0, 8);
     if (hipMemcpy(p->d_mem, hostbuf.data(), step_pos + 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset((char*)p->d_mem + q_pos, 0, 256) != hipSuccess ||
         hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         plan_release(p);
         return fail(h, SFQ_E_DEVICE, "sfq_plan_create: device setup failed");
@@ -2245,7 +2624,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     p->A.chunk_off = (const uint32_t*)((char*)p->d_mem + off_pos);
     p->A.step_ptr = p->d_step;
     if (desc->nsets > 0) p->A.sets = (const sfq_product_set*)((char*)p->d_mem + set_pos);
-    bind_queue(h, p->A, (char*)p->d_mem + q_pos, qs);
+    bind_queue(h, p->A, (char*)p->d_mem + q_pos, qs, qs);
     p->A.emit_split = emit_split_for(h, qs.grid);
     *out = p;
     return SFQ_OK;

@@ -21,6 +21,11 @@ namespace sfq {
 // Table geometry (identical to the generator's; checked when the table file is loaded).
 // ---------------------------------------------------------------------------------------------
 constexpr int RATE_DEG = 16;
+// The truncated evaluation form (an accuracy/speed dial, the analogue of the paper's choice of
+// coefficient counts, Sec. 4.5): the leading RATE_DEG_TRUNC terms of each rate segment and the
+// leading INV_TRUNC x INV_TRUNC coefficients of each inverse patch, from the same tables.
+constexpr int RATE_DEG_TRUNC = 10;
+constexpr int INV_TRUNC = 5;
 constexpr int CHI_OCT_LO = -6, CHI_OCT_HI = 16;
 constexpr int N_CHI_SEG = 1 + (CHI_OCT_HI - CHI_OCT_LO);
 constexpr int PAIR_OCT_LO = -7;
@@ -346,9 +351,10 @@ __device__ __forceinline__ T pow_asym(T chi, float a)
 // ---------------------------------------------------------------------------------------------
 // Rates.  `rad` and `pair` point to the (LDS-staged) coefficient tables.
 // ---------------------------------------------------------------------------------------------
-// W~_rad(chi) (Sec. 4.1, Eq. (wtilde)); sets *ood when chi is beyond the tables
+// W~_rad(chi) (Sec. 4.1, Eq. (wtilde)); sets *ood when chi is beyond the tables.  trunc (the
+// same in every lane): the leading RATE_DEG_TRUNC terms only.
 template <typename T, typename P>
-__device__ __forceinline__ T wtilde_rad(const P* rad, T chi, bool* ood)
+__device__ __forceinline__ T wtilde_rad(const P* rad, T chi, bool* ood, bool trunc)
 {
     int seg;
     T X;
@@ -356,12 +362,13 @@ __device__ __forceinline__ T wtilde_rad(const P* rad, T chi, bool* ood)
         *ood = true;
         return T(WRAD_ASYM_C1) * pow_asym(chi, -1.0f / 3.0f) - T(WRAD_ASYM_C2) / chi;
     }
-    return clenshaw<RATE_DEG>(rad + seg * RATE_DEG, X);
+    const P* c = rad + seg * RATE_DEG;
+    return trunc ? clenshaw<RATE_DEG_TRUNC>(c, X) : clenshaw<RATE_DEG>(c, X);
 }
 
 // W~_pair(chi) (Sec. 4.2, Eq. (wtilde_pair)) for chi >= 2^PAIR_OCT_LO
 template <typename T, typename P>
-__device__ __forceinline__ T wtilde_pair(const P* pair, T chi, bool* ood)
+__device__ __forceinline__ T wtilde_pair(const P* pair, T chi, bool* ood, bool trunc)
 {
     int seg;
     T X;
@@ -369,7 +376,8 @@ __device__ __forceinline__ T wtilde_pair(const P* pair, T chi, bool* ood)
         *ood = true;
         return T(WPAIR_ASYM_C) * pow_asym(chi, 2.0f / 3.0f);
     }
-    const T P_ = clenshaw<RATE_DEG>(pair + seg * RATE_DEG, X);
+    const P* c = pair + seg * RATE_DEG;
+    const T P_ = trunc ? clenshaw<RATE_DEG_TRUNC>(c, X) : clenshaw<RATE_DEG>(c, X);
     return chi * P_ * exp_nonpos(T(-8.0 / 3.0) / chi);
 }
 
@@ -501,8 +509,11 @@ __device__ __forceinline__ int kth_set_bit(unsigned long long mask, int k)
 // xor shuffles.  A wave runs ceil(active lanes / 8) rounds (rounded up to even), so partly
 // filled waves and rare re-evaluations cost only what they use.  Every lane of the wave must
 // call it.
+// With trunc (the same in every lane), the leading INV_TRUNC x INV_TRUNC coefficients: lanes
+// m >= INV_TRUNC of a group load nothing and add zero.
 template <typename T>
-__device__ __forceinline__ T coop_patch_eval(const T* table, int patch, T Xr, T Xc, bool active)
+__device__ __forceinline__ T coop_patch_eval(const T* table, int patch, T Xr, T Xc, bool active,
+                                             bool trunc)
 {
     const int L = __lane_id();
     const int g = L >> 3, m = L & 7;
@@ -522,14 +533,26 @@ __device__ __forceinline__ T coop_patch_eval(const T* table, int patch, T Xr, T 
         const T xr1 = __shfl(Xr, s1), xc1 = __shfl(Xc, s1);
         const T* c0 = table + (size_t)p0 * INV_PATCH + m;
         const T* c1 = table + (size_t)p1 * INV_PATCH + m;
-        T col0[INV_NR], col1[INV_NR];
+        T v0 = T(0), v1 = T(0);
+        if (!trunc) {
+            T col0[INV_NR], col1[INV_NR];
 #pragma unroll
-        for (int i = 0; i < INV_NR; ++i) {
-            col0[i] = c0[i * INV_NC];
-            col1[i] = c1[i * INV_NC];
+            for (int i = 0; i < INV_NR; ++i) {
+                col0[i] = c0[i * INV_NC];
+                col1[i] = c1[i * INV_NC];
+            }
+            v0 = clenshaw<INV_NR>(col0, xr0) * cheb_T(m, xc0);
+            v1 = clenshaw<INV_NR>(col1, xr1) * cheb_T(m, xc1);
+        } else if (m < INV_TRUNC) {
+            T col0[INV_TRUNC], col1[INV_TRUNC];
+#pragma unroll
+            for (int i = 0; i < INV_TRUNC; ++i) {
+                col0[i] = c0[i * INV_NC];
+                col1[i] = c1[i * INV_NC];
+            }
+            v0 = clenshaw<INV_TRUNC>(col0, xr0) * cheb_T(m, xc0);
+            v1 = clenshaw<INV_TRUNC>(col1, xr1) * cheb_T(m, xc1);
         }
-        T v0 = clenshaw<INV_NR>(col0, xr0) * cheb_T(m, xc0);
-        T v1 = clenshaw<INV_NR>(col1, xr1) * cheb_T(m, xc1);
         v0 += __shfl_xor(v0, 1);
         v1 += __shfl_xor(v1, 1);
         v0 += __shfl_xor(v0, 2);

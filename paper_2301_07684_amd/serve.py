@@ -7,7 +7,8 @@ step per tick of their own time loop.  The server
   buffers) fits the HBM budget.  Admission is first-come first-served, so a large simulation is
   not overtaken forever by small ones;
 * batches every step request that is ready into one ``sfq_step`` call on a free lane.  A lane is
-  a HIP stream with its own library handle and emitter queue, reserved once.  Each simulation's
+  a HIP stream with its own library handle and emitter queue, reserved once and charged to the
+  HBM budget.  Each simulation's
   tiles carry their own Philox step offset and product set, so its results do not depend on
   what it was batched with (draws depend only on seed, uid, step and purpose);
 * keeps one batch in flight per lane, so requests that become ready while others run on the GPU
@@ -42,6 +43,9 @@ PRODUCT_BYTES = 6 * 8                      # p, tau, uid, parent
 # 8 x 2048, 3 x 4096, 4 x 2048 and 3 x 2048 on the served workload (batches of about 24M
 # particles in beyond-LCFA kernels of 3 waves per SIMD), by a few percent
 LANE_LAUNCH = (4, 2048)
+# expected emitter fraction the lanes' emitter queues are sized for (fixed, so that their memory
+# is known when admitting; a batch with more emitters is still stepped exactly, more slowly)
+LANE_QUEUE_FRACTION = 1.0 / 16.0
 
 
 @dataclass
@@ -229,14 +233,21 @@ class Server:
         self.dev = dev or torch.device("cuda", 0)
         self.seed, self.on_step = seed, on_step
         self.dt = inputs.DT
-        self.sched = Scheduler(hbm_budget, max_batch_particles, max_batch_tiles)
         self.lanes: List[Lane] = []
         for _ in range(lanes):
             h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=self.dt, precision=precision,
                            decision=sfq.LOCAL, blcfa=True, device=self.dev.index or 0)
             h.set_launch(*launch)
+            h.set_queue(LANE_QUEUE_FRACTION, adaptive=False)
             h.reserve(max_batch_particles, max_batch_tiles)
             self.lanes.append(Lane(h, torch.cuda.Stream(device=self.dev), sfq.Counters(self.dev)))
+        # the lanes' emitter queues are charged to the budget before any simulation
+        self.queue_bytes = sum(lane.handle.queue_bytes() for lane in self.lanes)
+        if self.queue_bytes >= hbm_budget:
+            raise ValueError(f"the lanes' emitter queues ({self.queue_bytes} B) do not fit the "
+                             f"HBM budget of {hbm_budget} B")
+        self.sched = Scheduler(hbm_budget - self.queue_bytes, max_batch_particles,
+                               max_batch_tiles)
         self.client_streams = [torch.cuda.Stream(device=self.dev) for _ in range(clients)]
         self.pending: List[JobSpec] = []
         self.active: Dict[int, Simulation] = {}
@@ -346,7 +357,7 @@ class Server:
                     batches=len(self.batch_sizes),
                     admission_wait_p50_ms=percentile(self.admission_waits, 50) * 1e3,
                     admission_wait_max_ms=max(self.admission_waits, default=0.0) * 1e3,
-                    waited=len(self.sched.deferred))
+                    waited=len(self.sched.deferred), lane_queue_bytes=self.queue_bytes)
 
     def close(self):
         for lane in self.lanes:

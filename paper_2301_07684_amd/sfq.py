@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libsfq.so")
 ELECTRON, POSITRON, PHOTON = 0, 1, 2
 FP64, MIXED = 0, 1
 OPTICAL_DEPTH, LOCAL = 0, 1
+APPROX_FULL, APPROX_TRUNCATED = 0, 1
 FIELDS_ARRAYS, FIELDS_UNIFORM, FIELDS_PLANE_WAVE = 0, 1, 2
 P_INIT, P_EMIT, P_CHILD, P_CHILD2, P_LOCAL = 0, 1, 2, 3, 4
 MAX_TILES = 4096
@@ -33,13 +34,14 @@ EXPORTS = ("sfq_create", "sfq_destroy", "sfq_last_error", "sfq_units", "sfq_chi"
            "sfq_sample_photon", "sfq_sample_pair", "sfq_philox", "sfq_init_optical_depth",
            "sfq_step", "sfq_set_launch", "sfq_get_launch", "sfq_plan_create", "sfq_plan_destroy",
            "sfq_plan_launch", "sfq_plan_set_step", "sfq_plan_capture", "sfq_plan_replay",
-           "sfq_reserve", "sfq_profile_enable", "sfq_profile_read", "sfq_profile_read_steps")
+           "sfq_reserve", "sfq_set_queue", "sfq_queue_bytes", "sfq_profile_enable",
+           "sfq_profile_read", "sfq_profile_read_steps")
 
 
 class Config(C.Structure):
     _fields_ = [("ref_omega", C.c_double), ("ref_length", C.c_double), ("dt", C.c_double),
                 ("precision", C.c_int32), ("decision", C.c_int32), ("blcfa", C.c_int32),
-                ("bw_fast", C.c_int32), ("device", C.c_int32), ("reserved", C.c_int32),
+                ("bw_fast", C.c_int32), ("device", C.c_int32), ("approx", C.c_int32),
                 ("tables_path", C.c_char_p)]
 
 
@@ -79,7 +81,7 @@ class StepDesc(C.Structure):
 _TILE_POINTERS = tuple(nm for nm, _ in Tile._fields_[3:23])
 
 COUNTER_NAMES = ("processed", "emitted", "converted", "blcfa_rejected", "out_of_domain",
-                 "clamped", "overflow", "reserved")
+                 "clamped", "overflow", "deferred")
 
 _lib = None
 
@@ -134,6 +136,10 @@ def load(path: str = LIB_PATH):
     L.sfq_plan_replay.argtypes = [vp, vp]
     L.sfq_reserve.restype = st
     L.sfq_reserve.argtypes = [vp, u64, C.c_int]
+    L.sfq_set_queue.restype = st
+    L.sfq_set_queue.argtypes = [vp, C.c_double, C.c_int]
+    L.sfq_queue_bytes.restype = st
+    L.sfq_queue_bytes.argtypes = [vp, C.POINTER(C.c_uint64)]
     L.sfq_profile_enable.restype = st
     L.sfq_profile_enable.argtypes = [vp, C.c_int]
     L.sfq_profile_read.restype = st
@@ -177,17 +183,18 @@ class Handle:
     def __init__(self, *, ref_length: float | None = None, ref_omega: float | None = None,
                  dt: float, precision: int = FP64, decision: int = OPTICAL_DEPTH,
                  blcfa: bool = False, bw_fast: bool = False, device: int = 0,
-                 tables_path: str | None = None):
+                 tables_path: str | None = None, approx: int = APPROX_FULL):
         self._L = load()
         cfg = Config(ref_omega=ref_omega or 0.0, ref_length=ref_length or 0.0, dt=dt,
                      precision=precision, decision=decision, blcfa=int(blcfa),
-                     bw_fast=int(bw_fast), device=device, reserved=0,
+                     bw_fast=int(bw_fast), device=device, approx=int(approx),
                      tables_path=None if tables_path is None else tables_path.encode())
         h = C.c_void_p()
         self._check(self._L.sfq_create(C.byref(cfg), C.byref(h)))
         self._h = h
         self.profiling = False
         self.precision, self.decision, self.blcfa, self.bw_fast = precision, decision, blcfa, bw_fast
+        self.approx = approx
         self.device = torch.device("cuda", device)
         lc, lr = C.c_double(), C.c_double()
         self._check(self._L.sfq_units(self._h, C.byref(lc), C.byref(lr)))
@@ -220,6 +227,18 @@ class Handle:
     def reserve(self, max_particles: int, max_tiles: int = 1):
         """Pre-size the emitter queue so steps within these limits allocate nothing."""
         self._check(self._L.sfq_reserve(self._h, max_particles, max_tiles))
+
+    def set_queue(self, expected_fraction: float, adaptive: bool = True):
+        """Emitter-queue sizing: the fraction of a step's particles expected to emit (slices hold
+        twice that plus one share of a chunk), grown from observations when `adaptive`.  Shares
+        that do not fit are stepped by a further kernel of the same step: same results."""
+        self._check(self._L.sfq_set_queue(self._h, float(expected_fraction), int(bool(adaptive))))
+
+    def queue_bytes(self) -> int:
+        """Device bytes the emitter queue holds now."""
+        v = C.c_uint64()
+        self._check(self._L.sfq_queue_bytes(self._h, C.byref(v)))
+        return v.value
 
     def profile(self, enable: bool = True):
         """Start/stop timing the two step kernels of every step with HIP events."""
@@ -521,3 +540,8 @@ class Counters:
     def as_dict(self):
         v = self.t.cpu().tolist()
         return dict(zip(COUNTER_NAMES, v))
+
+    def results(self):
+        """The counters that describe the step's results: all but `deferred`, which depends on
+        how the work was scheduled (the size of the emitter queue), not on the results."""
+        return {k: v for k, v in self.as_dict().items() if k != "deferred"}

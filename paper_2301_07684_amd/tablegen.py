@@ -70,6 +70,13 @@ T_MAX = 2.0 ** T_OCT_HI
 
 MAGIC = b"SFQTAB03"
 
+# The truncated evaluation form (the accuracy/speed dial, the analogue of the paper's choice of
+# coefficient counts, Sec. 4.5): the kernels may evaluate only the leading RATE_DEG_TRUNC terms
+# of every rate segment and the leading INV_TRUNC x INV_TRUNC coefficients of every inverse
+# patch.  The same tables serve both forms; the errors of each form are measured below.
+RATE_DEG_TRUNC = 10
+INV_TRUNC = 5
+
 
 # ------------------------------------------------------------------------------------------------
 # Chebyshev utilities (first-kind nodes; coefficients with c_0 already halved, so that
@@ -92,12 +99,32 @@ def cheb_coeffs_from_values(vals, axis=-1):
 
 
 def cheb_eval(c, X):
-    """Clenshaw's recurrence (paper App. B) for coefficient vectors c[..., n] at X (broadcast)."""
-    b1 = np.zeros(np.broadcast(X, c[..., 0]).shape)
+    """Clenshaw's recurrence (paper App. B) for coefficient vectors c[..., n] at X (broadcast),
+    in the floating-point type of c and X (float64, or float32 to measure the FP32 form)."""
+    dt = np.result_type(c, X)
+    X = np.asarray(X, dtype=dt)
+    b1 = np.zeros(np.broadcast(X, c[..., 0]).shape, dtype=dt)
     b2 = np.zeros_like(b1)
+    two = dt.type(2.0)
     for k in range(c.shape[-1] - 1, 0, -1):
-        b1, b2 = 2.0 * X * b1 - b2 + c[..., k], b1
+        b1, b2 = two * X * b1 - b2 + c[..., k], b1
     return X * b1 - b2 + c[..., 0]
+
+
+def truncate_rates(tab):
+    """A rate table with only its leading RATE_DEG_TRUNC terms per segment (the rest zero: the
+    same values as a recurrence over the leading terms)."""
+    t = np.array(tab, dtype=np.float64)
+    t[..., RATE_DEG_TRUNC:] = 0.0
+    return t
+
+
+def truncate_patches(tab):
+    """An inverse table with only the leading INV_TRUNC x INV_TRUNC coefficients per patch."""
+    t = np.array(tab, dtype=np.float64)
+    t[..., INV_TRUNC:, :] = 0.0
+    t[..., :, INV_TRUNC:] = 0.0
+    return t
 
 
 def to_unit(x, a, b):
@@ -313,21 +340,22 @@ def build_rate_tables():
     return rad, pair
 
 
-def eval_rad(rad, chi):
+def eval_rad(rad, chi, dtype=np.float64):
     chi = np.asarray(chi, dtype=np.float64)
     seg = np.where(chi < 2.0 ** CHI_OCT_LO, 0,
                    np.floor(np.log2(np.maximum(chi, 1e-300))).astype(int) - CHI_OCT_LO + 1)
     seg = np.clip(seg, 0, N_CHI_SEG - 1)
     a = np.where(seg == 0, 0.0, 2.0 ** (seg - 1 + CHI_OCT_LO))
     b = np.where(seg == 0, 2.0 ** CHI_OCT_LO, 2 * a)
-    return cheb_eval(rad[seg], to_unit(chi, a, b))
+    return cheb_eval(rad[seg].astype(dtype), to_unit(chi, a, b).astype(dtype))
 
 
-def eval_pair_scaled(pair, chi):
+def eval_pair_scaled(pair, chi, dtype=np.float64):
     chi = np.asarray(chi, dtype=np.float64)
     o = np.clip(np.floor(np.log2(chi)).astype(int), PAIR_OCT_LO, CHI_OCT_HI - 1)
     a = 2.0 ** o
-    return chi * cheb_eval(pair[o - PAIR_OCT_LO], to_unit(chi, a, 2 * a))
+    return chi.astype(dtype) * cheb_eval(pair[o - PAIR_OCT_LO].astype(dtype),
+                                         to_unit(chi, a, 2 * a).astype(dtype))
 
 
 # ------------------------------------------------------------------------------------------------
@@ -499,19 +527,19 @@ def r_segment(r):
     return seg, X, upper, t
 
 
-def eval_inverse_2d(tab, chi, r):
+def eval_inverse_2d(tab, chi, r, dtype=np.float64):
     """Evaluate a [chi seg][r seg][NR][NC] table: returns the tabulated function value."""
     cs, Xc = chi_segment(chi)
     rs, Xr, up, t = r_segment(r)
-    c = tab[cs, rs]                                   # (n, NR, NC)
-    d = cheb_eval(c, Xc[:, None])                     # inner along chi -> (n, NR)
-    return cheb_eval(d, Xr), up, t
+    c = tab[cs, rs].astype(dtype)                     # (n, NR, NC)
+    d = cheb_eval(c, Xc[:, None].astype(dtype))       # inner along chi -> (n, NR)
+    return cheb_eval(d, Xr.astype(dtype)), up, t
 
 
-def eval_photon_xbar(tab, chi, r):
+def eval_photon_xbar(tab, chi, r, dtype=np.float64):
     """wbar^3 from the photon table."""
-    f, up, t = eval_inverse_2d(tab, chi, r)
-    r = np.asarray(r, dtype=np.float64)
+    f, up, t = eval_inverse_2d(tab, chi, r, dtype)
+    r = np.asarray(r, dtype=np.float64).astype(dtype)
     return np.where(up, np.exp(f), (f * r) ** 3)
 
 
@@ -615,15 +643,46 @@ def pair_chi_segment(chi):
     return seg, X
 
 
-def eval_pair_y(tab, chi, r):
+def eval_pair_y(tab, chi, r, dtype=np.float64):
     """y = eta_v - eta0 for the pair sample with uniform r (r' = 2r - 1, q = |r'|)."""
     chi, r = np.asarray(chi, dtype=np.float64), np.asarray(r, dtype=np.float64)
     q = np.abs(2.0 * r - 1.0)
     cs, Xc = pair_chi_segment(chi)
     rs, Xr, up, t = r_segment(q)
-    d = cheb_eval(tab[cs, rs], Xc[:, None])
-    f = cheb_eval(d, Xr)
-    return np.where(up, np.exp(f), (f * q) ** 2)
+    d = cheb_eval(tab[cs, rs].astype(dtype), Xc[:, None].astype(dtype))
+    f = cheb_eval(d, Xr.astype(dtype))
+    qd = q.astype(dtype)
+    return np.where(up, np.exp(f), (f * qd) ** 2)
+
+
+def photon_sample_forms(tab, chi, r):
+    """wbar^3 as each evaluation form gives it: FP64 or FP32 arithmetic (the FP32 form re-
+    evaluating in FP64 where the energy fraction exceeds 0.999, s = 3 chi wbar^3/2 > 999, as
+    the kernels do), full or truncated patches."""
+    out = {}
+    for trunc in (False, True):
+        t = truncate_patches(tab) if trunc else tab
+        x64 = eval_photon_xbar(t, chi, r)
+        x32 = eval_photon_xbar(t, chi, r, np.float32).astype(np.float64)
+        s32 = 1.5 * np.asarray(chi) * x32
+        out[("fp64", trunc)] = x64
+        out[("mixed", trunc)] = np.where(s32 > 999.0, x64, x32)
+    return out
+
+
+def pair_sample_forms(tab, chi, r):
+    """y as each evaluation form gives it (the FP32 form re-evaluating in FP64 where
+    v = sqrt(y/(y + eta0)) exceeds 0.998)."""
+    out = {}
+    eta0 = 8.0 / (3.0 * np.asarray(chi, dtype=np.float64))
+    for trunc in (False, True):
+        t = truncate_patches(tab) if trunc else tab
+        y64 = eval_pair_y(t, chi, r)
+        y32 = eval_pair_y(t, chi, r, np.float32).astype(np.float64)
+        v32 = np.sqrt(y32 / (y32 + eta0))
+        out[("fp64", trunc)] = y64
+        out[("mixed", trunc)] = np.where(v32 > 0.998, y64, y32)
+    return out
 
 
 # ------------------------------------------------------------------------------------------------
@@ -632,7 +691,7 @@ def eval_pair_y(tab, chi, r):
 GEOMETRY = ("RATE_DEG", "CHI_OCT_LO", "CHI_OCT_HI", "N_CHI_SEG", "PAIR_OCT_LO", "N_PAIR_SEG",
             "KA_DEG", "N_KA", "KB_DEG", "KB_OCT_LO", "KB_OCT_HI", "INV_NC", "INV_NR", "N_LO_SEG",
             "T_OCT_LO", "T_OCT_HI", "N_HI_SEG", "N_R_SEG", "SUB", "INV_CHI_OCT_LO", "N_INV_CHI",
-            "N_PAIR_INV_CHI")
+            "N_PAIR_INV_CHI", "RATE_DEG_TRUNC", "INV_TRUNC")
 
 
 def source_hash() -> int:
@@ -678,12 +737,20 @@ def _pair_segment(cs):
     return cheb_coeffs_from_values(c, axis=2)
 
 
+FORMS = (("fp64", False), ("fp64", True), ("mixed", False), ("mixed", True))
+
+
+def form_name(prec, trunc):
+    return prec + ("_trunc" if trunc else "")
+
+
 def _check_segment(args):
-    """Max relative error of the inverse tables against fresh exact inversions in one segment."""
+    """Max relative error of the inverse tables against fresh exact inversions in one segment,
+    for every evaluation form (the full-table FP64 value is the tables' own error)."""
     kind, cs, tab, seed = args
     bt = BesselTables()
     rng = np.random.default_rng(seed)
-    worst = 0.0
+    worst = {form_name(*f): 0.0 for f in FORMS}
     if kind == "photon":
         ca, cb = _inv_chi_segment_bounds(cs)
     else:
@@ -697,14 +764,16 @@ def _check_segment(args):
         if kind == "photon":
             ps = PhotonSpectrum(bt, chi)
             ex = np.concatenate([ps.inverse(r_lo, False), ps.inverse(omr, True)]) ** 3
-            ap = eval_photon_xbar(tab, np.full(80, chi), np.concatenate([r_lo, r_hi]))
+            forms = photon_sample_forms(tab, np.full(80, chi), np.concatenate([r_lo, r_hi]))
         else:
             ps = PairSpectrum(bt, chi)
             r = np.concatenate([0.5 + 0.5 * r_lo, 0.5 + 0.5 * r_hi])
             q = np.abs(2.0 * r - 1.0)          # the level the sampler sees (exact in double)
             ex = np.concatenate([ps.inverse(q[:40], False), ps.inverse(1.0 - q[40:], True)]) ** 2
-            ap = eval_pair_y(tab, np.full(80, chi), r)
-        worst = max(worst, float(np.max(np.abs(ap / ex - 1))))
+            forms = pair_sample_forms(tab, np.full(80, chi), r)
+        for f, ap in forms.items():
+            name = form_name(*f)
+            worst[name] = max(worst[name], float(np.max(np.abs(ap / ex - 1))))
     return kind, cs, worst
 
 
@@ -723,15 +792,40 @@ def build_all(jobs=8, verbose=True):
         checks = [("photon", cs, phinv, 100 + cs) for cs in range(N_INV_CHI)]
         checks += [("pair", cs, ppinv, 1000 + cs) for cs in range(N_PAIR_INV_CHI)]
         errs = list(ex.map(_check_segment, checks))
-    chi = np.concatenate([np.geomspace(1e-9, 2.0 ** CHI_OCT_HI * 0.999, 500),
-                          np.linspace(0, 2.0 ** CHI_OCT_LO, 60)[1:]])
-    rad_err = float(np.max(np.abs(eval_rad(rad, chi) / wrad_exact(chi) - 1)))
-    chi = np.geomspace(2.0 ** PAIR_OCT_LO, 2.0 ** CHI_OCT_HI * 0.999, 500)
-    pair_err = float(np.max(np.abs(eval_pair_scaled(pair, chi) / pair_scaled_exact(chi) - 1)))
+    chi_r = np.concatenate([np.geomspace(1e-9, 2.0 ** CHI_OCT_HI * 0.999, 500),
+                            np.linspace(0, 2.0 ** CHI_OCT_LO, 60)[1:]])
+    chi_p = np.geomspace(0.01, 2.0 ** CHI_OCT_HI * 0.999, 500)
+    ex_r = wrad_exact(chi_r)
+    ex_p = np.exp(-8.0 / (3.0 * chi_p)) * pair_scaled_exact(chi_p)   # W~_pair itself
+    forms = {}
+    for prec, trunc in FORMS:
+        dt = np.float32 if prec == "mixed" else np.float64
+        rt, pt = (truncate_rates(rad), truncate_rates(pair)) if trunc else (rad, pair)
+        e_r = float(np.max(np.abs(eval_rad(rt, chi_r, dt).astype(np.float64) / ex_r - 1)))
+        # W~_pair as the kernels form it, e^{-8/(3 chi)} included, in the form's precision: the
+        # rounding of the exponent's argument costs |8/(3 chi)| units in the last place; where
+        # the single-precision value underflows (chi below about 0.03, W~_pair < 1e-38) the
+        # kernels' result is compared with an absolute tolerance instead
+        cp = chi_p.astype(dt)
+        wp = (eval_pair_scaled(pt, chi_p, dt) * np.exp(dt(-8.0 / 3.0) / cp)).astype(np.float64)
+        keep = ex_p > np.finfo(dt).tiny * 16
+        e_p = float(np.max(np.abs(wp[keep] / ex_p[keep] - 1)))
+        name = form_name(prec, trunc)
+        e_ph = max(w[name] for k, cs, w in errs if k == "photon")
+        e_pp = max(w[name] for k, cs, w in errs if k == "pair")
+        forms[name] = {"rate": max(e_r, e_p), "photon_rate": e_r, "pair_rate": e_p,
+                       "sample": max(e_ph, e_pp), "photon_sample": e_ph, "pair_sample": e_pp,
+                       "rate_terms": RATE_DEG_TRUNC if trunc else RATE_DEG,
+                       "patch_terms": INV_TRUNC if trunc else INV_NR}
     report = {
-        "rate_rel_err": rad_err, "pair_rate_rel_err": pair_err,
-        "photon_inverse_rel_err_by_segment": {cs: e for k, cs, e in errs if k == "photon"},
-        "pair_inverse_rel_err_by_segment": {cs: e for k, cs, e in errs if k == "pair"},
+        "rate_rel_err": forms["fp64"]["photon_rate"], "pair_rate_rel_err": forms["fp64"]["pair_rate"],
+        "photon_inverse_rel_err_by_segment": {cs: w["fp64"] for k, cs, w in errs if k == "photon"},
+        "pair_inverse_rel_err_by_segment": {cs: w["fp64"] for k, cs, w in errs if k == "pair"},
+        # measured relative errors of each evaluation form: rates against the quadrature of
+        # Eqs. (wtilde), (wtilde_pair); samples (wbar^3 and y, which bound the errors of the
+        # energy fractions and their complements) against exact inversions; FP32 forms
+        # evaluated in single precision as the kernels do (without their fused multiply-adds)
+        "forms": forms,
         "build_seconds": time.time() - t0,
     }
     return dict(rad=rad, pair=pair, ka=bt.ka, kb=bt.kb, phinv=phinv, ppinv=ppinv), report

@@ -116,7 +116,7 @@ sys.path.insert(0, %r)
 from paper_2301_07684_amd import sfq
 L = sfq.load()
 cfg = sfq.Config(ref_omega=0.0, ref_length=1e-7, dt=0.01, precision=0, decision=0, blcfa=0,
-                 bw_fast=0, device=0, reserved=0, tables_path=None)
+                 bw_fast=0, device=0, approx=0, tables_path=None)
 h = C.c_void_p()
 st = L.sfq_create(C.byref(cfg), C.byref(h))
 bad = sfq.Config(ref_omega=1.0, ref_length=1e-7, dt=0.01)

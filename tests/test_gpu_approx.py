@@ -1,0 +1,191 @@
+"""The accuracy/speed dial's forms against the oracle, within the error bounds the dial reports.
+
+Each arithmetic form (FP64 or MIXED, the full tables or their truncated evaluation: the leading
+10 of 16 terms of every rate segment and 5 x 5 of 8 x 8 coefficients of every inverse patch, the
+analogue of the paper's coefficient counts, Sec. 4.5) must stay within the relative error bound
+that autotune.form_errors derives from the table generator's measured report: rates against the
+oracle's quadrature, sampled energy fractions (and their complements) against its exact
+inversion, and the whole step's decisions, recoil and products.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2301_07684_amd import autotune, inputs, sfq
+
+pytestmark = pytest.mark.gpu
+
+FORMS = [(sfq.FP64, sfq.APPROX_TRUNCATED), (sfq.MIXED, sfq.APPROX_TRUNCATED),
+         (sfq.FP64, sfq.APPROX_FULL), (sfq.MIXED, sfq.APPROX_FULL)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+@pytest.fixture(scope="module")
+def bounds():
+    return autotune.form_errors()
+
+
+# the oracle's own accuracy, added to every form's bound: its rates are outer quadratures to a
+# relative tolerance of 1e-12, its samples roots of cumulative distributions that are such
+# quadratures (good to about 1e-11 in the energy fractions)
+ORACLE_RATE = 1e-12
+ORACLE_SAMPLE = 1e-11
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.abs(a - b) / np.abs(b)
+    r[a == b] = 0.0
+    return r
+
+
+def handle(prec, approx, **kw):
+    return sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=prec, approx=approx,
+                      **kw)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("species", [sfq.ELECTRON, sfq.PHOTON])
+def test_rates_within_the_reported_bound(dev, bounds, form, species):
+    h = handle(*form)
+    lo = -5 if species != sfq.PHOTON else -2
+    chi = np.concatenate([10.0 ** np.linspace(lo, math.log10(3000), 400), [0.01, 0.3]])
+    gamma = 10.0 ** np.linspace(1, 6, chi.size)
+    out = h.rates(species, T(gamma, dev), T(chi, dev)).cpu().numpy()
+    ref = O.rates(species, gamma, chi, h.lr_over_lc)
+    tol = bounds[form]["pair_rate" if species == sfq.PHOTON else "emission_rate"] + ORACLE_RATE
+    # MIXED: where the FP32 exponential of the pair rate underflows, an absolute tolerance
+    tiny = np.finfo(np.float32).tiny * h.lr_over_lc if form[0] == sfq.MIXED else 0.0
+    ok = (np.abs(out - ref) <= tol * np.abs(ref)) | (np.abs(out - ref) <= tiny)
+    assert np.all(ok), (chi[~ok], rel(out, ref)[~ok], tol)
+    h.close()
+
+
+PH_CHI = [1e-5, 1e-3, 0.02, 0.3, 1.0, 7.0, 60.0, 500.0, 1900.0]
+PH_R = [1e-9, 1e-4, 0.01, 0.2, 0.4999, 0.5001, 0.8, 0.99, 0.9999, 1 - 2.0 ** -40, 1 - 2.0 ** -52]
+PP_CHI = [0.01, 0.05, 0.3, 1.0, 10.0, 100.0, 1000.0]
+PP_R = [1e-12, 1e-5, 0.1, 0.3, 0.4999, 0.5001, 0.7, 0.9, 0.99999, 1 - 2.0 ** -40]
+
+
+@pytest.fixture(scope="module")
+def grids():
+    rng = np.random.default_rng(12)
+    chi, r = np.meshgrid(PH_CHI, PH_R, indexing="ij")
+    chi = np.concatenate([chi.ravel(), 10.0 ** rng.uniform(-4, 3, 400)])
+    r = np.concatenate([r.ravel(), rng.uniform(0, 1, 400)])
+    g = np.full(chi.size, 1e4)
+    gph, gem, _ = O.sample_photon(g, chi, r)
+    chp, rp = np.meshgrid(PP_CHI, PP_R, indexing="ij")
+    chp = np.concatenate([chp.ravel(), 10.0 ** rng.uniform(-2, 3, 400)])
+    rp = np.concatenate([rp.ravel(), rng.uniform(0, 1, 400)])
+    gp_ = np.full(chp.size, 1e4)
+    ge, gpos, _ = O.sample_pair(gp_, chp, rp)
+    return (g, chi, r, gph, gem), (gp_, chp, rp, ge, gpos)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_samples_within_the_reported_bound(dev, bounds, grids, form):
+    h = handle(*form)
+    tol = bounds[form]["sample"] + ORACLE_SAMPLE
+    (g, chi, r, gph, gem), (gp_, chp, rp, ge, gpos) = grids
+    a, b = h.sample_photon(T(g, dev), T(chi, dev), T(r, dev))
+    assert np.max(rel(a.cpu().numpy(), gph)) <= tol          # xi
+    assert np.max(rel(b.cpu().numpy(), gem)) <= tol          # 1 - xi
+    a, b = h.sample_pair(T(gp_, dev), T(chp, dev), T(rp, dev))
+    assert np.max(rel(a.cpu().numpy(), ge)) <= tol           # electron share
+    assert np.max(rel(b.cpu().numpy(), gpos)) <= tol         # positron share
+    h.close()
+
+
+def test_truncated_is_less_accurate_than_full(dev, grids):
+    # the truncation is real: the truncated FP64 form departs from the full one by about its
+    # reported error, far more than FP64 rounding
+    (g, chi, r, gph, gem), _ = grids
+    full, trunc = handle(sfq.FP64, sfq.APPROX_FULL), handle(sfq.FP64, sfq.APPROX_TRUNCATED)
+    a = full.sample_photon(T(g, dev), T(chi, dev), T(r, dev))[0].cpu().numpy()
+    b = trunc.sample_photon(T(g, dev), T(chi, dev), T(r, dev))[0].cpu().numpy()
+    assert 1e-9 < np.max(rel(b, a)) < 1e-4
+    gam = np.full(200, 1e3)
+    c = 10.0 ** np.linspace(-3, 3, 200)
+    ra = full.rates(sfq.ELECTRON, T(gam, dev), T(c, dev)).cpu().numpy()
+    rb = trunc.rates(sfq.ELECTRON, T(gam, dev), T(c, dev)).cpu().numpy()
+    assert 1e-13 < np.max(rel(rb, ra)) < 1e-7
+
+
+@pytest.mark.parametrize("form", [(sfq.FP64, sfq.APPROX_TRUNCATED),
+                                  (sfq.MIXED, sfq.APPROX_TRUNCATED)])
+def test_truncated_step_against_the_oracle(dev, bounds, form):
+    # the plane-wave workload: decisions identical outside a band of the rate bound, every
+    # sampled emitter's recoil and products within the sample bound, component by component
+    h = handle(*form)
+    b = bounds[form]
+    n = 20000
+    for sp in (sfq.ELECTRON, sfq.PHOTON):
+        w = inputs.plane_wave(1 << 24, idx=np.arange(n) * 811 + 5, species=sp)
+        uid = T(w["uid"], dev)
+        tau0 = (h.init_optical_depth(uid, seed=2) * 0.05).cpu().numpy()
+        tile = sfq.TileArrays(sp, *[T(w["p"][i], dev) for i in range(3)],
+                              *[T(w["E"][i], dev) for i in range(3)],
+                              *[T(w["B"][i], dev) for i in range(3)], tau=T(tau0, dev), uid=uid,
+                              alive=torch.ones(n, dtype=torch.uint8, device=dev),
+                              rate_out=torch.zeros(n, dtype=torch.float64, device=dev))
+        pb, cnt = sfq.ProductBuffers.empty(n, n, dev), sfq.Counters(dev)
+        h.step([tile], seed=3, step=1, products=pb, counters=cnt)
+        torch.cuda.synchronize()
+        ref = O.step(sp, w["p"], w["E"], w["B"], tau0, w["uid"].view(np.uint64), dt=h.dt,
+                     lc_over_lr=h.lc_over_lr, seed=3, step=1)
+        W = ref["rate"]
+        rate = tile.rate_out.cpu().numpy()
+        rb = b["pair_rate" if sp == sfq.PHOTON else "emission_rate"] + ORACLE_RATE
+        sb = b["sample"] + ORACLE_SAMPLE
+        tiny = np.finfo(np.float32).tiny * h.lr_over_lc if form[0] == sfq.MIXED else 0.0
+        assert np.all((np.abs(rate - W) <= rb * W) | (np.abs(rate - W) <= tiny))
+        thr = W * h.dt
+        band = np.abs(tau0 - thr) <= 2 * rb * np.maximum(tau0, thr)
+        name, k = ("electrons", 1) if sp == sfq.PHOTON else ("photons", 0)
+        m = pb.host_counts()[k]
+        ps = getattr(pb, name)
+        par = ps.parent[:m].cpu().numpy().view(np.uint64)
+        emit_gpu = np.isin(w["uid"].view(np.uint64), par)
+        em = ref["emitted"].astype(bool)
+        assert not ((emit_gpu != em) & ~band).any()
+        assert (em & ~band).sum() > 50
+        got = {}
+        for nm in ("photons", "electrons", "positrons"):
+            q = getattr(pb, nm)
+            kk = pb.host_counts()[("photons", "electrons", "positrons").index(nm)]
+            pv = np.stack([getattr(q, f)[:kk].cpu().numpy() for f in ("px", "py", "pz")])
+            for j, p in enumerate(q.parent[:kk].cpu().numpy().view(np.uint64)):
+                got[(nm, int(p))] = pv[:, j]
+        keep = em & ~band
+        uids = w["uid"].view(np.uint64)
+        checked = 0
+        for q in ref["products"]:
+            i = int(np.flatnonzero(uids == np.uint64(q["parent"]))[0])
+            if not keep[i]:
+                continue
+            nm = {O.PHOTON: "photons", O.ELECTRON: "electrons", O.POSITRON: "positrons"}[q["species"]]
+            v = np.array([q["px"], q["py"], q["pz"]])
+            assert np.linalg.norm(got[(nm, q["parent"])] - v) <= sb * np.linalg.norm(v)
+            checked += 1
+        assert checked > 50
+        if sp != sfq.PHOTON:
+            pg = np.stack([t.cpu().numpy() for t in (tile.px, tile.py, tile.pz)])
+            d = np.linalg.norm(pg[:, keep] - ref["p"][:, keep], axis=0)
+            # the recoiled momentum: gamma/(1 + s), its error relative to the emitter's energy
+            assert np.all(d <= sb * np.linalg.norm(w["p"][:, keep], axis=0))
+    h.close()

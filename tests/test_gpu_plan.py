@@ -97,7 +97,7 @@ def test_plan_and_graph_match_step(dev, precision):
         _ = torch.ones(1000, device=dev).sum().item()  # eager work between replays
         assert same(state(eager), state(graphed)), rep
         assert same(product_set(pe), product_set(pg)), rep  # the last step's products
-    assert ce.as_dict() == cp.as_dict() == cg.as_dict()
+    assert ce.results() == cp.results() == cg.results()
     plan.close()
     gplan.close()
 
@@ -221,7 +221,7 @@ def test_extreme_launch_shapes_give_identical_results(dev, precision):
         for s in range(2):
             h.step(tiles, seed=21, step=s, products=pb, counters=cnt)
         torch.cuda.synchronize()
-        results.append((state(tiles), product_set(pb), cnt.as_dict()))
+        results.append((state(tiles), product_set(pb), cnt.results()))
     c0 = results[0][2]
     assert c0["emitted"] > 1000 and c0["overflow"] == 0
     for st, ps, c in results[1:]:
@@ -239,14 +239,20 @@ def test_select_form_dial(dev):
     prods = sfq.ProductBuffers.empty(100000, 100000, dev)
     cnt = sfq.Counters(dev)
     cand = [(2, 4096), (8, 1024)]
+    errs = autotune.form_errors()
+    fp64 = errs[(sfq.FP64, sfq.APPROX_FULL)]
     r = autotune.select_form(kw, tiles, prods, cnt, max_rel_error=1e-8, candidates=cand, repeats=2)
     assert r["precision"] == sfq.FP64 and not r["bw_fast"] and list(r["timings"]) == ["fp64"]
-    assert r["error_bound"] == {"rate": 1e-12, "sample": 1e-9}
+    assert r["approx"] == sfq.APPROX_FULL
+    assert r["error_bound"] == {"rate": fp64["rate"], "sample": fp64["sample"]}
     assert all(np.array_equal(a, b) for a, b in zip(before, state(tiles)))
     r["handle"].close()
+    # the truncated forms' bounds come from the table generator's measured report
+    assert errs[(sfq.FP64, sfq.APPROX_TRUNCATED)]["sample"] > fp64["sample"]
     r = autotune.select_form(kw, tiles, prods, cnt, max_rel_error=1e-4, allow_bw_fast=True,
                              candidates=cand, repeats=2)
-    assert set(r["timings"]) == {"fp64", "fp64+bw_fast", "mixed", "mixed+bw_fast"}
+    assert set(r["timings"]) == {f + b for f in ("fp64", "mixed", "fp64_trunc", "mixed_trunc")
+                                 for b in ("", "+bw_fast")}
     assert r["ms"] == min(r["timings"].values())
     assert ("bw_fast" in r["error_bound"]) == r["bw_fast"]
     assert all(np.array_equal(a, b) for a, b in zip(before, state(tiles)))
@@ -255,7 +261,7 @@ def test_select_form_dial(dev):
     a, b = clone_tiles(tiles), clone_tiles(tiles)
     pa, pb = sfq.ProductBuffers.empty(100000, 100000, dev), sfq.ProductBuffers.empty(100000, 100000, dev)
     r["handle"].step(a, seed=4, step=2, products=pa, counters=sfq.Counters(dev))
-    ref = sfq.Handle(**kw, precision=r["precision"], bw_fast=r["bw_fast"])
+    ref = sfq.Handle(**kw, precision=r["precision"], bw_fast=r["bw_fast"], approx=r["approx"])
     ref.step(b, seed=4, step=2, products=pb, counters=sfq.Counters(dev))
     torch.cuda.synchronize()
     assert all(np.array_equal(x, y) for x, y in zip(state(a), state(b)))
@@ -291,7 +297,7 @@ def test_one_handle_on_two_streams(dev):
     assert same(state(a), state(ra)) and same(state(b), state(rb))
     assert pa.host_counts() == qa.host_counts() and pb.host_counts() == qb.host_counts()
     assert same(product_set(pa), product_set(qa)) and same(product_set(pb), product_set(qb))
-    assert ca.as_dict() == rca.as_dict() and cb.as_dict() == rcb.as_dict()
+    assert ca.results() == rca.results() and cb.results() == rcb.results()
     assert ca.as_dict()["processed"] > 3 * 300000 and ca.as_dict()["overflow"] == 0
     assert cb.as_dict()["overflow"] == 0
 
@@ -333,7 +339,7 @@ def test_maximum_tile_count_and_overflow_rerun(dev):
     h.step(ref, seed=8, step=6, products=pr, counters=cr)
     torch.cuda.synchronize()
     assert same(state(big), state(ref))
-    assert same(product_set(pa), product_set(pr)) and ca.as_dict() == cr.as_dict()
+    assert same(product_set(pa), product_set(pr)) and ca.results() == cr.results()
     assert ca.as_dict()["emitted"] > 100 and ca.as_dict()["converted"] > 10
     with pytest.raises(ValueError):
         h.step(small + small[:1], seed=8, step=6, products=pa, counters=ca)

@@ -222,7 +222,7 @@ def test_plan_with_push_matches_eager_steps(dev):
             for f in ("px", "py", "pz", "tau", "alive"):
                 assert torch.equal(getattr(a, f), getattr(b, f)), (r, f)
         assert torch.equal(pe.counts, pp.counts)
-    assert ce.as_dict() == cp.as_dict()
+    assert ce.results() == cp.results()
     plan.close()
     # the momenta really moved: every electron was pushed four times
     w = inputs.general_fields(n, species=sfq.ELECTRON)

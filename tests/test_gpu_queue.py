@@ -1,0 +1,261 @@
+"""The bounded emitter queue: a queue too small for a step gives the same results.
+
+The streaming pass defers every share of a chunk that its wave's queue slice might not hold, and
+a further kernel of the same step steps those shares with the same arithmetic.  So a handle
+whose queue is forced to its minimum (one share per slice: almost every share deferred) or to a
+small fraction (some shares deferred) must give, bit for bit, the particle state, the set of
+products and the counters of a handle whose queue can never overflow, in every step form:
+FP64 and MIXED, array and plane-wave fields, with and without the push, optical-depth and local
+decisions, beyond-LCFA leptons, per-owner product sets, ragged tiles, and plans replayed from a
+graph.  Only the order of products in their buffers and the `deferred` counter may differ.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2301_07684_amd import inputs, sfq
+
+pytestmark = pytest.mark.gpu
+
+LAUNCH = (1, 256)   # many chunks per streaming block, so that slices fill up
+N = 1 << 17         # with 256 compute units, two tiles of N give four chunks per block
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+STATE = ("px", "py", "pz", "tau", "alive", "fperp", "dfperp", "just_created")
+
+
+def state(tiles):
+    return [getattr(t, f).cpu().numpy().copy() for t in tiles for f in STATE
+            if getattr(t, f) is not None]
+
+
+def product_set(pb):
+    """Products per species sorted by (parent, uid): the order in the buffers depends on the
+    queue and the scheduling, the contents do not."""
+    c = pb.host_counts()
+    out = []
+    for k, name in enumerate(("photons", "electrons", "positrons")):
+        ps = getattr(pb, name)
+        n = min(c[k], ps.capacity)
+        uid, parent = ps.uid[:n].cpu().numpy(), ps.parent[:n].cpu().numpy()
+        order = np.lexsort((uid, parent))
+        out.append(np.stack([uid, parent])[:, order])
+        out.append(np.stack([getattr(ps, f)[:n].cpu().numpy() for f in ("px", "py", "pz", "tau")])
+                   [:, order])
+    return out
+
+
+def same(a, b):
+    return len(a) == len(b) and all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def handle(frac, **kw):
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, **kw)
+    h.set_launch(*LAUNCH)
+    h.set_queue(frac, adaptive=False)
+    return h
+
+
+def array_tiles(dev, h, specs, tau_scale=0.05, alive=True):
+    """specs: (species, n, seed, chi_range) plane-wave-geometry tiles with field arrays."""
+    out = []
+    for sp, n, seed, chi_range in specs:
+        w = inputs.plane_wave(n, seed=seed, species=sp, chi_range=chi_range)
+        uid = T(w["uid"], dev)
+        out.append(sfq.TileArrays(sp, *[T(w["p"][i], dev) for i in range(3)],
+                                  *[T(w["E"][i], dev) for i in range(3)],
+                                  *[T(w["B"][i], dev) for i in range(3)],
+                                  tau=h.init_optical_depth(uid, seed=3) * tau_scale, uid=uid,
+                                  alive=torch.ones(n, dtype=torch.uint8, device=dev)
+                                  if (alive or sp == sfq.PHOTON) else None))
+    return out
+
+
+def clone(tiles):
+    out = []
+    for t in tiles:
+        kw = {f: getattr(t, f) for f in ("ex", "ey", "ez", "bx", "by", "bz", "uid", "wave_amp",
+                                         "wave_phase", "px_prev", "py_prev", "pz_prev")}
+        for f in ("tau", "alive", "fperp", "dfperp", "just_created"):
+            v = getattr(t, f)
+            kw[f] = None if v is None else v.clone()
+        out.append(sfq.TileArrays(t.species, t.px.clone(), t.py.clone(), t.pz.clone(), **kw,
+                                  product_set=t.product_set, step_offset=t.step_offset,
+                                  field_mode=t.field_mode, wave_k=t.wave_k, wave_pol=t.wave_pol,
+                                  wave_phase0=t.wave_phase0))
+    return out
+
+
+def run_pair(dev, make, *, steps=1, fracs=(0.0, 0.02), precision=sfq.FP64, decision=None,
+             blcfa=False, push=False, sets=0, caps=(1 << 18, 1 << 17)):
+    """The same steps on a handle whose queue never overflows and on handles with small queues;
+    returns the deferred counts of the small ones (each must be > 0)."""
+    kw = dict(precision=precision, blcfa=blcfa)
+    if decision is not None:
+        kw["decision"] = decision
+    ref_h = handle(1.0, **kw)
+    base = make(ref_h)
+    runs = []
+    for frac in (1.0, *fracs):
+        h = ref_h if frac == 1.0 else handle(frac, **kw)
+        tiles = clone(base)
+        cnt = sfq.Counters(dev)
+        if sets:
+            psets = [sfq.ProductBuffers.empty(*caps, dev) for _ in range(sets)]
+            pb = None
+        else:
+            psets, pb = None, sfq.ProductBuffers.empty(*caps, dev)
+        snaps = []
+        for s in range(steps):
+            h.step(tiles, seed=11, step=40 + s, products=pb, product_sets=psets, counters=cnt,
+                   push=push, zero_product_counts=True)
+            torch.cuda.synchronize()
+            prods = [product_set(p) for p in (psets or [pb])]
+            snaps.append((state(tiles), prods))
+        runs.append((frac, snaps, cnt.as_dict()))
+    ref = runs[0]
+    assert ref[2]["deferred"] == 0 and ref[2]["overflow"] == 0
+    deferred = []
+    for frac, snaps, c in runs[1:]:
+        for k, ((st, pr), (st0, pr0)) in enumerate(zip(snaps, ref[1])):
+            assert same(st, st0), (frac, k, "state")
+            assert all(same(a, b) for a, b in zip(pr, pr0)), (frac, k, "products")
+        c0 = dict(ref[2])
+        assert c["deferred"] > 0, frac
+        assert {k: v for k, v in c.items() if k != "deferred"} == \
+               {k: v for k, v in c0.items() if k != "deferred"}, (frac, c, c0)
+        deferred.append(c["deferred"])
+    return deferred, ref[2]
+
+
+@pytest.mark.parametrize("precision", [sfq.FP64, sfq.MIXED])
+def test_small_queue_same_results_array_tiles(dev, precision):
+    # aligned tiles (two particles per lane), a ragged unaligned one (one-particle loop), a
+    # tile with no alive array, both species
+    def make(h):
+        tiles = array_tiles(dev, h, [(sfq.ELECTRON, N, 501, (1e-2, 30.0)),
+                                     (sfq.PHOTON, N, 502, (0.1, 300.0)),
+                                     (sfq.POSITRON, 30001, 503, (1e-1, 10.0))])
+        t = tiles[2]
+        tiles[2] = sfq.TileArrays(t.species, t.px[1:], t.py[1:], t.pz[1:], t.ex[1:], t.ey[1:],
+                                  t.ez[1:], t.bx[1:], t.by[1:], t.bz[1:], tau=t.tau[1:],
+                                  uid=t.uid[1:], alive=None)
+        return tiles
+    deferred, c = run_pair(dev, make, precision=precision, steps=2)
+    assert c["emitted"] > 1000 and c["converted"] > 100
+    assert deferred[0] > 0.5 * c["processed"]  # the minimal queue defers almost everything
+
+
+def test_small_queue_same_results_plane_wave_push_and_local(dev):
+    def make(h):
+        out = []
+        for sp, n, seed in ((sfq.ELECTRON, N, 601), (sfq.PHOTON, N, 602)):
+            w = inputs.plane_wave(n, seed=seed, species=sp)
+            uid = T(w["uid"], dev)
+            out.append(sfq.TileArrays(sp, *[T(w["p"][i], dev) for i in range(3)], uid=uid,
+                                      tau=h.init_optical_depth(uid, seed=3) * 0.02,
+                                      alive=torch.ones(n, dtype=torch.uint8, device=dev),
+                                      field_mode=sfq.FIELDS_PLANE_WAVE,
+                                      wave_amp=T(w["wave_a"], dev),
+                                      wave_phase=T(w["wave_phase"], dev)))
+        return out
+    run_pair(dev, make, push=True, steps=2)
+    run_pair(dev, make, push=True, decision=sfq.LOCAL, precision=sfq.MIXED)
+
+
+def test_small_queue_same_results_beyond_lcfa_served_form(dev):
+    # the served configuration: beyond-LCFA leptons (local decisions), MIXED, the push, fields
+    # as arrays; several steps so that the force history matters
+    n = N
+
+    def make(h):
+        idx = np.arange(n)
+        gamma = 10.0 ** (3 + 1.5 * inputs.uniforms(8, 0, idx))
+        out = []
+        for sp in (sfq.ELECTRON, sfq.POSITRON):
+            w = inputs.general_fields(n, seed=700 + sp, species=sp, field_range=(50.0, 3e3))
+            out.append(sfq.TileArrays(sp, *[T(w["p"][i], dev) for i in range(3)],
+                                      *[T(w["E"][i], dev) for i in range(3)],
+                                      *[T(w["B"][i], dev) for i in range(3)],
+                                      uid=T(w["uid"], dev),
+                                      fperp=torch.zeros(3 * n, dtype=torch.float64, device=dev),
+                                      dfperp=torch.zeros(3 * n, dtype=torch.float64, device=dev),
+                                      just_created=torch.ones(n, dtype=torch.uint8, device=dev)))
+        del gamma
+        ph = array_tiles(dev, h, [(sfq.PHOTON, N // 2, 703, (0.5, 200.0))])
+        return out + ph
+    deferred, c = run_pair(dev, make, precision=sfq.MIXED, decision=sfq.LOCAL, blcfa=True,
+                           push=True, steps=3)
+    assert c["emitted"] > 500 and c["blcfa_rejected"] > 10
+
+
+def test_small_queue_same_results_product_sets_and_offsets(dev):
+    def make(h):
+        tiles = array_tiles(dev, h, [(sfq.ELECTRON, N, 801, (1e-2, 30.0)),
+                                     (sfq.PHOTON, N, 802, (0.1, 300.0)),
+                                     (sfq.ELECTRON, 12000, 803, (1e-1, 10.0))])
+        for k, t in enumerate(tiles):
+            t.product_set = k % 2
+            t.step_offset = 7 * k
+        return tiles
+    run_pair(dev, make, sets=2)
+
+
+def test_small_queue_in_a_replayed_graph(dev):
+    # a plan sized with the minimal queue, captured and replayed: the deferral words are cleared
+    # by each step, so every replay matches an eager step on a queue that never overflows
+    ref_h, small_h = handle(1.0), handle(0.0)
+    base = array_tiles(dev, ref_h, [(sfq.ELECTRON, N, 901, (1e-2, 30.0)),
+                                    (sfq.PHOTON, N, 902, (0.1, 300.0))])
+    eager, planned = clone(base), clone(base)
+    pe, pp = sfq.ProductBuffers.empty(1 << 17, 1 << 16, dev), sfq.ProductBuffers.empty(1 << 17, 1 << 16, dev)
+    ce, cp = sfq.Counters(dev), sfq.Counters(dev)
+    plan = small_h.plan(planned, seed=5, step=3, products=pp, counters=cp)
+    plan.capture(1)
+    for r in range(3):
+        ref_h.step(eager, seed=5, step=3 + r, products=pe, counters=ce, zero_product_counts=True)
+        plan.replay()
+        torch.cuda.synchronize()
+        assert same(state(eager), state(planned)), r
+        assert same(product_set(pe), product_set(pp)), r
+        a, b = ce.as_dict(), cp.as_dict()
+        assert b["deferred"] > 0 and a["deferred"] == 0
+        assert {k: v for k, v in a.items() if k != "deferred"} == \
+               {k: v for k, v in b.items() if k != "deferred"}, r
+    plan.close()
+
+
+def test_queue_is_sized_from_the_emitters_and_grows(dev):
+    # the headline geometry at 2^21 + 2^21 particles: the default queue is a small fraction of
+    # the worst case (48 B per particle); a step with many emitters raises the fraction (the
+    # adaptive default) and the queue grows, results unchanged
+    n = 1 << 21
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT)
+    h.set_launch(1, 1024)   # 16 chunks per streaming block
+    tiles = array_tiles(dev, h, [(sfq.ELECTRON, n, 951, None), (sfq.PHOTON, n, 952, None)],
+                        tau_scale=1.0)
+    pb, cnt = sfq.ProductBuffers.empty(n, n // 4, dev), sfq.Counters(dev)
+    h.step(tiles, seed=1, step=1, products=pb, counters=cnt, zero_product_counts=True)
+    torch.cuda.synchronize()
+    worst = 48 * 2 * n
+    b0 = h.queue_bytes()
+    assert 0 < b0 < 0.3 * worst, (b0, worst)
+    # nearly every particle emits now: the first step defers, the next ones have a bigger queue
+    for t in tiles:
+        t.tau.fill_(1e-30)
+    for s in range(3):
+        h.step(tiles, seed=1, step=2 + s, products=pb, counters=cnt, zero_product_counts=True)
+        torch.cuda.synchronize()
+    assert h.queue_bytes() > 2 * b0
+    assert cnt.as_dict()["deferred"] > 0

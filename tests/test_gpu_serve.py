@@ -101,7 +101,7 @@ def test_product_sets_and_step_offsets_match_separate_steps(dev, precision):
         cm, pm = product_set(sets[o])
         assert ca == cm and same(pa, pm), o
         k += len(a)
-    assert cnt.as_dict() == alone_c.as_dict()
+    assert cnt.results() == alone_c.results()
     assert cnt.as_dict()["emitted"] > 100 and cnt.as_dict()["converted"] > 10
 
 
@@ -160,10 +160,16 @@ def test_served_results_are_the_same_alone_and_in_the_mix(dev):
               serve.JobSpec(3, 60000, 1, steps=7, arrival=0.002, client=3),
               serve.JobSpec(4, 20000, 20000, steps=5, arrival=0.003, client=4)]
     logs = {}
+    # the lanes' emitter queues are charged to the budget before any simulation
+    probe = serve.Server(dev, hbm_budget=1 << 30, lanes=1, max_batch_particles=1 << 22)
+    lane_queue = probe.queue_bytes
+    assert 0 < lane_queue and probe.sched.budget == (1 << 30) - lane_queue
+    probe.close()
     for name, jobs, lanes, budget in (("alone", [target], 1, 1 << 30),
                                       ("mix", [target] + others, 2, 1 << 30),
                                       ("mix_tight", [target] + others, 1,
-                                       target.footprint + others[0].footprint + 4096)):
+                                       lane_queue + target.footprint + others[0].footprint
+                                       + 4096)):
         log = []
         srv = serve.Server(dev, hbm_budget=budget, lanes=lanes, max_batch_particles=1 << 22,
                            on_step=_recorder(0, log))
