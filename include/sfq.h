@@ -281,6 +281,22 @@ sfq_status sfq_get_launch(sfq_handle h, int* blocks_per_cu, int* chunk);
  * same result. */
 sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream);
 
+/* sfq_step for callers that cannot allocate device memory (tight serving loops, code that may
+ * not call hipMalloc): the same step and the same results, with no allocation of any kind in the
+ * call.  Its scratch (the tile descriptors, at most 2 MiB of them; the emitter queue; the
+ * deferred-share list) lives in a static device array of 256 MiB that the library holds on
+ * each device it runs on until the process ends; sfq_create sets it up, with a pinned buffer
+ * per handle for the descriptors.  The queue takes what the array leaves: shares that do not
+ * fit are stepped by the deferred-share kernel, so results never depend on it (the call uses
+ * the handle's launch shape, with the chunk halved while one share per slice would take more
+ * than half of the queue's room).  Steps with more chunks than the array can list (about
+ * sixteen million), or descriptors beyond 2 MiB, return SFQ_E_CAPACITY and enqueue nothing; a
+ * capturing stream returns SFQ_E_STATE.  All calls on one
+ * device share the array, and it keeps the last call's contents: calls that overlap on one
+ * device (other streams, other handles, other threads) race and must be ordered by the caller;
+ * calls on one stream are ordered by it.  Timing events (sfq_profile_*) are not recorded. */
+sfq_status sfq_step_noalloc(sfq_handle h, const sfq_step_desc* desc, void* stream);
+
 /* ------------------------------------------------------------------------------------------ */
 /* Plans: a fixed set of tiles stepped repeatedly.  The descriptors are uploaded once, the plan
  * owns its emitter queue, and the Philox step index lives in device memory and advances by one

@@ -1563,6 +1563,19 @@ constexpr size_t STAGING_BYTES = 2 << 20;
 
 }  // namespace
 
+// Scratch of the step that allocates nothing (sfq_step_noalloc): the tile descriptors (the first
+// STAGING_BYTES), then the emitter queue and the deferred-share list, in a file-scope device
+// array of fixed size.  Each device holds its own copy until the process ends; host code uses
+// its device address, queried once per device at set-up (the array's name is not a device
+// address in host code).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // by device ordinal
+}  // namespace
+
 struct ProfEvents {
     hipEvent_t e[3];
 };
@@ -1608,6 +1621,11 @@ struct sfq_ctx {
     // kernel timing (sfq_profile_*): events around the two step kernels of each timed step
     int prof = 0;
     std::vector<ProfEvents> prof_used, prof_free;
+    // sfq_step_noalloc: the device's static scratch, and a pinned host buffer and its event for
+    // uploading the descriptors (all set up by sfq_create; null when that failed)
+    void* na_scratch = nullptr;
+    void* na_host = nullptr;
+    hipEvent_t na_done = nullptr;
 };
 
 struct sfq_plan_t;
@@ -1740,6 +1758,11 @@ static void release(sfq_ctx* h)
     }
     if (h->d_queue) (void)hipFree(h->d_queue);
     if (h->obs_host) (void)hipHostFree(h->obs_host);
+    if (h->na_done) {
+        (void)hipEventSynchronize(h->na_done);
+        (void)hipEventDestroy(h->na_done);
+    }
+    if (h->na_host) (void)hipHostFree(h->na_host);
     if (h->d_tab64) (void)hipFree(h->d_tab64);
     if (h->d_tab32) (void)hipFree(h->d_tab32);
     delete h;
@@ -1818,6 +1841,24 @@ sfq_status sfq_create(const sfq_config* cfg, sfq_handle* out)
         } else {
             (void)hipHostFree(obs);
         }
+    }
+    // the step that allocates nothing: the device address of the static scratch (once per
+    // device, with the device current), a pinned descriptor buffer and its event
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if ((int)g_scratch_ptr.size() <= h->device) g_scratch_ptr.resize(h->device + 1, nullptr);
+        if (!g_scratch_ptr[h->device]) {
+            void* ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr)
+                g_scratch_ptr[h->device] = ptr;
+        }
+        h->na_scratch = g_scratch_ptr[h->device];
+    }
+    if (h->na_scratch) {
+        if (hipHostMalloc(&h->na_host, STAGING_BYTES, hipHostMallocDefault) != hipSuccess)
+            h->na_host = nullptr;
+        if (hipEventCreateWithFlags(&h->na_done, hipEventDisableTiming) != hipSuccess)
+            h->na_done = nullptr;
     }
     (void)hipGetLastError();
     *out = h;
@@ -2571,6 +2612,99 @@ sfq_status sfq_step(sfq_handle h, const sfq_step_desc* desc, void* stream)
     }
     h->last_stream = (hipStream_t)stream;
     h->any_step = true;
+    return SFQ_OK;
+}
+
+sfq_status sfq_step_noalloc(sfq_handle h, const sfq_step_desc* desc, void* stream)
+{
+    if (!h) return fail(h, SFQ_E_STATE, "sfq_step_noalloc: NULL handle");
+    std::lock_guard<std::mutex> lock(h->mu);
+    if (!h->na_scratch || !h->na_host || !h->na_done)
+        return fail(h, SFQ_E_STATE, "sfq_step_noalloc: the static scratch of this device could "
+                                    "not be set up at sfq_create");
+    // the handle's launch shape, with the chunk halved (results never depend on it) until one
+    // share per slice takes at most half of the queue's room, so that the rest holds emitters
+    const size_t room = NOALLOC_SCRATCH_BYTES - STAGING_BYTES;
+    const uint64_t slices = (uint64_t)h->num_cus * (uint64_t)h->blocks_per_cu * STEP_WAVES;
+    int chunk = h->chunk;
+    while (chunk > STEP_BLOCK &&
+           slices * (uint64_t)(chunk / STEP_WAVES) * queue_entry_bytes(h) > room / 2)
+        chunk = std::max(STEP_BLOCK, (chunk / 2) & ~(STEP_BLOCK - 1));
+    std::vector<uint32_t> off;
+    const sfq_status v = validate_desc(h, desc, off, chunk);
+    if (v != SFQ_OK) return v;
+    const int nt = desc->ntiles;
+    HIP_TRY(h, hipSetDevice(h->device));
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(h, hipStreamIsCapturing((hipStream_t)stream, &cap));
+    if (cap != hipStreamCaptureStatusNone)
+        return fail(h, SFQ_E_STATE, "sfq_step_noalloc: the stream is capturing a graph; capture "
+                                    "a plan instead (sfq_plan_create, sfq_plan_capture)");
+    const int nchunks = (int)off[nt];
+    if (nchunks == 0) {
+        if (desc->zero_product_counts) {
+            if (desc->nsets > 0) {
+                for (int k = 0; k < desc->nsets; ++k)
+                    HIP_TRY(h, hipMemsetAsync(desc->product_sets[k].product_counts, 0,
+                                              3 * sizeof(unsigned long long),
+                                              (hipStream_t)stream));
+            } else {
+                HIP_TRY(h, hipMemsetAsync(desc->product_counts, 0, 3 * sizeof(unsigned long long),
+                                          (hipStream_t)stream));
+            }
+        }
+        return SFQ_OK;
+    }
+    // descriptors: the first STAGING_BYTES of the scratch
+    const size_t off_pos = (nt * sizeof(sfq_tile) + 15) & ~(size_t)15;
+    const size_t set_pos = (off_pos + (nt + 1) * sizeof(uint32_t) + 15) & ~(size_t)15;
+    const size_t used = set_pos + (size_t)desc->nsets * sizeof(sfq_product_set);
+    if (used > STAGING_BYTES)
+        return fail(h, SFQ_E_CAPACITY, "sfq_step_noalloc: the tile and product-set descriptors "
+                                       "exceed the static scratch's " +
+                                           std::to_string(STAGING_BYTES) + " bytes for them");
+    // the queue: the rest of the scratch, its slices as large as it allows (at most the worst
+    // case); shares that do not fit are stepped by the deferred-share kernel
+    QueueShape qs = queue_shape(h, nchunks, h->blocks_per_cu, chunk, 1.0);
+    const uint64_t worst = qs.cap_per_wave;
+    QueueShape probe = qs;
+    probe.entries = 0;
+    const QueueLayout L0 = queue_layout(h, probe);   // everything but the entries
+    const uint64_t per_entry = (uint64_t)queue_entry_bytes(h) * qs.slices;
+    if (L0.total + per_entry > room)
+        return fail(h, SFQ_E_CAPACITY,
+                    "sfq_step_noalloc: " + std::to_string(nchunks) + " chunks of " +
+                        std::to_string(chunk) + " particles and " + std::to_string(qs.grid) +
+                        " blocks need more than the static scratch of " +
+                        std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes (at most about " +
+                        std::to_string(room / (4 * STEP_WAVES)) +
+                        " chunks; use sfq_step, or a larger chunk)");
+    qs.cap_per_wave = std::min<uint64_t>(worst, (room - L0.total) / per_entry);
+    qs.entries = qs.slices * qs.cap_per_wave;
+    qs.may_defer = qs.cap_per_wave < worst ? 1 : 0;
+    // upload: through the handle's pinned buffer, free again once the previous upload is done
+    HIP_TRY(h, hipEventSynchronize(h->na_done));
+    char* hb = (char*)h->na_host;
+    memcpy(hb, desc->tiles, nt * sizeof(sfq_tile));
+    memcpy(hb + off_pos, off.data(), (nt + 1) * sizeof(uint32_t));
+    if (desc->nsets > 0)
+        memcpy(hb + set_pos, desc->product_sets, desc->nsets * sizeof(sfq_product_set));
+    char* sc = (char*)h->na_scratch;  // the device address, never the array's name
+    HIP_TRY(h, hipMemcpyAsync(sc, hb, used, hipMemcpyHostToDevice, (hipStream_t)stream));
+    // the deferral words must start at zero: the deferred-share kernel's last block leaves them
+    // so, but the array holds whatever the last call on this device left
+    HIP_TRY(h, hipMemsetAsync(sc + STAGING_BYTES, 0, 256, (hipStream_t)stream));
+    StepArgs A;
+    fill_args(h, desc, A, nchunks, chunk);
+    A.tiles = (const sfq_tile*)sc;
+    A.chunk_off = (const uint32_t*)(sc + off_pos);
+    if (desc->nsets > 0) A.sets = (const sfq_product_set*)(sc + set_pos);
+    bind_queue(h, A, sc + STAGING_BYTES, qs, qs);
+    A.emit_split = emit_split_for(h, qs.grid);
+    if (desc->zero_product_counts) enqueue_zero_counts(A, (hipStream_t)stream);
+    launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, nullptr);
+    HIP_TRY(h, hipGetLastError());
+    HIP_TRY(h, hipEventRecord(h->na_done, (hipStream_t)stream));
     return SFQ_OK;
 }
 

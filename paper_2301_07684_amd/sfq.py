@@ -32,7 +32,7 @@ STATUS = {0: "SFQ_OK", 1: "SFQ_E_ARG", 2: "SFQ_E_STATE", 3: "SFQ_E_NOMEM", 4: "S
 # every symbol declared in include/sfq.h
 EXPORTS = ("sfq_create", "sfq_destroy", "sfq_last_error", "sfq_units", "sfq_chi", "sfq_rates",
            "sfq_sample_photon", "sfq_sample_pair", "sfq_philox", "sfq_init_optical_depth",
-           "sfq_step", "sfq_set_launch", "sfq_get_launch", "sfq_plan_create", "sfq_plan_destroy",
+           "sfq_step", "sfq_step_noalloc", "sfq_set_launch", "sfq_get_launch", "sfq_plan_create", "sfq_plan_destroy",
            "sfq_plan_launch", "sfq_plan_set_step", "sfq_plan_capture", "sfq_plan_replay",
            "sfq_reserve", "sfq_set_queue", "sfq_queue_bytes", "sfq_profile_enable",
            "sfq_profile_read", "sfq_profile_read_steps")
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
     L.sfq_init_optical_depth.argtypes = [vp, sz, dp, u64, dp, vp]
     L.sfq_step.restype = st
     L.sfq_step.argtypes = [vp, C.POINTER(StepDesc), vp]
+    L.sfq_step_noalloc.restype = st
+    L.sfq_step_noalloc.argtypes = [vp, C.POINTER(StepDesc), vp]
     L.sfq_set_launch.restype = st
     L.sfq_set_launch.argtypes = [vp, C.c_int, C.c_int]
     L.sfq_get_launch.restype = st
@@ -362,6 +364,16 @@ class Handle:
         desc, _keep = self._desc(tiles, seed, step, products, counters, product_sets, push,
                                  zero_product_counts)
         self._check(self._L.sfq_step(self._h, C.byref(desc), _stream(stream)))
+
+    def step_noalloc(self, tiles: Sequence["TileArrays"], *, seed: int, step: int,
+                     products: Optional["ProductBuffers"] = None, counters: "Counters",
+                     product_sets: Optional[Sequence["ProductBuffers"]] = None,
+                     push: bool = False, zero_product_counts: bool = False, stream=None):
+        """step() through sfq_step_noalloc: no allocation in the call (its scratch is the
+        library's static device array); calls that overlap on one device race."""
+        desc, _keep = self._desc(tiles, seed, step, products, counters, product_sets, push,
+                                 zero_product_counts)
+        self._check(self._L.sfq_step_noalloc(self._h, C.byref(desc), _stream(stream)))
 
     def plan(self, tiles, *, seed: int, step: int, products: Optional["ProductBuffers"] = None,
              counters: "Counters", zero_product_counts: bool = True,
