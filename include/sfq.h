@@ -270,6 +270,7 @@ typedef struct {
 sfq_status sfq_set_launch(sfq_handle h, int blocks_per_cu, int chunk);
 sfq_status sfq_get_launch(sfq_handle h, int* blocks_per_cu, int* chunk);
 
+
 /* The Monte Carlo step (paper Fig. 7 workflow; App. A functions 4-6, 8-11, 15-17): for every
  * alive particle of every tile, gamma and chi (or, for blcfa leptons, the Sec. 5 force update),
  * the LCFA rate, the decision of cfg.decision, and for the particles that emit: Philox draws,
@@ -356,16 +357,22 @@ sfq_status sfq_queue_bytes(sfq_handle h, uint64_t* bytes);
 
 /* Kernel timing (instrumentation).  With enable = 1, every sfq_step and sfq_plan_launch on this
  * handle records HIP events on its stream before the streaming kernel, between it and the
- * emitter kernel, and after that (not inside sfq_plan_capture); they are timing-only events
- * (hipEventDisableSystemFence), so recording them does not write back the caches.  sfq_profile_read waits for the
- * recorded events, returns the summed durations in ms of the streaming and emitter kernels and
- * the number of steps timed since the previous read, and clears them.  Any output may be NULL. */
+ * emitter pass, and after the step's last kernel; with enable = 2 only the first and the last
+ * (the whole step); 0 stops.  Not inside sfq_plan_capture, nor in a launch the caller
+ * captures.  They are timing-only events (hipEventDisableSystemFence), so recording them does
+ * not write back the caches; each record still leaves the device idle for a few microseconds
+ * before the next kernel starts, which the timings include (enable = 2 adds one such gap per
+ * step, enable = 1 two).  sfq_profile_read waits for the recorded events, returns the summed
+ * durations in ms of the streaming kernel and of the emitter pass (for steps timed whole: the
+ * whole step, and 0) and the number of steps timed since the previous read, and clears them.
+ * Any output may be NULL.  SFQ_E_ARG for another enable value. */
 sfq_status sfq_profile_enable(sfq_handle h, int enable);
 sfq_status sfq_profile_read(sfq_handle h, double* stream_ms, double* emit_ms, uint64_t* steps);
 
 /* The same timings step by step (for latency percentiles): for each step timed since the
  * previous read, in order, the streaming kernel's and the emitter pass's (scan and emitter
- * kernels) durations in ms go to stream_ms[k] and emit_ms[k] (host arrays of max_steps floats,
+ * kernels) durations in ms go to stream_ms[k] and emit_ms[k] (a step timed whole: its duration
+ * and 0) (host arrays of max_steps floats,
  * owned by the caller); *steps receives the count, and the timings are cleared.  The events are
  * timing-only (no system-scope fence on record).  SFQ_E_CAPACITY, and nothing cleared, when
  * more than max_steps steps are pending; SFQ_E_ARG for NULL arrays when steps are pending. */

@@ -13,11 +13,12 @@
 //                writes every slot of a chunk it updates (whole cache lines), addresses each
 //                chunk from its first element (scalar bases, one 32-bit lane offset), and
 //                carries none of the sampling code, so its register footprint stays small.
-//   scan_kernel  one block: prefix sums of the queued emitters over blocks give every block its
-//                product slots; the step's counters are written once.
 //   emit_kernel  each queue slice is sampled by a few blocks with all lanes busy: Philox draws,
-//                the inverse-CDF tables (L2-resident), recoil and products at the scanned slots
-//                (per-wave reservations only for beyond-LCFA photons and per-set products).
+//                the inverse-CDF tables (L2-resident), recoil and products.  Each block's
+//                product slots come from the queued counts of every earlier slice, which it
+//                sums itself; the last block out writes the step's totals once (per-wave
+//                reservations only for beyond-LCFA photons and per-set products).
+//   defer_kernel the shares the streaming pass deferred (queue too small), stepped whole.
 //   rates/chi/sample/philox kernels: grid-stride elementwise kernels behind the batched calls.
 #include <hip/hip_runtime.h>
 
@@ -81,14 +82,15 @@ struct StepArgs {
     double* q_aux;              // beyond-LCFA tau/tau_C for the threshold (negative: LCFA)
     double* q_aux2;             // beyond-LCFA: gamma of the pushed momentum minus gamma^{(n)}
     uint32_t* q_count;          // [2 slices]: lepton and photon emitters queued in each slice
+    uint32_t* q_sbcount;        // [2 grid]: the same summed over each streaming block's slices
     unsigned long long* q_proc; // [grid]: particles processed by each block of the streaming pass
-    unsigned long long* q_base; // [3 slices]: first product slot of each slice (photons, e-, e+)
     uint64_t q_cap_per_wave;    // entries of one slice
     // Shares that did not fit: a wave whose slice could not take every particle of its share of
     // a chunk (STEP_BLOCK/64 waves share a chunk) leaves that share untouched and appends
     // chunk * STEP_WAVES + wave here; the emitter kernel steps those shares afterwards.
     uint32_t* d_list;
-    unsigned* d_ctl;            // [4]: shares deferred, next share to step, emitter blocks done
+    unsigned* d_ctl;            // [4]: shares deferred, next share to step, deferred-share
+                                // blocks done, emitter blocks done
     unsigned* obs;              // nullable, host-mapped: [0] the largest emitter fraction of a
                                 // wave's share (float bits), [1] shares deferred (for sizing)
     int grid;                   // blocks of the streaming kernel (STEP_WAVES slices each)
@@ -103,7 +105,7 @@ struct StepArgs {
     int push;                    // leptons get the Boris push before the step
     int wave;                    // some tile gives its fields as a plane wave
     int zero_counts;             // the step's product counts start from zero (nsets == 0: the
-                                 // scan kernel takes the bases as 0 instead of reading them)
+                                 // emitter kernel takes the bases as 0 instead of reading them)
 };
 
 enum { CNT_PROCESSED, CNT_EMITTED, CNT_CONVERTED, CNT_REJECTED, CNT_OOD, CNT_CLAMPED, CNT_OVERFLOW,
@@ -433,6 +435,28 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long* s_tm
     return r;
 }
 
+// Sums of two values over the block (every thread gets both); s_tmp: two words of shared
+// memory the caller is not using.
+__device__ __forceinline__ void block_sum2(unsigned long long* s_tmp, unsigned long long& a,
+                                          unsigned long long& b)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_down(a, o);
+        b += __shfl_down(b, o);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) s_tmp[0] = s_tmp[1] = 0;
+    __syncthreads();
+    if (lane_id() == 0) {
+        if (a) atomicAdd(&s_tmp[0], a);
+        if (b) atomicAdd(&s_tmp[1], b);
+    }
+    __syncthreads();
+    a = s_tmp[0];
+    b = s_tmp[1];
+    __syncthreads();
+}
+
 __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
                                                    sfq_counters* global,
                                                    const unsigned long long (&vals)[CNT_N])
@@ -451,7 +475,7 @@ __device__ __forceinline__ void block_add_counters(unsigned long long* s_cnt,
 // =============================================================================================
 // Emitter work of one lane (wave-cooperative: every lane of the wave calls it; lanes with
 // valid == false pass through): Philox draws, the energy sample, recoil written in place and
-// the products.  Product slots come from the scan (k_ph, k_el, k_po: this lane's slots), or,
+// the products.  Product slots come from the caller (k_ph, k_el, k_po: this lane's slots), or,
 // with atomic_slots (and always for beyond-LCFA photons and per-set products), from one atomic
 // per wave and buffer.
 // =============================================================================================
@@ -481,8 +505,9 @@ __device__ __forceinline__ void emit_one(const StepArgs& A, bool valid, bool pai
     if (!valid) { chi = 1.0; gamma = 1.0; px = py = pz = 0.0; }
     Draw d1{0, 0}, d2{0, 0};
     if (valid) {
-        // with optical-depth decisions the streaming pass did not read the id
-        uid = LOCAL ? quid : A.tiles[t].uid[i];
+        // with optical-depth decisions the streaming pass did not read the id (a non-temporal
+        // load: the scattered line is not kept in the caches)
+        uid = LOCAL ? quid : ld_stream(&A.tiles[t].uid[i]);
         step = base_step + (uint32_t)A.tiles[t].step_offset;
         d1 = philox_draw(A.seed, uid, step, SFQ_P_EMIT);
         d2 = philox_draw(A.seed, uid, step, SFQ_P_CHILD);
@@ -803,6 +828,7 @@ __device__ __forceinline__ void lcfa_wave_pairs(const StepArgs& A, const sfq_til
 }
 
 typedef double dv2 __attribute__((ext_vector_type(2)));
+
 // LCFA chunks of array tiles (optical-depth decisions), two adjacent particles per lane per
 // iteration: every array is read and the optical depths (and, with the fused push, the pushed
 // momenta) written with 16-byte accesses
@@ -1152,33 +1178,35 @@ __device__ __forceinline__ void stream_chunk(const StepArgs& A, int c, int tid, 
     }
 }
 
-template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE>
-__global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) void bulk_kernel(StepArgs A)
+// The streaming work of block b of G: chunks b, b + G, ...; its waves' queue slices
+// STEP_WAVES b ... .  s_tmp: two words of shared memory.
+template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE, typename RT>
+__device__ __forceinline__ void stream_block(const StepArgs& A, int b, int G, RT* s_rad,
+                                             RT* s_pair, unsigned long long* s_cnt,
+                                             unsigned long long* s_tmp)
 {
     static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
-    using RT = typename std::conditional<MIXED, float, double>::type;
-    __shared__ RT s_rad[RAD_SIZE];
-    __shared__ RT s_pair[PAIR_SIZE];
-    __shared__ unsigned long long s_cnt[CNT_N];
-
     const int tid = threadIdx.x;
     const RT* g_rad = MIXED ? (const RT*)A.tb.rad32 : (const RT*)A.tb.rad;
     const RT* g_pair = MIXED ? (const RT*)A.tb.pair32 : (const RT*)A.tb.pair;
     for (int k = tid; k < RAD_SIZE; k += STEP_BLOCK) s_rad[k] = g_rad[k];
     for (int k = tid; k < PAIR_SIZE; k += STEP_BLOCK) s_pair[k] = g_pair[k];
     if (tid < CNT_N) s_cnt[tid] = 0;
+    // beyond-LCFA photons take their slots by atomics in the emitter kernel: a step whose
+    // product counts start from zero starts that count here
+    if (BLCFA && A.zero_counts && A.nsets == 0 && b == 0 && tid == 0) A.prod_counts[0] = 0;
     __syncthreads();
 
     unsigned long long c_proc = 0, c_ood = 0;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const uint64_t slice = (uint64_t)blockIdx.x * STEP_WAVES + (uint64_t)wv;
+    const uint64_t slice = (uint64_t)b * STEP_WAVES + (uint64_t)wv;
     QueueSink sink{slice * A.q_cap_per_wave, 0u, 0u};
     const uint32_t share = (uint32_t)(A.chunk / STEP_WAVES);  // most particles of a wave's share
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
 
-    for (int c = blockIdx.x; c < A.nchunks; c += gridDim.x) {
+    for (int c = b; c < A.nchunks; c += G) {
         // a share whose every particle might emit must fit the slice; otherwise it is left
-        // untouched for the emitter kernel to step (no result depends on which wave steps it)
+        // untouched for the deferred-share kernel (no result depends on which wave steps it)
         if (A.q_cap_per_wave - (uint64_t)(sink.nl + sink.np) < (uint64_t)share) {
             if (lane_id() == 0) {
                 const unsigned k = atomicAdd(&A.d_ctl[0], 1u);
@@ -1193,155 +1221,117 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
         A.q_count[2 * slice] = sink.nl;
         A.q_count[2 * slice + 1] = sink.np;
     }
-    // the block's processed count goes to the queue for the scan kernel (no global atomic:
+    // the block's totals (what the emitter kernel sums over earlier blocks) and the block's
+    // processed count go to the queue for the emitter kernel (no global atomic:
     // thousands of blocks adding to one word serialise); the rare out-of-domain count is added
-    __shared__ unsigned long long s_tmp[1];
+    unsigned long long tl = lane_id() == 0 ? sink.nl : 0u, tp = lane_id() == 0 ? sink.np : 0u;
+    block_sum2(s_tmp, tl, tp);
     const unsigned long long proc = block_sum(s_tmp, c_proc);
-    if (tid == 0) A.q_proc[blockIdx.x] = proc;
+    if (tid == 0) {
+        A.q_sbcount[2 * b] = (uint32_t)tl;
+        A.q_sbcount[2 * b + 1] = (uint32_t)tp;
+        A.q_proc[b] = proc;
+    }
     const unsigned long long vals[CNT_N] = {0, 0, 0, 0, c_ood, 0, 0, 0};
     block_add_counters(s_cnt, A.counters, vals);
 }
 
-// Between the two passes, one block: each queue slice's first product slot (exclusive prefix
-// sums of the queued emitters over the slices, from the current product counts), the new
-// product counts, and the step's processed / emitted / converted counters, each written once.
-// Every queued lepton emits and every queued photon converts, except that beyond-LCFA
-// rejections are only known in the emitter pass, which then reserves photon slots itself.
-// The largest emitter fraction of a wave's share goes to A.obs (when set) for queue sizing.
-constexpr int SCAN_BLOCK = 256;
-
-// inclusive prefix sum over the 64 lanes of a wave
-__device__ __forceinline__ unsigned long long wave_inclusive_scan(unsigned long long v)
+template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE>
+__global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) void bulk_kernel(StepArgs A)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long u = __shfl_up(v, o);
-        if (lane >= o) v += u;
-    }
-    return v;
+    using RT = typename std::conditional<MIXED, float, double>::type;
+    __shared__ RT s_rad[RAD_SIZE];
+    __shared__ RT s_pair[PAIR_SIZE];
+    __shared__ unsigned long long s_cnt[CNT_N];
+    __shared__ unsigned long long s_tmp[2];
+    stream_block<MIXED, BLCFA, LOCAL, PUSH, WAVE>(A, (int)blockIdx.x, (int)gridDim.x, s_rad,
+                                                   s_pair, s_cnt, s_tmp);
 }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void scan_kernel(StepArgs A)
-{
-    constexpr int NW = SCAN_BLOCK / 64;
-    __shared__ unsigned long long s_w[3][NW];
-    __shared__ unsigned s_fmax;
-    const int tid = threadIdx.x, w = tid >> 6, G = A.grid, S = A.grid * STEP_WAVES;
-    if (tid == 0) s_fmax = 0;
-    const int per = (S + SCAN_BLOCK - 1) / SCAN_BLOCK;
-    const int lo = min(tid * per, S), hi = min(lo + per, S);
-    unsigned long long nl = 0, np = 0, proc = 0;
-    float fmax = 0.0f;
-    for (int b = lo; b < hi; ++b) {
-        const unsigned a = A.q_count[2 * b], c = A.q_count[2 * b + 1];
-        nl += a;
-        np += c;
-        if (A.obs) {
-            // particles of the wave's shares: its block's chunks times a share
-            const int blk = b / STEP_WAVES;
-            const int chunks = (A.nchunks - blk + G - 1) / G;
-            const float room = (float)chunks * (float)(A.chunk / STEP_WAVES);
-            if (room > 0.0f) fmax = fmaxf(fmax, (float)(a + c) / room);
-        }
-    }
-    for (int b = tid; b < G; b += SCAN_BLOCK) proc += A.q_proc[b];
-    // block-wide inclusive scans: within each wave, then over the wave totals
-    unsigned long long il = wave_inclusive_scan(nl), ip = wave_inclusive_scan(np);
-    const unsigned long long in = wave_inclusive_scan(proc);
-    if ((tid & 63) == 63) { s_w[0][w] = il; s_w[1][w] = ip; s_w[2][w] = in; }
-    __syncthreads();
-    unsigned long long tl = 0, tp = 0, tn = 0;
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-        if (k < w) { il += s_w[0][k]; ip += s_w[1][k]; }
-        tl += s_w[0][k]; tp += s_w[1][k]; tn += s_w[2][k];
-    }
-    const bool multi = A.nsets > 0;
-    // zeroed counts: the bases are 0 (no separate zeroing kernel before the step)
-    const bool from0 = multi || A.zero_counts;
-    const unsigned long long b0 = from0 ? 0ull : A.prod_counts[0];
-    const unsigned long long b1 = from0 ? 0ull : A.prod_counts[1];
-    const unsigned long long b2 = from0 ? 0ull : A.prod_counts[2];
-    unsigned long long run_l = il - nl, run_p = ip - np;
-    for (int b = lo; b < hi; ++b) {
-        A.q_base[3 * b] = b0 + run_l;
-        A.q_base[3 * b + 1] = b1 + run_p;
-        A.q_base[3 * b + 2] = b2 + run_p;
-        run_l += A.q_count[2 * b];
-        run_p += A.q_count[2 * b + 1];
-    }
-    if (A.obs && fmax > 0.0f) atomicMax(&s_fmax, __float_as_uint(fmax));  // fmax >= 0
-    __syncthreads();  // every read of the product counts happens before they are advanced
-    if (tid == 0) {
-        if (!multi) {
-            // beyond-LCFA photons take their slots in the emitter kernel, from this count
-            if (!A.blcfa) A.prod_counts[0] = b0 + tl;
-            else if (A.zero_counts) A.prod_counts[0] = 0;
-            A.prod_counts[1] = b1 + tp;
-            A.prod_counts[2] = b2 + tp;
-        }
-        atomicAdd(&A.counters->processed, tn);
-        if (!A.blcfa) atomicAdd(&A.counters->emitted, tl);
-        atomicAdd(&A.counters->converted, tp);
-        if (A.obs) {
-            // observations for sizing the queue (plain stores to host memory, which the host
-            // reads at a later step; a late or overwritten value only delays a resize)
-            A.obs[0] = s_fmax;
-            A.obs[1] = A.d_ctl[0];
-        }
-    }
-}
 
 // Emitter pass: the slices of streaming block qb are sampled by emit_split blocks with every
 // lane busy, each taking a contiguous range of their entries: Philox draws, inverse-CDF tables,
-// recoil and products at the scanned slots.
+// recoil and products.
+// Product slots: every queued lepton emits one photon and every queued photon converts into
+// one pair (beyond-LCFA rejections are only known here, so that mode takes photon slots by
+// atomics, and steps with per-tile product sets by atomics per set).  A block's slots start at
+// the product counts before the step plus the emitters queued by every earlier streaming
+// block: each block sums those counts itself (one coalesced read of the per-block totals),
+// and the last block out advances the product counts and adds the step's processed / emitted /
+// converted counters, each once, so no scan kernel runs between the two passes.
+struct EmitShared {
+    unsigned cum[2 * STEP_WAVES + 1];
+    unsigned long long base[3 * STEP_WAVES];
+    unsigned long long tmp[2];
+    uint2 own[STEP_WAVES];
+    unsigned long long b[3];
+};
+
+// The emitter work of one block (every thread calls it): part `part` of the entries queued by
+// streaming block qb.
 template <bool MIXED, bool BLCFA, bool LOCAL>
-__global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepArgs A)
+__device__ __forceinline__ void emit_item(const StepArgs& A, int qb, int part, EmitCounts& C,
+                                          EmitShared& sh)
 {
     static_assert(LOCAL || !BLCFA, "beyond-LCFA steps use local decisions");
-    __shared__ unsigned long long s_cnt[CNT_N];
-    __shared__ unsigned s_cum[2 * STEP_WAVES + 1];
-    __shared__ unsigned long long s_base[3 * STEP_WAVES];
     const int tid = threadIdx.x;
-    if (tid < CNT_N) s_cnt[tid] = 0;
-    const int qb = blockIdx.x / A.emit_split, part = blockIdx.x % A.emit_split;
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
     const bool multi = A.nsets > 0;
-    // the block's slices in order: leptons then photons of slice 0, of slice 1, ...
+    // zeroed counts: the bases are 0 (no separate zeroing kernel before the step)
+    const bool from0 = multi || A.zero_counts;
+    const uint2* qc = reinterpret_cast<const uint2*>(A.q_count);
+    // the emitters queued by the streaming blocks before qb, qb's own slice counts and the
+    // product counts before the step (only the last block out changes them, after every block
+    // has read them here): all loads issued together, one memory round trip
+    unsigned long long pl = 0, pp = 0;
+    {
+        const uint2* qs = reinterpret_cast<const uint2*>(A.q_sbcount);
+#pragma unroll 4
+        for (int k = tid; k < qb; k += STEP_BLOCK) {
+            const uint2 c = qs[k];
+            pl += c.x;
+            pp += c.y;
+        }
+        const int s_lo = qb * STEP_WAVES;
+        if (tid < STEP_WAVES) sh.own[tid] = qc[s_lo + tid];
+        else if (tid < STEP_WAVES + 3)
+            sh.b[tid - STEP_WAVES] = from0 ? 0ull : A.prod_counts[tid - STEP_WAVES];
+    }
+    block_sum2(sh.tmp, pl, pp);  // its barriers also publish sh.own and sh.b
+    // qb's slices in order: leptons then photons of slice 0, of slice 1, ...
     if (tid == 0) {
         unsigned acc = 0;
+        unsigned long long rl = pl, rp = pp;
         for (int w = 0; w < STEP_WAVES; ++w) {
-            const uint64_t sl = (uint64_t)qb * STEP_WAVES + w;
-            s_cum[2 * w] = acc;
-            acc += A.q_count[2 * sl];
-            s_cum[2 * w + 1] = acc;
-            acc += A.q_count[2 * sl + 1];
+            const uint2 c = sh.own[w];
+            sh.cum[2 * w] = acc;
+            acc += c.x;
+            sh.cum[2 * w + 1] = acc;
+            acc += c.y;
+            // this slice's first photon, electron and positron slots
+            sh.base[3 * w] = multi ? 0ull : sh.b[0] + rl;
+            sh.base[3 * w + 1] = multi ? 0ull : sh.b[1] + rp;
+            sh.base[3 * w + 2] = multi ? 0ull : sh.b[2] + rp;
+            rl += c.x;
+            rp += c.y;
         }
-        s_cum[2 * STEP_WAVES] = acc;
+        sh.cum[2 * STEP_WAVES] = acc;
     }
-    // product slots of the block's slices, from the scan kernel: one photon per lepton emitter
-    // and one electron-positron pair per converting photon (beyond-LCFA rejections leave no
-    // product, so that mode reserves photon slots per wave instead, and steps with per-tile
-    // product sets reserve per wave and set)
-    if (tid < 3 * STEP_WAVES)
-        s_base[tid] = multi ? 0ull : A.q_base[(uint64_t)3 * STEP_WAVES * qb + tid];
     __syncthreads();
-    const unsigned total = s_cum[2 * STEP_WAVES];
-    EmitCounts C;
+    const unsigned total = sh.cum[2 * STEP_WAVES];
     const unsigned per = (total + A.emit_split - 1) / A.emit_split;
     const unsigned e_lo = min(total, per * (unsigned)part), e_hi = min(total, e_lo + per);
-    for (unsigned b0 = e_lo; b0 < e_hi; b0 += STEP_BLOCK) {
-        const unsigned e = b0 + tid;
+    for (unsigned b0e = e_lo; b0e < e_hi; b0e += STEP_BLOCK) {
+        const unsigned e = b0e + tid;
         const bool valid = e < e_hi;
         // this lane's entry: the segment (slice, species) that holds entry e
         int k = 0;
 #pragma unroll
         for (int j = 1; j < 2 * STEP_WAVES; ++j)
-            if (e >= s_cum[j]) k = j;
+            if (e >= sh.cum[j]) k = j;
         const int w = k >> 1;
         const bool pair = valid && (k & 1);
-        const unsigned rank = e - s_cum[k];
+        const unsigned rank = e - sh.cum[k];
         const uint64_t sbase = ((uint64_t)qb * STEP_WAVES + w) * A.q_cap_per_wave;
         const uint64_t slot = pair ? sbase + A.q_cap_per_wave - 1 - rank : sbase + rank;
         uint32_t i = 0;
@@ -1363,14 +1353,82 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
             }
         }
         emit_one<MIXED, BLCFA, LOCAL>(A, valid, pair, i, t, chi, gamma, px, py, pz, quid, aux,
-                                      aux2, base_step, false, s_base[3 * w] + rank,
-                                      s_base[3 * w + 1] + rank, s_base[3 * w + 2] + rank, C);
+                                      aux2, base_step, false, sh.base[3 * w] + rank,
+                                      sh.base[3 * w + 1] + rank, sh.base[3 * w + 2] + rank, C);
     }
+}
+
+template <bool MIXED, bool BLCFA, bool LOCAL>
+__global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepArgs A)
+{
+    __shared__ unsigned long long s_cnt[CNT_N];
+    __shared__ EmitShared sh;
+    __shared__ unsigned s_fmax;
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    if (tid < CNT_N) s_cnt[tid] = 0;
+    EmitCounts C;
+    emit_item<MIXED, BLCFA, LOCAL>(A, (int)blockIdx.x / A.emit_split,
+                                   (int)blockIdx.x % A.emit_split, C, sh);
     __syncthreads();
-    // emissions and conversions were counted by the scan kernel, except beyond-LCFA emissions
+    // counted by the last block below, except beyond-LCFA emissions
     const unsigned long long vals[CNT_N] = {0, BLCFA ? C.emit : 0ull, 0, C.rej, C.ood, C.clamp,
                                             C.over, 0};
     block_add_counters(s_cnt, A.counters, vals);
+    // The last block out: the step's totals.  It reads only what the streaming kernel wrote,
+    // and every block's read of the product counts returned before its count here, so no
+    // memory fence is needed (a device-scope fence would write back the whole L2 of the
+    // block's XCD, in every block).
+    if (tid == 0) {
+        const unsigned done = atomicAdd(&A.d_ctl[3], 1u);
+        s_last = done == gridDim.x - 1;
+        s_fmax = 0;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    const bool multi = A.nsets > 0;
+    const uint2* qc = reinterpret_cast<const uint2*>(A.q_count);
+    const int G = A.grid, S = G * STEP_WAVES;
+    unsigned long long tl = 0, tp = 0, proc = 0, dummy = 0;
+    float fmax = 0.0f;
+#pragma unroll 8
+    for (int sl = tid; sl < S; sl += STEP_BLOCK) {
+        const uint2 c = qc[sl];
+        tl += c.x;
+        tp += c.y;
+        if (A.obs) {
+            // the emitter fraction of the wave's shares: its block's chunks times a share
+            const int blk = sl / STEP_WAVES;
+            const int chunks = (A.nchunks - blk + G - 1) / G;
+            const float room = (float)chunks * (float)(A.chunk / STEP_WAVES);
+            if (room > 0.0f) fmax = fmaxf(fmax, (float)(c.x + c.y) / room);
+        }
+    }
+#pragma unroll 4
+    for (int b = tid; b < G; b += STEP_BLOCK) proc += A.q_proc[b];
+    if (A.obs && fmax > 0.0f) atomicMax(&s_fmax, __float_as_uint(fmax));  // fmax >= 0
+    block_sum2(sh.tmp, tl, tp);
+    block_sum2(sh.tmp, proc, dummy);
+    if (tid == 0) {
+        if (!multi) {
+            // beyond-LCFA photons took their slots by atomics from this count (which the
+            // streaming kernel zeroed when the step starts from zero)
+            if (!BLCFA) A.prod_counts[0] = (A.zero_counts ? 0ull : A.prod_counts[0]) + tl;
+            A.prod_counts[1] = (A.zero_counts ? 0ull : A.prod_counts[1]) + tp;
+            A.prod_counts[2] = (A.zero_counts ? 0ull : A.prod_counts[2]) + tp;
+        }
+        atomicAdd(&A.counters->processed, proc);
+        if (!BLCFA) atomicAdd(&A.counters->emitted, tl);
+        atomicAdd(&A.counters->converted, tp);
+        if (A.obs) {
+            // observations for sizing the queue: the largest emitter fraction of a wave's
+            // shares and the shares deferred (plain stores to host memory, which the host reads
+            // at a later step; a late or overwritten value only delays a resize)
+            A.obs[0] = s_fmax;
+            A.obs[1] = A.d_ctl[0];
+        }
+        A.d_ctl[3] = 0;
+    }
 }
 
 // The shares the streaming pass deferred (enqueued after the emitter kernel whenever the
@@ -1409,14 +1467,14 @@ __global__ __launch_bounds__(STEP_BLOCK, 1) void defer_kernel(StepArgs A)
     const unsigned long long vals[CNT_N] = {c_proc, C.emit, C.conv, C.rej, C.ood + c_ood,
                                             C.clamp, C.over, c_proc};
     block_add_counters(s_cnt, A.counters, vals);
+    // the last block out clears the deferral words (every block is past its last use of them
+    // when it counts itself out; no fence: the next kernel sees the stores)
     if (tid == 0) {
-        __threadfence();
         const unsigned done = atomicAdd(&A.d_ctl[2], 1u);
         if (done == gridDim.x - 1) {
             A.d_ctl[0] = 0;
             A.d_ctl[1] = 0;
             A.d_ctl[2] = 0;
-            __threadfence();
         }
     }
 }
@@ -1578,6 +1636,7 @@ std::vector<void*> g_scratch_ptr;  // by device ordinal
 
 struct ProfEvents {
     hipEvent_t e[3];
+    int split;  // e[1] recorded between the streaming kernel and the emitter pass
 };
 
 struct sfq_ctx {
@@ -1598,7 +1657,7 @@ struct sfq_ctx {
     uint64_t q_cap_entries = 0, q_cap_slices = 0, q_cap_grid = 0, q_cap_deferrable = 0;
     double q_frac = 0.125;
     int q_adaptive = 1;
-    unsigned* obs_host = nullptr;  // pinned, mapped: the scan kernel's observations
+    unsigned* obs_host = nullptr;  // pinned, mapped: the emitter kernel's observations
     unsigned* obs_dev = nullptr;
     // The end of the handle's last step (its own step_done event, or the step's timing event
     // when timing is on): a step on another stream waits for it, since steps share the queue.
@@ -1829,7 +1888,7 @@ sfq_status sfq_create(const sfq_config* cfg, sfq_handle* out)
     }
     h->approx = cfg->approx;
     h->ph.trunc = h->tb.trunc = (cfg->approx == SFQ_APPROX_TRUNCATED) ? 1 : 0;
-    // the scan kernel's observations for sizing the emitter queue: pinned host memory the
+    // the emitter kernel's observations for sizing the emitter queue: pinned host memory the
     // kernel writes directly (without it the queue keeps its initial size)
     void* obs = nullptr;
     if (hipHostMalloc(&obs, 256, hipHostMallocMapped) == hipSuccess) {
@@ -2131,10 +2190,11 @@ static size_t queue_entry_bytes(const sfq_ctx* h)
     return 48 + (h->decision == SFQ_LOCAL ? 8 : 0) + (h->blcfa ? 16 : 0);
 }
 
-// Queue memory: the deferral words (d_ctl, the first 256 bytes), per slice 2 counts and 3
-// product bases, per block the processed count, the deferred-share list, then the entries.
+// Queue memory: the deferral words (d_ctl, the first 256 bytes), per slice 2 counts, per
+// streaming block their 2 sums and its processed count, the deferred-share list, then the
+// entries.
 struct QueueLayout {
-    size_t count, proc, base, dlist, soa, total;
+    size_t count, sbcount, proc, dlist, soa, total;
 };
 
 static QueueLayout queue_layout(const sfq_ctx* h, const QueueShape& q)
@@ -2142,9 +2202,9 @@ static QueueLayout queue_layout(const sfq_ctx* h, const QueueShape& q)
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     QueueLayout L;
     L.count = 256;
-    L.proc = al(L.count + 8 * q.slices);
-    L.base = al(L.proc + 8 * (size_t)q.grid);
-    L.dlist = al(L.base + 24 * q.slices);
+    L.sbcount = al(L.count + 8 * q.slices);
+    L.proc = al(L.sbcount + 8 * (size_t)q.grid);
+    L.dlist = al(L.proc + 8 * (size_t)q.grid);
     L.soa = al(L.dlist + 4 * q.deferrable);
     L.total = L.soa + q.entries * queue_entry_bytes(h);
     return L;
@@ -2193,8 +2253,8 @@ static void bind_queue(const sfq_ctx* h, StepArgs& A, void* mem, const QueueShap
     A.q_tile = (uint32_t*)(q + pos + 4 * E);
     A.d_ctl = (unsigned*)base;
     A.q_count = (uint32_t*)(base + L.count);
+    A.q_sbcount = (uint32_t*)(base + L.sbcount);
     A.q_proc = (unsigned long long*)(base + L.proc);
-    A.q_base = (unsigned long long*)(base + L.base);
     A.d_list = (uint32_t*)(base + L.dlist);
     A.q_cap_per_wave = qs.cap_per_wave;
     A.grid = qs.grid;
@@ -2251,9 +2311,13 @@ static ProfEvents* prof_events(sfq_ctx* h)
     }
     h->prof_used.push_back(h->prof_free.back());
     h->prof_free.pop_back();
+    h->prof_used.back().split = h->prof == 1;
     return &h->prof_used.back();
 }
 
+// The step's kernels, with the timing events (pe: before the streaming kernel, between it and
+// the emitter pass when the timing is split, after the step's last kernel) when the step is
+// timed.
 static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, hipStream_t st,
                                 const ProfEvents* pe = nullptr)
 {
@@ -2261,50 +2325,49 @@ static void launch_step_kernels(const sfq_ctx* h, const StepArgs& A, int grid, h
     if (pe) (void)hipEventRecord(pe->e[0], st);
     const bool mixed = h->precision == SFQ_MIXED, local = h->decision == SFQ_LOCAL;
     const dim3 ge(grid * A.emit_split);
-#define SFQ_LAUNCH_FORM(K, G, M, BL, L)                                                        \
+#define SFQ_LAUNCH_FORM(K, G, M, BL, L, X)                                                     \
     do {                                                                                       \
-        if (A.push) {                                                                          \
-            if (A.wave) hipLaunchKernelGGL((K<M, BL, L, true, true>), G, b, 0, st, A);         \
-            else hipLaunchKernelGGL((K<M, BL, L, true, false>), G, b, 0, st, A);               \
+        if (X.push) {                                                                          \
+            if (X.wave) hipLaunchKernelGGL((K<M, BL, L, true, true>), G, b, 0, st, X);         \
+            else hipLaunchKernelGGL((K<M, BL, L, true, false>), G, b, 0, st, X);               \
         } else {                                                                               \
-            if (A.wave) hipLaunchKernelGGL((K<M, BL, L, false, true>), G, b, 0, st, A);        \
-            else hipLaunchKernelGGL((K<M, BL, L, false, false>), G, b, 0, st, A);              \
+            if (X.wave) hipLaunchKernelGGL((K<M, BL, L, false, true>), G, b, 0, st, X);        \
+            else hipLaunchKernelGGL((K<M, BL, L, false, false>), G, b, 0, st, X);              \
         }                                                                                      \
     } while (0)
-#define SFQ_LAUNCH(K, G)                                                                       \
+#define SFQ_LAUNCH_ARGS(K, G, X)                                                               \
     do {                                                                                       \
         if (h->blcfa) {                                                                        \
-            if (mixed) SFQ_LAUNCH_FORM(K, G, true, true, true);                                \
-            else SFQ_LAUNCH_FORM(K, G, false, true, true);                                     \
+            if (mixed) SFQ_LAUNCH_FORM(K, G, true, true, true, X);                             \
+            else SFQ_LAUNCH_FORM(K, G, false, true, true, X);                                  \
         } else if (mixed) {                                                                    \
-            if (local) SFQ_LAUNCH_FORM(K, G, true, false, true);                               \
-            else SFQ_LAUNCH_FORM(K, G, true, false, false);                                    \
+            if (local) SFQ_LAUNCH_FORM(K, G, true, false, true, X);                            \
+            else SFQ_LAUNCH_FORM(K, G, true, false, false, X);                                 \
         } else {                                                                               \
-            if (local) SFQ_LAUNCH_FORM(K, G, false, false, true);                              \
-            else SFQ_LAUNCH_FORM(K, G, false, false, false);                                   \
+            if (local) SFQ_LAUNCH_FORM(K, G, false, false, true, X);                           \
+            else SFQ_LAUNCH_FORM(K, G, false, false, false, X);                                \
         }                                                                                      \
     } while (0)
-#define SFQ_LAUNCH_EMIT(K, G)                                                                  \
+#define SFQ_LAUNCH_EMIT(K, G, X)                                                               \
     do {                                                                                       \
         if (mixed) {                                                                           \
-            if (h->blcfa) hipLaunchKernelGGL((K<true, true, true>), G, b, 0, st, A);           \
-            else if (local) hipLaunchKernelGGL((K<true, false, true>), G, b, 0, st, A);        \
-            else hipLaunchKernelGGL((K<true, false, false>), G, b, 0, st, A);                  \
+            if (h->blcfa) hipLaunchKernelGGL((K<true, true, true>), G, b, 0, st, X);           \
+            else if (local) hipLaunchKernelGGL((K<true, false, true>), G, b, 0, st, X);        \
+            else hipLaunchKernelGGL((K<true, false, false>), G, b, 0, st, X);                  \
         } else {                                                                               \
-            if (h->blcfa) hipLaunchKernelGGL((K<false, true, true>), G, b, 0, st, A);          \
-            else if (local) hipLaunchKernelGGL((K<false, false, true>), G, b, 0, st, A);       \
-            else hipLaunchKernelGGL((K<false, false, false>), G, b, 0, st, A);                 \
+            if (h->blcfa) hipLaunchKernelGGL((K<false, true, true>), G, b, 0, st, X);          \
+            else if (local) hipLaunchKernelGGL((K<false, false, true>), G, b, 0, st, X);       \
+            else hipLaunchKernelGGL((K<false, false, false>), G, b, 0, st, X);                 \
         }                                                                                      \
     } while (0)
-    SFQ_LAUNCH(bulk_kernel, g);
-    if (pe) (void)hipEventRecord(pe->e[1], st);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, A);
-    SFQ_LAUNCH_EMIT(emit_kernel, ge);
+    SFQ_LAUNCH_ARGS(bulk_kernel, g, A);
+    if (pe && pe->split) (void)hipEventRecord(pe->e[1], st);
+    SFQ_LAUNCH_EMIT(emit_kernel, ge, A);
     // the deferred shares, when the queue may have been too small for some
     const dim3 gd(2 * h->num_cus);
-    if (A.may_defer) SFQ_LAUNCH(defer_kernel, gd);
+    if (A.may_defer) SFQ_LAUNCH_ARGS(defer_kernel, gd, A);
 #undef SFQ_LAUNCH_EMIT
-#undef SFQ_LAUNCH
+#undef SFQ_LAUNCH_ARGS
 #undef SFQ_LAUNCH_FORM
     if (pe) (void)hipEventRecord(pe->e[2], st);
 }
@@ -2334,7 +2397,7 @@ static void plan_release(sfq_plan_t* p)
 }
 
 // Zeroes the product counts of a step with product sets (a kernel, not a memset, so graphs
-// replay it safely).  Steps without sets need none: their scan kernel starts from zero.
+// replay it safely).  Steps without sets need none: their emitter kernel starts from zero.
 static void enqueue_zero_counts(const StepArgs& A, hipStream_t st)
 {
     if (A.nsets > 0)
@@ -2349,10 +2412,7 @@ static void plan_enqueue(sfq_plan_t* p, hipStream_t st, const ProfEvents* pe = n
     hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, st, p->d_step);
 }
 
-// Grows the handle's emitter queue to hold a step of shape qs (caller holds h->mu).  Growing
-// waits for the device, since in-flight steps may still use the old queue; a new queue starts
-// with its deferral words cleared.
-static sfq_status ensure_queue(sfq_ctx* h, const QueueShape& qs, const char* who)
+static QueueShape queue_capacity(const sfq_ctx* h)
 {
     QueueShape cap;
     cap.may_defer = 0;
@@ -2361,6 +2421,15 @@ static sfq_status ensure_queue(sfq_ctx* h, const QueueShape& qs, const char* who
     cap.entries = h->q_cap_entries;
     cap.deferrable = h->q_cap_deferrable;
     cap.cap_per_wave = 0;
+    return cap;
+}
+
+// Grows the handle's emitter queue to hold a step of shape qs (caller holds h->mu).  Growing
+// waits for the device, since in-flight steps may still use the old queue; a new queue starts
+// with its deferral words cleared.
+static sfq_status ensure_queue(sfq_ctx* h, const QueueShape& qs, const char* who)
+{
+    QueueShape cap = queue_capacity(h);
     if (h->d_queue && queue_fits(cap, qs)) return SFQ_OK;
     QueueShape want = qs;
     if (h->d_queue) {
@@ -2385,17 +2454,6 @@ static sfq_status ensure_queue(sfq_ctx* h, const QueueShape& qs, const char* who
     return SFQ_OK;
 }
 
-static QueueShape queue_capacity(const sfq_ctx* h)
-{
-    QueueShape cap;
-    cap.may_defer = 0;
-    cap.grid = (int)h->q_cap_grid;
-    cap.slices = h->q_cap_slices;
-    cap.entries = h->q_cap_entries;
-    cap.deferrable = h->q_cap_deferrable;
-    cap.cap_per_wave = 0;
-    return cap;
-}
 
 // What the last completed steps observed (the largest emitter fraction of a wave's share,
 // shares deferred): the queue grows to twice the observed fraction, faster after deferrals
@@ -2458,7 +2516,9 @@ sfq_status sfq_profile_enable(sfq_handle h, int enable)
 {
     if (!h) return fail(h, SFQ_E_STATE, "sfq_profile_enable: NULL handle");
     std::lock_guard<std::mutex> lock(h->mu);
-    h->prof = enable ? 1 : 0;
+    if (enable < 0 || enable > 2)
+        return fail(h, SFQ_E_ARG, "sfq_profile_enable: enable must be 0, 1 or 2");
+    h->prof = enable;
     return SFQ_OK;
 }
 
@@ -2475,8 +2535,13 @@ sfq_status sfq_profile_read_steps(sfq_handle h, uint64_t max_steps, float* strea
     uint64_t k = 0;
     for (auto& pe : h->prof_used) {
         HIP_TRY(h, hipEventSynchronize(pe.e[2]));
-        HIP_TRY(h, hipEventElapsedTime(&stream_ms[k], pe.e[0], pe.e[1]));
-        HIP_TRY(h, hipEventElapsedTime(&emit_ms[k], pe.e[1], pe.e[2]));
+        if (pe.split) {
+            HIP_TRY(h, hipEventElapsedTime(&stream_ms[k], pe.e[0], pe.e[1]));
+            HIP_TRY(h, hipEventElapsedTime(&emit_ms[k], pe.e[1], pe.e[2]));
+        } else {
+            HIP_TRY(h, hipEventElapsedTime(&stream_ms[k], pe.e[0], pe.e[2]));
+            emit_ms[k] = 0.0f;
+        }
         ++k;
     }
     h->prof_free.insert(h->prof_free.end(), h->prof_used.begin(), h->prof_used.end());
@@ -2495,8 +2560,12 @@ sfq_status sfq_profile_read(sfq_handle h, double* stream_ms, double* emit_ms, ui
     for (auto& pe : h->prof_used) {
         HIP_TRY(h, hipEventSynchronize(pe.e[2]));
         float t1 = 0, t2 = 0;
-        HIP_TRY(h, hipEventElapsedTime(&t1, pe.e[0], pe.e[1]));
-        HIP_TRY(h, hipEventElapsedTime(&t2, pe.e[1], pe.e[2]));
+        if (pe.split) {
+            HIP_TRY(h, hipEventElapsedTime(&t1, pe.e[0], pe.e[1]));
+            HIP_TRY(h, hipEventElapsedTime(&t2, pe.e[1], pe.e[2]));
+        } else {
+            HIP_TRY(h, hipEventElapsedTime(&t1, pe.e[0], pe.e[2]));
+        }
         a += t1;
         b += t2;
     }
@@ -2771,7 +2840,11 @@ sfq_status sfq_plan_launch(sfq_plan p, void* stream)
     if (!p) return fail(nullptr, SFQ_E_STATE, "sfq_plan_launch: NULL plan");
     HIP_TRY(p->h, hipSetDevice(p->h->device));
     std::lock_guard<std::mutex> lock(p->h->mu);
-    plan_enqueue(p, (hipStream_t)stream, prof_events(p->h));
+    // a launch captured into the caller's graph is not timed
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(p->h, hipStreamIsCapturing((hipStream_t)stream, &cap));
+    plan_enqueue(p, (hipStream_t)stream,
+                 cap == hipStreamCaptureStatusNone ? prof_events(p->h) : nullptr);
     HIP_TRY(p->h, hipGetLastError());
     return SFQ_OK;
 }

@@ -32,7 +32,8 @@ STATUS = {0: "SFQ_OK", 1: "SFQ_E_ARG", 2: "SFQ_E_STATE", 3: "SFQ_E_NOMEM", 4: "S
 # every symbol declared in include/sfq.h
 EXPORTS = ("sfq_create", "sfq_destroy", "sfq_last_error", "sfq_units", "sfq_chi", "sfq_rates",
            "sfq_sample_photon", "sfq_sample_pair", "sfq_philox", "sfq_init_optical_depth",
-           "sfq_step", "sfq_step_noalloc", "sfq_set_launch", "sfq_get_launch", "sfq_plan_create", "sfq_plan_destroy",
+           "sfq_step", "sfq_step_noalloc", "sfq_set_launch", "sfq_get_launch", "sfq_plan_create",
+           "sfq_plan_destroy",
            "sfq_plan_launch", "sfq_plan_set_step", "sfq_plan_capture", "sfq_plan_replay",
            "sfq_reserve", "sfq_set_queue", "sfq_queue_bytes", "sfq_profile_enable",
            "sfq_profile_read", "sfq_profile_read_steps")
@@ -242,9 +243,12 @@ class Handle:
         self._check(self._L.sfq_queue_bytes(self._h, C.byref(v)))
         return v.value
 
-    def profile(self, enable: bool = True):
-        """Start/stop timing the two step kernels of every step with HIP events."""
-        self._check(self._L.sfq_profile_enable(self._h, int(enable)))
+    def profile(self, enable: bool = True, whole_step: bool = False):
+        """Start/stop timing every step with HIP events: the streaming kernel and the emitter
+        pass apart, or with `whole_step` the step as a whole (one event record fewer between
+        the kernels; the emitter-pass times read as 0)."""
+        mode = (2 if whole_step else 1) if enable else 0
+        self._check(self._L.sfq_profile_enable(self._h, mode))
         self.profiling = bool(enable)
 
     def profile_read(self):
