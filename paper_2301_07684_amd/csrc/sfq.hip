@@ -82,18 +82,21 @@ struct StepArgs {
     double* q_aux;              // beyond-LCFA tau/tau_C for the threshold (negative: LCFA)
     double* q_aux2;             // beyond-LCFA: gamma of the pushed momentum minus gamma^{(n)}
     uint32_t* q_count;          // [2 slices]: lepton and photon emitters queued in each slice
-    uint32_t* q_sbcount;        // [2 grid]: the same summed over each streaming block's slices
+    uint32_t* q_sbcount;        // [4 grid]: per streaming block its slices' two sums, the chunks
+                                // it took and a spare word
     unsigned long long* q_proc; // [grid]: particles processed by each block of the streaming pass
     uint64_t q_cap_per_wave;    // entries of one slice
     // Shares that did not fit: a wave whose slice could not take every particle of its share of
     // a chunk (STEP_BLOCK/64 waves share a chunk) leaves that share untouched and appends
     // chunk * STEP_WAVES + wave here; the emitter kernel steps those shares afterwards.
     uint32_t* d_list;
-    unsigned* d_ctl;            // [4]: shares deferred, next share to step, deferred-share
-                                // blocks done, emitter blocks done
+    unsigned* d_ctl;            // [5]: shares deferred, next share to step, deferred-share
+                                // blocks done, emitter blocks done, next chunk to stream
     unsigned* obs;              // nullable, host-mapped: [0] the largest emitter fraction of a
                                 // wave's share (float bits), [1] shares deferred (for sizing)
     int grid;                   // blocks of the streaming kernel (STEP_WAVES slices each)
+    int max_chunks;             // the most chunks one streaming block takes (the queue's worst
+                                // case is sized for it)
     int emit_split;             // emitter blocks per streaming block's slices
     int may_defer;              // the slices are smaller than the step's worst case (host side:
                                 // the deferred-share kernel is enqueued)
@@ -1178,8 +1181,12 @@ __device__ __forceinline__ void stream_chunk(const StepArgs& A, int c, int tid, 
     }
 }
 
-// The streaming work of block b of G: chunks b, b + G, ...; its waves' queue slices
-// STEP_WAVES b ... .  s_tmp: two words of shared memory.
+// The streaming work of block b of G: its waves' queue slices are STEP_WAVES b ... .  Chunks
+// are taken one at a time from a step-wide counter (the next one fetched while the current one
+// streams), at most A.max_chunks per block: blocks that start late or run slow take fewer, so
+// the grid finishes together instead of waiting for its slowest block's fixed share.  (Which
+// block streams a chunk changes no result, only the order of products in their buffers.)
+// s_tmp: two words of shared memory.
 template <bool MIXED, bool BLCFA, bool LOCAL, bool PUSH, bool WAVE, typename RT>
 __device__ __forceinline__ void stream_block(const StepArgs& A, int b, int G, RT* s_rad,
                                              RT* s_pair, unsigned long long* s_cnt,
@@ -1204,7 +1211,15 @@ __device__ __forceinline__ void stream_block(const StepArgs& A, int b, int G, RT
     const uint32_t share = (uint32_t)(A.chunk / STEP_WAVES);  // most particles of a wave's share
     const uint32_t base_step = A.step_ptr ? (uint32_t)*A.step_ptr : A.step;
 
-    for (int c = b; c < A.nchunks; c += G) {
+    // every chunk index the counter hands out below N is streamed (or deferred) by the block
+    // that got it; G blocks of at most max_chunks >= ceil(N / G) each take all N
+    __shared__ int s_chunk;
+    if (tid == 0) s_chunk = (int)atomicAdd(&A.d_ctl[4], 1u);
+    __syncthreads();
+    int c = s_chunk, taken = 0;
+    for (; c < A.nchunks && taken < A.max_chunks; ++taken) {
+        unsigned nxt = 0;
+        if (tid == 0 && taken + 1 < A.max_chunks) nxt = atomicAdd(&A.d_ctl[4], 1u);
         // a share whose every particle might emit must fit the slice; otherwise it is left
         // untouched for the deferred-share kernel (no result depends on which wave steps it)
         if (A.q_cap_per_wave - (uint64_t)(sink.nl + sink.np) < (uint64_t)share) {
@@ -1212,10 +1227,14 @@ __device__ __forceinline__ void stream_block(const StepArgs& A, int b, int G, RT
                 const unsigned k = atomicAdd(&A.d_ctl[0], 1u);
                 A.d_list[k] = (uint32_t)c * STEP_WAVES + (uint32_t)wv;
             }
-            continue;
+        } else {
+            stream_chunk<MIXED, BLCFA, LOCAL, PUSH, WAVE>(A, c, tid, s_rad, s_pair, sink, c_proc,
+                                                           c_ood, base_step);
         }
-        stream_chunk<MIXED, BLCFA, LOCAL, PUSH, WAVE>(A, c, tid, s_rad, s_pair, sink, c_proc,
-                                                       c_ood, base_step);
+        __syncthreads();  // every wave is done with s_chunk
+        if (tid == 0) s_chunk = taken + 1 < A.max_chunks ? (int)nxt : A.nchunks;
+        __syncthreads();
+        c = s_chunk;
     }
     if (lane_id() == 0) {
         A.q_count[2 * slice] = sink.nl;
@@ -1228,8 +1247,8 @@ __device__ __forceinline__ void stream_block(const StepArgs& A, int b, int G, RT
     block_sum2(s_tmp, tl, tp);
     const unsigned long long proc = block_sum(s_tmp, c_proc);
     if (tid == 0) {
-        A.q_sbcount[2 * b] = (uint32_t)tl;
-        A.q_sbcount[2 * b + 1] = (uint32_t)tp;
+        reinterpret_cast<uint4*>(A.q_sbcount)[b] = make_uint4((uint32_t)tl, (uint32_t)tp,
+                                                               (uint32_t)taken, 0u);
         A.q_proc[b] = proc;
     }
     const unsigned long long vals[CNT_N] = {0, 0, 0, 0, c_ood, 0, 0, 0};
@@ -1285,10 +1304,10 @@ __device__ __forceinline__ void emit_item(const StepArgs& A, int qb, int part, E
     // has read them here): all loads issued together, one memory round trip
     unsigned long long pl = 0, pp = 0;
     {
-        const uint2* qs = reinterpret_cast<const uint2*>(A.q_sbcount);
+        const uint4* qs = reinterpret_cast<const uint4*>(A.q_sbcount);
 #pragma unroll 4
         for (int k = tid; k < qb; k += STEP_BLOCK) {
-            const uint2 c = qs[k];
+            const uint4 c = qs[k];
             pl += c.x;
             pp += c.y;
         }
@@ -1366,68 +1385,87 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
     __shared__ unsigned s_fmax;
     __shared__ int s_last;
     const int tid = threadIdx.x;
+    const bool multi = A.nsets > 0;
+    const int G = A.grid;
     if (tid < CNT_N) s_cnt[tid] = 0;
+    if (blockIdx.x == 0) {
+        // Block 0 first adds the step's processed / emitted / converted counters (every queued
+        // lepton emits, every queued photon converts; beyond-LCFA acceptances are counted by
+        // the blocks) and stores the observations for sizing the queue: the largest emitter
+        // fraction of a wave's shares and the shares deferred (plain stores to host memory,
+        // which the host reads at a later step; a late or overwritten value only delays a
+        // resize).  All of it comes from what the streaming kernel wrote.
+        const uint2* qc = reinterpret_cast<const uint2*>(A.q_count);
+        const int S = G * STEP_WAVES;
+        unsigned long long tl = 0, tp = 0, proc = 0, dummy = 0;
+        float fmax = 0.0f;
+        if (tid == 0) s_fmax = 0;
+        const uint4* qs = reinterpret_cast<const uint4*>(A.q_sbcount);
+#pragma unroll 8
+        for (int sl = tid; sl < S; sl += STEP_BLOCK) {
+            const uint2 c = qc[sl];
+            tl += c.x;
+            tp += c.y;
+            if (A.obs) {
+                // the emitter fraction of the wave's shares: its block's chunks times a share
+                const unsigned chunks = qs[sl / STEP_WAVES].z;
+                const float room = (float)chunks * (float)(A.chunk / STEP_WAVES);
+                if (room > 0.0f) fmax = fmaxf(fmax, (float)(c.x + c.y) / room);
+            }
+        }
+#pragma unroll 4
+        for (int b = tid; b < G; b += STEP_BLOCK) proc += A.q_proc[b];
+        block_sum2(sh.tmp, tl, tp);  // its first barrier also publishes s_fmax = 0
+        if (A.obs && fmax > 0.0f) atomicMax(&s_fmax, __float_as_uint(fmax));  // fmax >= 0
+        block_sum2(sh.tmp, proc, dummy);
+        if (tid == 0) {
+            atomicAdd(&A.counters->processed, proc);
+            if (!BLCFA) atomicAdd(&A.counters->emitted, tl);
+            atomicAdd(&A.counters->converted, tp);
+            if (A.obs) {
+                A.obs[0] = s_fmax;
+                A.obs[1] = A.d_ctl[0];
+            }
+        }
+    }
     EmitCounts C;
     emit_item<MIXED, BLCFA, LOCAL>(A, (int)blockIdx.x / A.emit_split,
                                    (int)blockIdx.x % A.emit_split, C, sh);
     __syncthreads();
-    // counted by the last block below, except beyond-LCFA emissions
     const unsigned long long vals[CNT_N] = {0, BLCFA ? C.emit : 0ull, 0, C.rej, C.ood, C.clamp,
                                             C.over, 0};
     block_add_counters(s_cnt, A.counters, vals);
-    // The last block out: the step's totals.  It reads only what the streaming kernel wrote,
-    // and every block's read of the product counts returned before its count here, so no
-    // memory fence is needed (a device-scope fence would write back the whole L2 of the
+    // The last block out advances the product counts.  It reads only what the streaming kernel
+    // wrote, and every block's read of the product counts returned before its count here, so
+    // no memory fence is needed (a device-scope fence would write back the whole L2 of the
     // block's XCD, in every block).
     if (tid == 0) {
         const unsigned done = atomicAdd(&A.d_ctl[3], 1u);
         s_last = done == gridDim.x - 1;
-        s_fmax = 0;
     }
     __syncthreads();
     if (!s_last) return;
-    const bool multi = A.nsets > 0;
-    const uint2* qc = reinterpret_cast<const uint2*>(A.q_count);
-    const int G = A.grid, S = G * STEP_WAVES;
-    unsigned long long tl = 0, tp = 0, proc = 0, dummy = 0;
-    float fmax = 0.0f;
-#pragma unroll 8
-    for (int sl = tid; sl < S; sl += STEP_BLOCK) {
-        const uint2 c = qc[sl];
-        tl += c.x;
-        tp += c.y;
-        if (A.obs) {
-            // the emitter fraction of the wave's shares: its block's chunks times a share
-            const int blk = sl / STEP_WAVES;
-            const int chunks = (A.nchunks - blk + G - 1) / G;
-            const float room = (float)chunks * (float)(A.chunk / STEP_WAVES);
-            if (room > 0.0f) fmax = fmaxf(fmax, (float)(c.x + c.y) / room);
-        }
-    }
+    if (!multi) {
+        const uint4* qs = reinterpret_cast<const uint4*>(A.q_sbcount);
+        unsigned long long tl = 0, tp = 0;
 #pragma unroll 4
-    for (int b = tid; b < G; b += STEP_BLOCK) proc += A.q_proc[b];
-    if (A.obs && fmax > 0.0f) atomicMax(&s_fmax, __float_as_uint(fmax));  // fmax >= 0
-    block_sum2(sh.tmp, tl, tp);
-    block_sum2(sh.tmp, proc, dummy);
-    if (tid == 0) {
-        if (!multi) {
+        for (int b = tid; b < G; b += STEP_BLOCK) {
+            const uint4 c = qs[b];
+            tl += c.x;
+            tp += c.y;
+        }
+        block_sum2(sh.tmp, tl, tp);
+        if (tid == 0) {
             // beyond-LCFA photons took their slots by atomics from this count (which the
             // streaming kernel zeroed when the step starts from zero)
             if (!BLCFA) A.prod_counts[0] = (A.zero_counts ? 0ull : A.prod_counts[0]) + tl;
             A.prod_counts[1] = (A.zero_counts ? 0ull : A.prod_counts[1]) + tp;
             A.prod_counts[2] = (A.zero_counts ? 0ull : A.prod_counts[2]) + tp;
         }
-        atomicAdd(&A.counters->processed, proc);
-        if (!BLCFA) atomicAdd(&A.counters->emitted, tl);
-        atomicAdd(&A.counters->converted, tp);
-        if (A.obs) {
-            // observations for sizing the queue: the largest emitter fraction of a wave's
-            // shares and the shares deferred (plain stores to host memory, which the host reads
-            // at a later step; a late or overwritten value only delays a resize)
-            A.obs[0] = s_fmax;
-            A.obs[1] = A.d_ctl[0];
-        }
+    }
+    if (tid == 0) {
         A.d_ctl[3] = 0;
+        A.d_ctl[4] = 0;  // the next step's streaming kernel takes chunks from 0 again
     }
 }
 
@@ -2154,8 +2192,20 @@ static sfq_status validate_desc(sfq_ctx* h, const sfq_step_desc* desc, std::vect
     return SFQ_OK;
 }
 
+// The most chunks one streaming block may take: its even share and a sixteenth more (at least
+// one), so that fast blocks take over from slow ones at the end of the step (none more below 4
+// chunks per block, where a step is short and a larger worst case would only defer shares).
+// The queue's worst case is sized for it.  A small surplus keeps the emitter blocks' work,
+// which follows the streaming blocks' slices, nearly even.
+static int max_chunks_per_block(int nchunks, int grid)
+{
+    const int even = (nchunks + grid - 1) / grid;
+    return even + (even >= 4 ? std::max(1, even / 16) : 0);
+}
+
 struct QueueShape {
     int grid;                // streaming blocks
+    int max_chunks;          // max_chunks_per_block
     uint64_t slices;         // grid * STEP_WAVES: one per wave
     uint64_t cap_per_wave;   // entries of a slice
     uint64_t entries;        // slices * cap_per_wave
@@ -2172,7 +2222,8 @@ static QueueShape queue_shape(const sfq_ctx* h, int nchunks, int blocks_per_cu, 
     QueueShape q;
     q.grid = std::max(1, std::min(nchunks, h->num_cus * blocks_per_cu));
     q.slices = (uint64_t)q.grid * STEP_WAVES;
-    const uint64_t chunks_per_block = (uint64_t)((nchunks + q.grid - 1) / q.grid);
+    q.max_chunks = max_chunks_per_block(nchunks, q.grid);
+    const uint64_t chunks_per_block = (uint64_t)q.max_chunks;
     const uint64_t share = (uint64_t)chunk / STEP_WAVES;
     const uint64_t worst = chunks_per_block * share;
     const double want = (double)share + std::ceil(std::max(0.0, frac) * (double)worst);
@@ -2190,9 +2241,9 @@ static size_t queue_entry_bytes(const sfq_ctx* h)
     return 48 + (h->decision == SFQ_LOCAL ? 8 : 0) + (h->blcfa ? 16 : 0);
 }
 
-// Queue memory: the deferral words (d_ctl, the first 256 bytes), per slice 2 counts, per
-// streaming block their 2 sums and its processed count, the deferred-share list, then the
-// entries.
+// Queue memory: the control words (d_ctl, the first 256 bytes), per slice 2 counts, per
+// streaming block their 2 sums, its chunk count and its processed count, the deferred-share
+// list, then the entries.
 struct QueueLayout {
     size_t count, sbcount, proc, dlist, soa, total;
 };
@@ -2203,7 +2254,7 @@ static QueueLayout queue_layout(const sfq_ctx* h, const QueueShape& q)
     QueueLayout L;
     L.count = 256;
     L.sbcount = al(L.count + 8 * q.slices);
-    L.proc = al(L.sbcount + 8 * (size_t)q.grid);
+    L.proc = al(L.sbcount + 16 * (size_t)q.grid);
     L.dlist = al(L.proc + 8 * (size_t)q.grid);
     L.soa = al(L.dlist + 4 * q.deferrable);
     L.total = L.soa + q.entries * queue_entry_bytes(h);
@@ -2258,6 +2309,7 @@ static void bind_queue(const sfq_ctx* h, StepArgs& A, void* mem, const QueueShap
     A.d_list = (uint32_t*)(base + L.dlist);
     A.q_cap_per_wave = qs.cap_per_wave;
     A.grid = qs.grid;
+    A.max_chunks = qs.max_chunks;
     A.obs = nullptr;
     A.may_defer = qs.may_defer;
 }
@@ -2417,6 +2469,7 @@ static QueueShape queue_capacity(const sfq_ctx* h)
     QueueShape cap;
     cap.may_defer = 0;
     cap.grid = (int)h->q_cap_grid;
+    cap.max_chunks = 0;
     cap.slices = h->q_cap_slices;
     cap.entries = h->q_cap_entries;
     cap.deferrable = h->q_cap_deferrable;

@@ -386,7 +386,8 @@ def test_step_tiling_invariance_and_ragged_tiles(h64, dev):
         p = np.concatenate([np.stack([t.px.cpu().numpy(), t.py.cpu().numpy(), t.pz.cpu().numpy()])
                             for t in tiles], axis=1)
         tau = np.concatenate([t.tau.cpu().numpy() for t in tiles])
-        return p, tau, products_by_parent(prods, "photons"), cnt.as_dict()
+        # the counters of the results (`deferred` depends on how the work was scheduled)
+        return p, tau, products_by_parent(prods, "photons"), cnt.results()
 
     p1, t1, m1, c1 = run([0, n])
     p2, t2, m2, c2 = run([0, 1, 256, 513, 4610, 4610, n])  # includes an empty tile
@@ -441,7 +442,7 @@ def test_step_same_on_unaligned_views(dev, form, shifted):
         flags = [t.alive.cpu().numpy() for t in tiles]
         ptrs = [t.tau.data_ptr() % 16 for t in tiles]
         maps = {k: products_by_parent(prods, k) for k in ("photons", "electrons", "positrons")}
-        return out, flags, maps, cnt.as_dict(), ptrs
+        return out, flags, maps, cnt.results(), ptrs
 
     o1, f1, m1, c1, a1 = run(None)
     o2, f2, m2, c2, a2 = run(shifted)
