@@ -201,6 +201,19 @@ def test_reserve_and_kernel_timing(dev):
     plan.launch()
     torch.cuda.synchronize()
     assert same(state(a), state(b)) and same(product_set(pa), product_set(pb))
+    # steps timed whole (two events per step): the step's time, and 0 for the emitter pass;
+    # a split-timed step beside them keeps its split
+    h.profile(True, whole_step=True)
+    h.step(a, seed=5, step=7, products=pa, counters=ca)
+    plan.launch()
+    h.profile(True)
+    h.step(a, seed=5, step=8, products=pa, counters=ca)
+    whole, zero = h.profile_read_steps(3)
+    assert len(whole) == 3 and np.all(whole > 0)
+    assert zero[0] == 0 and zero[1] == 0 and zero[2] > 0
+    h.profile(False)
+    with pytest.raises(sfq.SFQError):
+        h._check(h._L.sfq_profile_enable(h._h, 3))    # only 0, 1 and 2
     plan.close()
     with pytest.raises(sfq.SFQError):
         h.reserve(10, 0)
@@ -208,8 +221,9 @@ def test_reserve_and_kernel_timing(dev):
 
 @pytest.mark.parametrize("precision", [sfq.FP64, sfq.MIXED])
 def test_extreme_launch_shapes_give_identical_results(dev, precision):
-    """16384 blocks of 256-particle chunks (every scan thread sums 64 blocks) and 1 block per CU
-    with 2^22-particle chunks against the default shape: same state, same products."""
+    """16384 blocks of 256-particle chunks (each emitter block sums up to 16384 block totals) and
+    1 block per CU with 2^22-particle chunks against the default shape: same state, same
+    products."""
     h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=precision)
     base = make_tiles(dev, h, sizes=(1 << 21, 3, (1 << 21) + 77, 4096))
     results = []
