@@ -335,8 +335,9 @@ sfq_status sfq_plan_replay(sfq_plan p, void* stream);
  * not take every particle of its next share of a chunk (chunk / 4 particles) leaves that share
  * untouched, and a further kernel of the same step steps it afterwards with the same arithmetic.
  * So the queue size never changes results, only speed (sfq_counters.deferred counts the
- * particles of such shares).  A slice holds one share plus `2 * expected_fraction` of the
- * particles of the wave's shares (at most all of them, which makes deferral impossible).
+ * particles of such shares).  Streaming blocks take chunks as they become free, up to their
+ * even share plus a sixteenth; a slice holds one share plus `2 * expected_fraction` of the
+ * particles of that many shares (at most all of them, which makes deferral impossible).
  *
  * Pre-sizes the queue for sfq_step calls of up to `max_particles` particles in up to
  * `max_tiles` tiles with the current launch shape and queue fraction, so that such calls
@@ -370,10 +371,10 @@ sfq_status sfq_profile_enable(sfq_handle h, int enable);
 sfq_status sfq_profile_read(sfq_handle h, double* stream_ms, double* emit_ms, uint64_t* steps);
 
 /* The same timings step by step (for latency percentiles): for each step timed since the
- * previous read, in order, the streaming kernel's and the emitter pass's (scan and emitter
- * kernels) durations in ms go to stream_ms[k] and emit_ms[k] (a step timed whole: its duration
- * and 0) (host arrays of max_steps floats,
- * owned by the caller); *steps receives the count, and the timings are cleared.  The events are
+ * previous read, in order, the streaming kernel's and the emitter pass's (emitter and
+ * deferred-share kernels) durations in ms go to stream_ms[k] and emit_ms[k] (a step timed
+ * whole: its duration and 0; host arrays of max_steps floats, owned by the caller); *steps
+ * receives the count, and the timings are cleared.  The events are
  * timing-only (no system-scope fence on record).  SFQ_E_CAPACITY, and nothing cleared, when
  * more than max_steps steps are pending; SFQ_E_ARG for NULL arrays when steps are pending. */
 sfq_status sfq_profile_read_steps(sfq_handle h, uint64_t max_steps, float* stream_ms,

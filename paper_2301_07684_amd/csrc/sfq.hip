@@ -1275,9 +1275,9 @@ __global__ __launch_bounds__(STEP_BLOCK, bulk_waves(MIXED, BLCFA, PUSH, WAVE)) v
 // one pair (beyond-LCFA rejections are only known here, so that mode takes photon slots by
 // atomics, and steps with per-tile product sets by atomics per set).  A block's slots start at
 // the product counts before the step plus the emitters queued by every earlier streaming
-// block: each block sums those counts itself (one coalesced read of the per-block totals),
-// and the last block out advances the product counts and adds the step's processed / emitted /
-// converted counters, each once, so no scan kernel runs between the two passes.
+// block: each block sums those counts itself (one coalesced read of the per-block totals);
+// block 0 adds the step's processed / emitted / converted counters once and the last block out
+// advances the product counts, so no scan kernel runs between the two passes.
 struct EmitShared {
     unsigned cum[2 * STEP_WAVES + 1];
     unsigned long long base[3 * STEP_WAVES];
