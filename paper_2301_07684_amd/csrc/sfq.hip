@@ -16,8 +16,9 @@
 //   emit_kernel  each queue slice is sampled by a few blocks with all lanes busy: Philox draws,
 //                the inverse-CDF tables (L2-resident), recoil and products.  Each block's
 //                product slots come from the queued counts of every earlier slice, which it
-//                sums itself; the last block out writes the step's totals once (per-wave
-//                reservations only for beyond-LCFA photons and per-set products).
+//                sums itself; block 0 adds the step's counters once and the last block out
+//                advances the product counts (per-wave reservations only for beyond-LCFA
+//                photons and per-set products).
 //   defer_kernel the shares the streaming pass deferred (queue too small), stepped whole.
 //   rates/chi/sample/philox kernels: grid-stride elementwise kernels behind the batched calls.
 #include <hip/hip_runtime.h>
