@@ -1358,18 +1358,19 @@ __device__ __forceinline__ void emit_item(const StepArgs& A, int qb, int part, E
         int t = 0;
         double chi = 1.0, gamma = 1.0, px = 0, py = 0, pz = 0, aux = -1.0, aux2 = 0.0;
         uint64_t quid = 0;
+        // the entry is read once: non-temporal loads keep the inverse-CDF tables in the L2
         if (valid) {
-            i = A.q_idx[slot];
-            t = (int)A.q_tile[slot];
-            chi = A.q_chi[slot];
-            gamma = A.q_gamma[slot];
-            px = A.q_px[slot];
-            py = A.q_py[slot];
-            pz = A.q_pz[slot];
-            if (LOCAL) quid = A.q_uid[slot];
+            i = ld_stream(&A.q_idx[slot]);
+            t = (int)ld_stream(&A.q_tile[slot]);
+            chi = ld_stream(&A.q_chi[slot]);
+            gamma = ld_stream(&A.q_gamma[slot]);
+            px = ld_stream(&A.q_px[slot]);
+            py = ld_stream(&A.q_py[slot]);
+            pz = ld_stream(&A.q_pz[slot]);
+            if (LOCAL) quid = ld_stream(&A.q_uid[slot]);
             if (BLCFA && !pair) {
-                aux = A.q_aux[slot];
-                aux2 = A.q_aux2[slot];
+                aux = ld_stream(&A.q_aux[slot]);
+                aux2 = ld_stream(&A.q_aux2[slot]);
             }
         }
         emit_one<MIXED, BLCFA, LOCAL>(A, valid, pair, i, t, chi, gamma, px, py, pz, quid, aux,
