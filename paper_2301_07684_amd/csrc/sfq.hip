@@ -1358,9 +1358,9 @@ __device__ __forceinline__ void emit_item(const StepArgs& A, int qb, int part, E
     }
     __syncthreads();
     const unsigned total = sh.cum[2 * STEP_WAVES];
-    // where the streaming block found emitters dense, the products bypass the L2 (non-temporal
-    // stores), which then keeps more of the inverse-CDF tables; where they are sparse, ordinary
-    // stores are faster (measured at 2 % and 13 % emitters)
+    // where the streaming block found emitters dense, the products are written with
+    // non-temporal stores, which are faster there; where they are sparse, ordinary stores are
+    // faster (measured at 2 % and 13 % emitters)
     const bool nt_prod =
         (float)total > NT_PRODUCT_FRACTION * (float)sh.chunks * (float)A.chunk;
     const unsigned per = (total + A.emit_split - 1) / A.emit_split;
@@ -1382,7 +1382,8 @@ __device__ __forceinline__ void emit_item(const StepArgs& A, int qb, int part, E
         int t = 0;
         double chi = 1.0, gamma = 1.0, px = 0, py = 0, pz = 0, aux = -1.0, aux2 = 0.0;
         uint64_t quid = 0;
-        // the entry is read once: non-temporal loads keep the inverse-CDF tables in the L2
+        // the entry is read once: non-temporal loads (measured faster, most where emitters are
+        // dense)
         if (valid) {
             i = ld_stream(&A.q_idx[slot]);
             t = (int)ld_stream(&A.q_tile[slot]);
