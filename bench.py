@@ -115,7 +115,8 @@ def device_tiles(dev, sfq, h, workloads, wave=False):
 
 
 class StateReset:
-    """The tiles' evolving state (momenta, optical depths, alive flags) as it was when made, put
+    """The tiles' evolving state (momenta, optical depths, alive flags, beyond-LCFA state) as it
+    was when made (or when the reset was created), put
     back by a device copy before every timed step, outside the step's timed events, so that each
     repeat steps the same ensemble (no converted photons pile up as dead slots).  A copy through
     an unrelated buffer after it leaves the caches as a step of its own would find them."""
@@ -125,7 +126,7 @@ class StateReset:
 
         self.pairs = []
         for t in tiles:
-            for f in ("px", "py", "pz", "tau", "alive"):
+            for f in ("px", "py", "pz", "tau", "alive", "fperp", "dfperp", "just_created"):
                 v = getattr(t, f)
                 if v is not None:
                     self.pairs.append((v, v.clone()))
@@ -136,6 +137,50 @@ class StateReset:
         for dst, src in self.pairs:
             dst.copy_(src)
         self.flush_dst.copy_(self.flush_src)
+
+
+def time_steps(h, tiles, prods, cnt, reset, steps, warmup, push=False):
+    """Warm-up steps, then `steps` steps each timed whole on the step's stream by the library's
+    timing events (before the streaming kernel and after the step's last kernel; no
+    system-scope fence), the state put back by `reset` before each outside the timed region,
+    then up to 10 more steps timed with the streaming/emitter split (a third event between the
+    two passes, whose idle gap the split times include).  Every step zeroes the product counts
+    itself: the buffers hold that step's products."""
+    import torch
+
+    for s in range(warmup):
+        reset()
+        h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt, push=push,
+               zero_product_counts=True)
+    torch.cuda.synchronize()
+    cnt.reset()
+    h.profile(True, whole_step=True)
+    h.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        reset()
+        h.step(tiles, seed=0, step=warmup + s + 1, products=prods, counters=cnt, push=push,
+               zero_product_counts=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    whole, _ = h.profile_read_steps(steps)
+    if len(whole) != steps:
+        raise RuntimeError("the step timing events did not cover every timed step")
+    step_ms = whole.astype(np.float64)           # per step: streaming kernel to the step's end
+    c = cnt.as_dict()
+    if c["overflow"]:
+        raise RuntimeError("product buffers overflowed during the benchmark")
+    h.profile(True)
+    nsplit = min(steps, 10)
+    for s in range(nsplit):
+        reset()
+        h.step(tiles, seed=0, step=warmup + steps + s + 1, products=prods, counters=cnt,
+               push=push, zero_product_counts=True)
+    bulk, emit = h.profile_read_steps(nsplit)
+    h.profile(False)
+    return dict(wall=wall, device_s=float(step_ms.sum()) * 1e-3, step_ms=step_ms, counters=c,
+                bulk_ms=float(bulk.mean()), emit_ms=float(emit.mean()))
 
 
 def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False, wave=False,
@@ -164,51 +209,70 @@ def run_form(precision, workload, n, steps, warmup, dev, launch=None, push=False
         tuned = {"shape": list(launch)}
     h.reserve(2 * n, 2)
     reset = StateReset(tiles, dev)
-    for s in range(warmup):
-        reset()
-        h.step(tiles, seed=0, step=s + 1, products=prods, counters=cnt, push=push,
-               zero_product_counts=True)
-    torch.cuda.synchronize()
-    cnt.reset()
-    # the library's timing events (before the streaming kernel and after the step's last
-    # kernel; no system-scope fence) time every step on the step's stream; the state reset runs
-    # between them
-    h.profile(True, whole_step=True)
-    h.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(steps):
-        reset()
-        # the step zeroes the product counts itself: the buffers hold this step's products
-        h.step(tiles, seed=0, step=warmup + s + 1, products=prods, counters=cnt, push=push,
-               zero_product_counts=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    whole, _ = h.profile_read_steps(steps)
-    if len(whole) != steps:
-        raise RuntimeError("the step timing events did not cover every timed step")
-    step_ms = whole.astype(np.float64)           # per step: streaming kernel to the step's end
-    c = cnt.as_dict()
-    if c["overflow"]:
-        raise RuntimeError("product buffers overflowed during the benchmark")
-    # the split between the streaming kernel and the emitter pass, from further steps timed
-    # apart (a third event between the two, whose idle gap the split times include)
-    h.profile(True)
-    nsplit = min(steps, 10)
-    for s in range(nsplit):
-        reset()
-        h.step(tiles, seed=0, step=warmup + steps + s + 1, products=prods, counters=cnt,
-               push=push, zero_product_counts=True)
-    bulk, emit = h.profile_read_steps(nsplit)
-    h.profile(False)
-    bulk_ms, emit_ms, nprof = float(bulk.sum()), float(emit.sum()), len(bulk)
+    r = time_steps(h, tiles, prods, cnt, reset, steps, warmup, push=push)
     qbytes = h.queue_bytes()
     h.close()
     del tiles, prods, reset
     torch.cuda.empty_cache()
-    return dict(wall=wall, device_s=float(step_ms.sum()) * 1e-3, step_ms=step_ms, counters=c,
-                n_total=2 * n, n_flags=n_flags, bulk_ms=bulk_ms / nprof, emit_ms=emit_ms / nprof,
-                shape=tuned["shape"], queue_bytes=qbytes)
+    return dict(r, n_total=2 * n, n_flags=n_flags, shape=tuned["shape"], queue_bytes=qbytes)
+
+
+def served_stream_kernel_bytes(n_leptons, n_flags, photons_live):
+    """Algorithmic bytes of the streaming kernel of the served form's step (beyond-LCFA
+    electrons pushed in the kernel, plane-wave tiles, local decisions, so no optical depths).
+    Every electron: p, the wave's amplitude and phase, F_perp, dF, the id and the just-created
+    flag read (97 B); the pushed p, F_perp, dF and the flag written (73 B).  Every photon slot:
+    its alive flag (1 B); every live photon: p, the wave's amplitude and phase and the id read
+    (48 B)."""
+    return 170 * n_leptons + n_flags + 48 * photons_live
+
+
+def run_served_step(n, steps, warmup, dev, launch=None):
+    """The served form's kernels on one large step: n electrons with beyond-LCFA state and n
+    photons as plane-wave tiles, the fused push, local decisions, MIXED (the kernels a served
+    batch runs, without the serving loop's small batches and concurrent lanes)."""
+    import torch
+
+    from paper_2301_07684_amd import autotune, inputs, sfq
+
+    h = sfq.Handle(ref_length=inputs.LAMBDA_R, dt=inputs.DT, precision=sfq.MIXED,
+                   decision=sfq.LOCAL, blcfa=True)
+    e = inputs.plane_wave_t(n, dev, species=sfq.ELECTRON)
+    g = inputs.plane_wave_t(n, dev, species=sfq.PHOTON)
+    wave = dict(field_mode=sfq.FIELDS_PLANE_WAVE, wave_k=(1.0, 0.0, 0.0),
+                wave_pol=(0.0, 1.0, 0.0))
+    p, k = e["p"].contiguous(), g["p"].contiguous()
+    fperp = torch.zeros(3 * n, dtype=torch.float64, device=dev)
+    tiles = [sfq.TileArrays(sfq.ELECTRON, p[0], p[1], p[2], uid=e["uid"], fperp=fperp,
+                            dfperp=torch.zeros_like(fperp),
+                            just_created=torch.ones(n, dtype=torch.uint8, device=dev),
+                            wave_amp=e["a"], wave_phase=e["phi"], **wave),
+             sfq.TileArrays(sfq.PHOTON, k[0], k[1], k[2], uid=g["uid"],
+                            alive=torch.ones(n, dtype=torch.uint8, device=dev),
+                            wave_amp=g["a"], wave_phase=g["phi"], **wave)]
+    del e, g
+    prods = sfq.ProductBuffers.empty(n // 2, n // 8, dev)
+    cnt = sfq.Counters(dev)
+    # a particle's first beyond-LCFA step only records its force: three steps (the wave's
+    # phase advancing) bring every electron to where it can emit
+    for s in range(3):
+        for t in tiles:
+            t.wave_phase0 = 2.0 * inputs.DT * s
+        h.step(tiles, seed=1, step=s + 1, products=prods, counters=cnt, push=True,
+               zero_product_counts=True)
+    if launch is None:
+        tuned = autotune.tune(h, tiles, prods, cnt, seed=0, step=1, repeats=3, cache_path=None,
+                              push=True)
+    else:
+        h.set_launch(*launch)
+        tuned = {"shape": list(launch)}
+    h.reserve(2 * n, 2)
+    reset = StateReset(tiles, dev)
+    r = time_steps(h, tiles, prods, cnt, reset, steps, warmup, push=True)
+    h.close()
+    del tiles, prods, reset, p, k, fperp
+    torch.cuda.empty_cache()
+    return dict(r, n_leptons=n, n_flags=n, shape=tuned["shape"])
 
 
 def run_batched(steps, warmup, dev):
@@ -443,6 +507,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-served-step", action="store_true",
+                    help="skip the served form's kernels on one large step")
     ap.add_argument("--no-push", action="store_true")
     ap.add_argument("--no-constant-field", action="store_true")
     ap.add_argument("--no-wave", action="store_true")
@@ -489,6 +555,11 @@ def main():
     served = None if args.no_served else run_served(dev)
     if served is not None:
         print(f"# served form done: {served['wall']:.2f} s", file=sys.stderr, flush=True)
+    served_step = None if args.no_served_step else run_served_step(args.n, args.steps,
+                                                                   args.warmup, dev, launch)
+    if served_step is not None:
+        print(f"# served form's kernels on one step done: "
+              f"{served_step['wall'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     # each form takes the launch shape the autotuner finds for it (or --launch): the
     # plane-wave-fields form, with more arithmetic per byte, runs best with more waves
     fused = None if args.no_push else run_form(0, "plane_wave", args.n, args.steps, args.warmup,
@@ -650,6 +721,26 @@ def main():
                          "jobs_that_waited_for_memory": served["waited"],
                          "wall_s": served["wall"], "emitted": cs["emitted"],
                          "blcfa_rejected": cs["blcfa_rejected"], "converted": cs["converted"]}
+    if served_step is not None:
+        cv = served_step["counters"]
+        pv = lambda k: cv[k] / K
+        vb = served_stream_kernel_bytes(served_step["n_leptons"], served_step["n_flags"],
+                                        pv("processed") - served_step["n_leptons"])
+        out["served_kernels_one_step"] = {
+            "value": cv["processed"] / served_step["device_s"], "unit": "particle-updates/s",
+            "dtype": "f32 (f64 chi, tails and beyond-LCFA state)",
+            "workload": "the served form's kernels on one large step: 2^24 electrons with "
+                        "beyond-LCFA state + 2^24 photons, plane-wave tiles, fused push, local "
+                        "decisions",
+            "ms_per_step": served_step["device_s"] / K * 1e3,
+            "p50_step_ms": float(np.percentile(served_step["step_ms"], 50)),
+            "p99_step_ms": float(np.percentile(served_step["step_ms"], 99)),
+            "bulk_kernel_ms": served_step["bulk_ms"], "emitter_pass_ms": served_step["emit_ms"],
+            "bulk_algorithmic_bytes": vb,
+            "bulk_roofline_frac": vb / (served_step["bulk_ms"] * 1e-3) / HBM_PEAK,
+            "launch_shape": served_step["shape"],
+            "emitted_per_step": pv("emitted"), "blcfa_rejected_per_step": pv("blcfa_rejected"),
+            "converted_per_step": pv("converted")}
     if fused is not None:
         cf = fused["counters"]
         pf = lambda k: cf[k] / K

@@ -37,6 +37,10 @@ def test_byte_counts_differ_between_forms_by_what_each_form_moves():
     # a uniform-field tile reads p and tau only, and writes them back for non-emitters
     assert bench.constant_field_kernel_bytes(n, 0) == 64 * n
     assert bench.constant_field_kernel_bytes(n, n) == 32 * n
+    # the served form's step: 170 B per beyond-LCFA electron (97 read, 73 written: pushed p,
+    # F_perp, dF, flag), every photon slot's flag and 48 B per live photon; no optical depths
+    assert bench.served_stream_kernel_bytes(leptons, n - leptons, live - leptons) == \
+        170 * leptons + (n - leptons) + 48 * (live - leptons)
     # the whole step's yardstick: 96 B per update, 80 B per emission, 104 B per conversion
     assert bench.survey_step_bytes(live, 0, 0) == 96 * live
     assert bench.survey_step_bytes(live, em, conv) - bench.survey_step_bytes(live, 0, 0) == \
