@@ -497,6 +497,35 @@ def copy_calibration(dev, nbytes=1 << 31, reps=5):
                       "GB_per_s": 2 * nbytes / dt / 1e9}), flush=True)
 
 
+PROBE_SHAPES = ((2, 2), (3, 2), (4, 2), (2, 4))  # (blocks per CU, particles per lane)
+
+
+def memory_probe(n=1 << 25, chunk=2048, repeats=12):
+    """The practical ceiling of the streaming kernel's access pattern on this machine: the
+    memory-only probe of csrc/mem_probe.hip (ten FP64 arrays of n read, one written back, 88 B
+    per element, no arithmetic) at a few launch shapes; TB/s of read plus written bytes per
+    shape, from the median of `repeats` launches, each after a cache-evicting copy."""
+    import ctypes
+
+    from paper_2301_07684_amd import build
+
+    if not os.path.exists(build.PROBE_LIB):
+        raise RuntimeError(f"{build.PROBE_LIB} is missing: run the build step first")
+    lib = ctypes.CDLL(build.PROBE_LIB)
+    fn = lib.sfq_probe_stream
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                   ctypes.POINTER(ctypes.c_float)]
+    out = {}
+    for bpc, ppl in PROBE_SHAPES:
+        ms = ctypes.c_float(0.0)
+        rc = fn(bpc, ppl, n, chunk, repeats, ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"memory probe failed with code {rc}")
+        out[f"{bpc}x{chunk}, {ppl} per lane"] = 88.0 * n / (ms.value * 1e-3) / 1e12
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -518,6 +547,8 @@ def main():
     ap.add_argument("--constant-field-n", type=int, default=1 << 30,
                     help="electrons of the constant-field run")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-memory-probe", action="store_true",
+                    help="skip the memory-only probe of the streaming kernel's access pattern")
     ap.add_argument("--launch", default=None,
                     help="fixed launch shape BLOCKS_PER_CUxCHUNK for the FP64 and MIXED forms "
                          "instead of the autotuner (e.g. for profiling runs)")
@@ -582,6 +613,10 @@ def main():
                   file=sys.stderr, flush=True)
     const = None if args.no_constant_field else run_constant_field(dev, args.constant_field_n,
                                                                    launch=launch)
+    probe = None if args.no_memory_probe else memory_probe()
+    if probe is not None:
+        print(f"# memory probe done: best {max(probe.values()):.2f} TB/s", file=sys.stderr,
+              flush=True)
     if const is not None:
         print(f"# constant-field run done: {const['wall'] / const['K'] * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
@@ -810,6 +845,14 @@ def main():
             "bulk_algorithmic_bytes": kb,
             "bulk_roofline_frac": kb / (const["bulk_ms"] * 1e-3) / HBM_PEAK,
             "photons": cc["emitted"], "N_T_R": n_a, "photons_over_N_T_R": cc["emitted"] / n_a}
+    if probe is not None:
+        best = max(probe.values())
+        out["memory_probe"] = {
+            "what": "the streaming kernel's bytes (ten FP64 arrays read, one written back) with no "
+                    "arithmetic: the practical ceiling of its access pattern on this machine",
+            "unit": "TB/s", "by_shape": probe, "best": best,
+            "streaming_kernel_fraction_of_best": (out["roofline"]["traffic"] or bulk_bytes)
+                                                 / bulk_s / 1e12 / best}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

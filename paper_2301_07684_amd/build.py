@@ -2,8 +2,10 @@
 
     python -m paper_2301_07684_amd.build
 
-compiles csrc/sfq.hip into libsfq.so next to this file (hipcc, --offload-arch=gfx950) and
-(re)generates data/sfq_tables.bin when the table generator's source changed.
+compiles csrc/sfq.hip into libsfq.so next to this file (hipcc, --offload-arch=gfx950),
+csrc/mem_probe.hip into libsfq_probe.so (the benchmark's memory-only reference, not part of
+the step's ABI) and (re)generates data/sfq_tables.bin when the table generator's source
+changed.
 """
 from __future__ import annotations
 
@@ -16,6 +18,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "libsfq.so")
 SOURCES = [os.path.join(HERE, "csrc", "sfq.hip")]
+PROBE_LIB = os.path.join(HERE, "libsfq_probe.so")
+PROBE_SOURCES = [os.path.join(HERE, "csrc", "mem_probe.hip")]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -80,6 +84,10 @@ def build_library(verbose: bool = True) -> str:
     return _hipcc_shared(LIB, SOURCES, verbose)
 
 
+def build_probe(verbose: bool = True) -> str:
+    return _hipcc_shared(PROBE_LIB, PROBE_SOURCES, verbose)
+
+
 def build_tables(verbose: bool = True) -> str:
     from . import tablegen
 
@@ -90,6 +98,7 @@ def build_tables(verbose: bool = True) -> str:
 def build(verbose: bool = True):
     build_tables(verbose)
     build_library(verbose)
+    build_probe(verbose)
 
 
 if __name__ == "__main__":

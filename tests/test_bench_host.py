@@ -59,3 +59,23 @@ def test_traffic_is_reported_only_for_the_measured_sources(monkeypatch):
         assert t is None
     monkeypatch.setattr(build, "kernel_source_hash", lambda: "0" * 16)
     assert bench.measured_traffic() is None
+
+
+def test_memory_probe_library_rejects_bad_arguments_before_any_device_call():
+    # the benchmark's memory-only reference (csrc/mem_probe.hip, built beside libsfq.so):
+    # argument checks come first, so these calls touch no GPU
+    import ctypes
+
+    if not os.path.exists(build.PROBE_LIB):
+        build.build_probe(verbose=False)
+    fn = ctypes.CDLL(build.PROBE_LIB).sfq_probe_stream
+    fn.restype = ctypes.c_int
+    fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                   ctypes.POINTER(ctypes.c_float)]
+    ms = ctypes.c_float(0.0)
+    good = (2, 2, 1 << 20, 2048, 5)
+    for bad in ((0, 2, 1 << 20, 2048, 5), (17, 2, 1 << 20, 2048, 5), (2, 3, 1 << 20, 2048, 5),
+                (2, 4, 1 << 20, 1536, 5), (2, 2, 1000, 2048, 5), (2, 2, 1 << 20, 2048, 2),
+                (2, 2, 0, 2048, 5)):
+        assert bad != good and fn(*bad, ctypes.byref(ms)) == -1
+    assert fn(*good, None) == -1
