@@ -613,7 +613,12 @@ def main():
                   file=sys.stderr, flush=True)
     const = None if args.no_constant_field else run_constant_field(dev, args.constant_field_n,
                                                                    launch=launch)
-    probe = None if args.no_memory_probe else memory_probe()
+    probe = None
+    if not args.no_memory_probe:
+        try:
+            probe = memory_probe()
+        except (OSError, RuntimeError) as e:  # a reference figure: its failure spoils no other
+            print(f"# memory probe failed: {e}", file=sys.stderr, flush=True)
     if probe is not None:
         print(f"# memory probe done: best {max(probe.values()):.2f} TB/s", file=sys.stderr,
               flush=True)
