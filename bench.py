@@ -569,6 +569,17 @@ def main():
     f64 = run_form(0, "plane_wave", args.n, args.steps, args.warmup, dev, launch)
     print(f"# fp64 form done: {f64['wall'] / args.steps * 1e3:.3f} ms/step", file=sys.stderr,
           flush=True)
+    # the memory-only reference right after the headline form, on the same machine state
+    probe = None
+    if not args.no_memory_probe:
+        torch.cuda.empty_cache()
+        try:
+            probe = memory_probe()
+        except (OSError, RuntimeError) as e:  # a reference figure: its failure spoils no other
+            print(f"# memory probe failed: {e}", file=sys.stderr, flush=True)
+    if probe is not None:
+        print(f"# memory probe done: best {max(probe.values()):.2f} TB/s", file=sys.stderr,
+              flush=True)
     mixed = None if args.no_mixed else run_form(1, "plane_wave_skewed", args.n, args.steps,
                                                 args.warmup, dev, launch)
     if mixed is not None:
@@ -613,15 +624,6 @@ def main():
                   file=sys.stderr, flush=True)
     const = None if args.no_constant_field else run_constant_field(dev, args.constant_field_n,
                                                                    launch=launch)
-    probe = None
-    if not args.no_memory_probe:
-        try:
-            probe = memory_probe()
-        except (OSError, RuntimeError) as e:  # a reference figure: its failure spoils no other
-            print(f"# memory probe failed: {e}", file=sys.stderr, flush=True)
-    if probe is not None:
-        print(f"# memory probe done: best {max(probe.values()):.2f} TB/s", file=sys.stderr,
-              flush=True)
     if const is not None:
         print(f"# constant-field run done: {const['wall'] / const['K'] * 1e3:.3f} ms/step",
               file=sys.stderr, flush=True)
