@@ -100,7 +100,9 @@ def clone(tiles):
 def run_pair(dev, make, *, steps=1, fracs=(0.0, 0.02), precision=sfq.FP64, decision=None,
              blcfa=False, push=False, sets=0, caps=(1 << 18, 1 << 17)):
     """The same steps on a handle whose queue never overflows and on handles with small queues;
-    returns the deferred counts of the small ones (each must be > 0)."""
+    returns the deferred counts of the small ones.  The minimal queue (frac 0: one share per
+    slice) must defer; a small one defers when a block happens to take enough emitter-rich
+    chunks, which depends on which blocks take which chunks, so it is not required to."""
     kw = dict(precision=precision, blcfa=blcfa)
     if decision is not None:
         kw["decision"] = decision
@@ -132,7 +134,8 @@ def run_pair(dev, make, *, steps=1, fracs=(0.0, 0.02), precision=sfq.FP64, decis
             assert same(st, st0), (frac, k, "state")
             assert all(same(a, b) for a, b in zip(pr, pr0)), (frac, k, "products")
         c0 = dict(ref[2])
-        assert c["deferred"] > 0, frac
+        if frac == 0.0:
+            assert c["deferred"] > 0, frac
         assert {k: v for k, v in c.items() if k != "deferred"} == \
                {k: v for k, v in c0.items() if k != "deferred"}, (frac, c, c0)
         deferred.append(c["deferred"])
