@@ -95,6 +95,8 @@ struct StepArgs {
                                 // blocks done, emitter blocks done, next chunk to stream
     unsigned* obs;              // nullable, host-mapped: [0] the largest emitter fraction of a
                                 // wave's share (float bits), [1] shares deferred (for sizing)
+    unsigned* emit_obs;         // nullable, host-mapped: the step's emitters over the particles
+                                // it processed (float bits; picks the emitter pass's grid)
     int grid;                   // blocks of the streaming kernel (STEP_WAVES slices each)
     int max_chunks;             // the most chunks one streaming block takes (the queue's worst
                                 // case is sized for it)
@@ -329,9 +331,11 @@ constexpr int bulk_waves(bool mixed, bool blcfa, bool push, bool wave)
 #ifndef SFQ_EMIT_WAVES
 #define SFQ_EMIT_WAVES 3
 #endif
-// The emitter fraction of a streaming block's particles above which the emitter kernel writes
-// that block's products with non-temporal stores.
-constexpr float NT_PRODUCT_FRACTION = 0.06f;
+// Emitters dense: above this fraction of a streaming block's particles the emitter kernel
+// writes the block's products with non-temporal stores, and above it for the whole step the
+// next step's emitter pass runs twice the blocks per compute unit (both measured faster at
+// 10-13 % emitters and slower at 2 %).
+constexpr float DENSE_EMITTER_FRACTION = 0.06f;
 
 // read as the alive flag of tiles that have no alive array
 __device__ const uint8_t k_alive_one[1] = {1};
@@ -1362,7 +1366,7 @@ __device__ __forceinline__ void emit_item(const StepArgs& A, int qb, int part, E
     // non-temporal stores, which are faster there; where they are sparse, ordinary stores are
     // faster (measured at 2 % and 13 % emitters)
     const bool nt_prod =
-        (float)total > NT_PRODUCT_FRACTION * (float)sh.chunks * (float)A.chunk;
+        (float)total > DENSE_EMITTER_FRACTION * (float)sh.chunks * (float)A.chunk;
     const unsigned per = (total + A.emit_split - 1) / A.emit_split;
     const unsigned e_lo = min(total, per * (unsigned)part), e_hi = min(total, e_lo + per);
     for (unsigned b0e = e_lo; b0e < e_hi; b0e += STEP_BLOCK) {
@@ -1454,6 +1458,8 @@ __global__ __launch_bounds__(STEP_BLOCK, SFQ_EMIT_WAVES) void emit_kernel(StepAr
                 A.obs[0] = s_fmax;
                 A.obs[1] = A.d_ctl[0];
             }
+            if (A.emit_obs && proc > 0)
+                *A.emit_obs = __float_as_uint((float)(tl + tp) / (float)proc);
         }
     }
     EmitCounts C;
@@ -1725,6 +1731,8 @@ struct sfq_ctx {
     int q_adaptive = 1;
     unsigned* obs_host = nullptr;  // pinned, mapped: the emitter kernel's observations
     unsigned* obs_dev = nullptr;
+    double emit_frac = 0.0;        // the emitter fraction of the last step observed (steps and
+                                   // plan launches): picks the emitter pass's blocks per CU
     // The end of the handle's last step (its own step_done event, or the step's timing event
     // when timing is on): a step on another stream waits for it, since steps share the queue.
     // One event record per step: a staging slot's event is recorded only when the descriptors
@@ -2292,13 +2300,16 @@ static QueueLayout queue_layout(const sfq_ctx* h, const QueueShape& q)
 static size_t queue_bytes(const sfq_ctx* h, const QueueShape& q) { return queue_layout(h, q).total; }
 
 // Emitter blocks per streaming block's slices: enough emitter blocks to keep every compute unit
-// busy with the latency-bound emitter pass even when the streaming pass runs few, large blocks.
+// busy with the latency-bound emitter pass even when the streaming pass runs few, large blocks;
+// twice as many after a step whose emitters were dense, as each block then has several rounds
+// of emitters to chain.
 #ifndef SFQ_EMIT_BPC
 #define SFQ_EMIT_BPC 6
 #endif
 static int emit_split_for(const sfq_ctx* h, int grid)
 {
-    return std::max(1, std::min(16, (h->num_cus * SFQ_EMIT_BPC) / std::max(1, grid)));
+    const int bpc = h->emit_frac > DENSE_EMITTER_FRACTION ? 2 * SFQ_EMIT_BPC : SFQ_EMIT_BPC;
+    return std::max(1, std::min(16, (h->num_cus * bpc) / std::max(1, grid)));
 }
 
 // The arrays of a queue allocated with the capacities `cap` at `mem`, bound for a step of shape
@@ -2339,6 +2350,7 @@ static void bind_queue(const sfq_ctx* h, StepArgs& A, void* mem, const QueueShap
     A.grid = qs.grid;
     A.max_chunks = qs.max_chunks;
     A.obs = nullptr;
+    A.emit_obs = h->obs_host ? h->obs_dev + 2 : nullptr;
     A.may_defer = qs.may_defer;
 }
 
@@ -2539,8 +2551,21 @@ static sfq_status ensure_queue(sfq_ctx* h, const QueueShape& qs, const char* who
 // What the last completed steps observed (the largest emitter fraction of a wave's share,
 // shares deferred): the queue grows to twice the observed fraction, faster after deferrals
 // (caller holds h->mu).  The observation may be a step or two old; sizing never changes results.
+static void observe_emitters(sfq_ctx* h)
+{
+    if (!h->obs_host) return;
+    volatile unsigned* o = h->obs_host;
+    const unsigned fb = o[2];
+    if (!fb) return;
+    float f;
+    memcpy(&f, &fb, sizeof f);
+    h->emit_frac = f;
+    o[2] = 0;
+}
+
 static void adapt_queue(sfq_ctx* h)
 {
+    observe_emitters(h);
     if (!h->q_adaptive || !h->obs_host) return;
     volatile unsigned* o = h->obs_host;
     const unsigned fb = o[0], nd = o[1];
@@ -2850,6 +2875,7 @@ sfq_status sfq_step_noalloc(sfq_handle h, const sfq_step_desc* desc, void* strea
     A.chunk_off = (const uint32_t*)(sc + off_pos);
     if (desc->nsets > 0) A.sets = (const sfq_product_set*)(sc + set_pos);
     bind_queue(h, A, sc + STAGING_BYTES, qs, qs);
+    observe_emitters(h);
     A.emit_split = emit_split_for(h, qs.grid);
     if (desc->zero_product_counts) enqueue_zero_counts(A, (hipStream_t)stream);
     launch_step_kernels(h, A, qs.grid, (hipStream_t)stream, nullptr);
@@ -2909,6 +2935,7 @@ sfq_status sfq_plan_create(sfq_handle h, const sfq_step_desc* desc, int zero_pro
     p->A.step_ptr = p->d_step;
     if (desc->nsets > 0) p->A.sets = (const sfq_product_set*)((char*)p->d_mem + set_pos);
     bind_queue(h, p->A, (char*)p->d_mem + q_pos, qs, qs);
+    observe_emitters(h);
     p->A.emit_split = emit_split_for(h, qs.grid);
     *out = p;
     return SFQ_OK;
